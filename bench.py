@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of the relaxing-TVD patch advance on one MI355X.
+
+Workload: a periodic 256^3 grid, i.e. 32768 octree patches of 8^3 cells,
+lognormal density (sigma_ln = 1), Gaussian velocities (sigma = 0.3 c_s),
+uniform pressure P = 1, gamma = 5/3, CFL 0.5, seeded.  A step is one pass of
+the whole hot path on the device: the Eq. (CFL) signal speed and the time
+step on even steps (fused into the previous odd step's advance), the
+sibling ghost-zone fill, and one triple of 1-D sweeps (xyz on even steps,
+zyx on odd steps).
+
+Reported (one JSON line on stdout):
+* value: cell-updates/s of the FP32 batched kernel on 2^3 patch groups
+  (4096 blocks of 16^3 interior cells), inputs resident in HBM;
+* fp64_plain: the same steps with the plain FP64 per-patch kernel
+  (32768 blocks of 8^3) on the same FP32-rounded initial state;
+* l1_vs_fp64: relative L1 error per variable of the FP32 result against
+  the FP64 result after the same steps;
+* roofline: the advance kernel's algorithmic HBM bytes per launch over its
+  average duration (HIP events on the launch stream) against 8 TB/s;
+* cpu_baseline: the FP64 oracle on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_GRID = 256
+SEED = 2024
+GAMMA = 5.0 / 3.0
+CFL = 0.5
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 error; HBM GB/s % of peak"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_ic():
+    from paper_0907_3390_amd import workloads as wl
+    g = wl.lognormal(N_GRID, seed=SEED, sigma_ln=1.0, vel_sigma_rel=0.3, P0=1.0, gamma=GAMMA)
+    return g.astype(np.float32)  # FP32-rounded; the FP64 runs start from the same values
+
+
+def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, time_advance=True):
+    import torch
+    from paper_0907_3390_amd import layout
+    from paper_0907_3390_amd.driver import DeviceBlocks
+    bs = layout.periodic_grid_blockset(N_GRID, n)
+    dev = DeviceBlocks(ctx, bs, dtype=dtype, gamma=GAMMA, cfl=CFL, kernel=kernel)
+    dev.upload(layout.grid_to_blocks(grid32.astype(np.float64), n))
+    for _ in range(warmup):
+        dev.step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    adv_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for k in range(steps):
+        s = dev.step_index
+        if s % 2 == 0:
+            if s == 0:
+                dev.signal_speed()
+            dev.set_dt_from_speed()
+        dev.fill_ghosts()
+        adv_ev[k][0].record(stream)
+        dev.advance(s % 2, fuse_speed=(s % 2 == 1))
+        adv_ev[k][1].record(stream)
+        dev.step_index += 1
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(stop)
+    adv_ms = [a.elapsed_time(b) for a, b in adv_ev]
+    st, floored, bad = ctx.tvd_read_flags()
+    return dev, {"total_ms": total_ms, "wall_s": wall, "adv_ms": adv_ms, "floored": floored,
+                 "nonphysical": bad, "blocks": bs.n_blocks, "edge": n}
+
+
+def cpu_baseline(grid32, budget_s=15.0):
+    """The FP64 oracle (as it stands) on the host cores over a bounded sample
+    of the same workload: the first patches of the 256^3 grid (8^3 patches),
+    one forward step from the initial state, advance only."""
+    import oracle
+    g = grid32.astype(np.float64)
+    t = time.perf_counter()
+    blocks = oracle.periodic_ghosted_blocks(g, 8)
+    prep = time.perf_counter() - t
+    # probe the rate on a few blocks, then size the sample to the budget
+    c = oracle.Counts()
+    probe = blocks[:256]
+    t = time.perf_counter()
+    oracle.advance_blocks(probe, 0, 1e-4, 1.0 / N_GRID, GAMMA, counts=c)
+    rate = 256 * 512 / (time.perf_counter() - t)
+    nb = int(min(len(blocks), max(256, budget_s * rate / 512)))
+    c = oracle.Counts()
+    t = time.perf_counter()
+    oracle.advance_blocks(blocks[:nb], 0, 1e-4, 1.0 / N_GRID, GAMMA, counts=c)
+    el = time.perf_counter() - t
+    return {"value": nb * 512 / el, "unit": "cell-updates/s", "cores": c.threads,
+            "kind": "oracle",
+            "sample": f"{nb} of the 32768 8^3 patches of the 256^3 workload, one xyz step, "
+                      f"FP64, {el:.1f} s (ghost fill {prep:.1f} s not timed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps % 2 or args.warmup % 2:
+        sys.exit("--steps and --warmup must be even (steps come in xyz/zyx pairs)")
+
+    import torch
+    from paper_0907_3390_amd import tvd
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"bench: building the 256^3 initial state (seed {SEED})")
+    grid32 = make_ic()
+    ctx = tvd.Context(0)
+    cells = N_GRID ** 3
+
+    log(f"bench: FP32 batched, edge {args.edge}, {args.warmup}+{args.steps} steps")
+    dev32, r32 = run_gpu(ctx, grid32, args.edge, torch.float32, tvd.TVD_KERNEL_AUTO,
+                         args.steps, args.warmup)
+    ms_step = r32["total_ms"] / args.steps
+    value = cells * args.steps / (r32["total_ms"] * 1e-3)
+    n = args.edge
+    nb = r32["blocks"]
+    bytes_launch = nb * ((n + 6) ** 3 + n ** 3) * 5 * 4
+    adv_avg_ms = float(np.mean(r32["adv_ms"]))
+    achieved = bytes_launch / (adv_avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256^3 periodic grid = 32768 patches of 8^3 (run as 4096 "
+                               "2^3 patch groups of 16^3), lognormal rho sigma_ln=1, Gaussian "
+                               "v sigma=0.3 c_s, P=1, gamma=5/3, CFL 0.5, seed 2024"
+                               if n == 16 else
+                               "256^3 periodic grid = 32768 patches of 8^3, lognormal rho "
+                               "sigma_ln=1, Gaussian v sigma=0.3 c_s, P=1, gamma=5/3, CFL 0.5, "
+                               "seed 2024",
+                   "cells": cells, "blocks": nb, "block_edge": n, "precision": "fp32"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_batched<float,{n}>", "avg_launch_ms": adv_avg_ms,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "advance_cell_updates_per_s": cells / (adv_avg_ms * 1e-3),
+        "health": {"floored": r32["floored"], "nonphysical": r32["nonphysical"]},
+    }
+    log(f"bench: FP32 {value / 1e9:.2f} G cell-updates/s, advance {adv_avg_ms:.3f} ms "
+        f"({achieved:.0f} GB/s)")
+
+    if not args.no_fp64:
+        log(f"bench: FP64 plain, edge 8, {args.warmup}+{args.steps} steps")
+        s32 = np.stack(dev32.download()).astype(np.float64)
+        del dev32
+        torch.cuda.empty_cache()
+        dev64, r64 = run_gpu(ctx, grid32, 8, torch.float64, tvd.TVD_KERNEL_PLAIN, args.steps,
+                             args.warmup)
+        v64 = cells * args.steps / (r64["total_ms"] * 1e-3)
+        a64 = float(np.mean(r64["adv_ms"]))
+        from paper_0907_3390_amd import layout
+        s64 = np.stack(dev64.download())
+        g32 = layout.blocks_to_grid(s32, (5, N_GRID, N_GRID, N_GRID))
+        g64 = layout.blocks_to_grid(s64, (5, N_GRID, N_GRID, N_GRID))
+        del dev64
+        nrm = {}
+        for k, nm in enumerate(["rho", "m_x", "m_y", "m_z", "e"]):
+            d = np.abs(g32[k] - g64[k]).sum()
+            nrm[nm] = d / np.abs(g64[k]).sum()
+        rho = g64[0]
+        kin = 0.5 * (g64[1] ** 2 + g64[2] ** 2 + g64[3] ** 2) / rho
+        cs = np.sqrt(GAMMA * np.maximum((GAMMA - 1) * (g64[4] - kin), 0) / rho)
+        scale = (rho * cs).sum()
+        for k, nm in enumerate(["m_x", "m_y", "m_z"]):
+            nrm[nm + "_scale"] = np.abs(g32[k + 1] - g64[k + 1]).sum() / scale
+        out["fp64_plain"] = {"value": v64, "unit": "cell-updates/s", "ms_per_step": r64["total_ms"] / args.steps,
+                             "avg_launch_ms": a64, "blocks": r64["blocks"], "block_edge": 8}
+        out["speedup_fp32_batched_vs_fp64_plain"] = value / v64
+        out["l1_vs_fp64"] = {k: float(v) for k, v in nrm.items()}
+        out["l1_vs_fp64"]["after_steps"] = args.warmup + args.steps
+        log(f"bench: FP64 plain {v64 / 1e9:.3f} G cell-updates/s; relL1 {nrm}")
+    if not args.no_cpu_baseline:
+        log("bench: FP64 oracle on the host cores (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(grid32)
+        log(f"bench: oracle {out['cpu_baseline']['value'] / 1e6:.2f} M cell-updates/s")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

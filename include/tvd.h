@@ -1,0 +1,201 @@
+/*
+ * tvd.h -- C ABI of libtvd, the MI355X (gfx950) library that advances a
+ * batch of ghosted cubic blocks of cells by one step of GAMER's dimensionally
+ * split relaxing TVD scheme for the Euler equations (Schive, Tsai & Chiueh,
+ * "GAMER: a GPU-Accelerated Adaptive Mesh Refinement Code for Astrophysics",
+ * Sec. 2.2, Sec. 3.1 and Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status: 0 = TVD_OK, < 0 an error, > 0 a
+ *   warning.  No exception crosses this boundary and nothing calls exit().
+ *   Arguments are validated on the host before any launch; an invalid call
+ *   launches nothing.  tvd_last_error() gives the text of the last failure.
+ * - Pointers named d_* are device pointers on the context's device; they are
+ *   owned by the caller, who keeps them alive until the work queued on the
+ *   stream has finished.  The library never frees or keeps them.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Every call only enqueues work on that stream and returns; nothing
+ *   synchronises except tvd_read_flags(), tvd_autotune() and the create,
+ *   destroy and sequence-create calls.
+ * - Variables are stored as five consecutive cubes per block, in the order
+ *   (rho, m_x, m_y, m_z, e): mass density, momentum density, total energy
+ *   density (Eqs. MassConserve-EnergyConserve, ThermalEnergy, EOS).  Within
+ *   a cube x is fastest, then y, then z.  A "ghosted" block of interior edge
+ *   n holds (n+6)^3 cells per variable: the n^3 interior plus three ghost
+ *   zones on every side (the seven-point stencil of Sec. 2.2).  An
+ *   "interior" block holds n^3 cells per variable.
+ * - The element type of every state buffer is the batch dtype (TVD_F32:
+ *   float, TVD_F64: double); time steps, zone sizes, gamma, speeds and sums
+ *   are always double.
+ * - A context is not thread safe: use one per host thread.
+ */
+#ifndef TVD_H
+#define TVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    TVD_OK = 0,
+    TVD_WARN_FLOORED = 1,         /* tvd_read_flags: some cells had P < p_floor   */
+    TVD_ERR_INVALID_ARG = -1,     /* a NULL pointer, a bad size or enum value      */
+    TVD_ERR_UNSUPPORTED = -2,     /* valid request this build does not implement  */
+    TVD_ERR_HIP = -3,             /* a HIP runtime call failed (text in last_error)*/
+    TVD_ERR_NONPHYSICAL = -4,     /* tvd_read_flags: rho <= 0 or non-finite cells  */
+    TVD_ERR_ALIAS = -5,           /* input and output buffers overlap              */
+    TVD_ERR_STATE = -6            /* call not allowed in the current state         */
+};
+
+enum { TVD_F32 = 1, TVD_F64 = 2 };            /* state element type              */
+enum { TVD_XYZ = 0, TVD_ZYX = 1 };            /* forward / backward sweep triple  */
+enum { TVD_LAYOUT_GHOSTED = 0, TVD_LAYOUT_INTERIOR = 1 };
+
+/* flags of tvd_patch_advance: which kernel runs */
+enum {
+    TVD_KERNEL_AUTO = 0,      /* the batched kernel, tuned variant if tuned      */
+    TVD_KERNEL_BATCHED = 1,   /* LDS-staged batched kernel, FP32 or FP64          */
+    TVD_KERNEL_PLAIN = 2      /* plain FP64 kernel, one workgroup per 8^3 block  */
+};
+
+typedef struct tvd_ctx tvd_ctx;
+
+/*
+ * A batch of blocks.  Every block b has an interior edge e_b (8 or 16), a
+ * time step dt_b and a zone size dh_b.
+ *   edge      uniform interior edge when d_edge == NULL.
+ *   d_edge    [n_blocks] device int32 edges, or NULL.  When non-NULL the
+ *             offsets below are required.
+ *   d_in_off  [n_blocks] device int64: element offset of block b's ghosted
+ *             data (5 cubes of (e_b+6)^3) from the base pointer, or NULL for
+ *             dense packing b * 5 * (edge+6)^3.
+ *   d_out_off [n_blocks] device int64: element offset of block b's interior
+ *             data (5 cubes of e_b^3), or NULL for dense b * 5 * edge^3.
+ *   d_dt,d_dh [n_blocks] device double, or NULL to use the scalars dt, dh.
+ * Offsets must keep every block inside the buffers the caller passes; the
+ * library cannot check device arrays and reads them as given.
+ */
+typedef struct tvd_batch {
+    int32_t dtype;
+    int32_t n_blocks;
+    int32_t edge;
+    int32_t reserved;
+    const int32_t *d_edge;
+    const int64_t *d_in_off;
+    const int64_t *d_out_off;
+    const double *d_dt;
+    const double *d_dh;
+    double dt;
+    double dh;
+} tvd_batch;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`: allocates the workspace that holds
+ * per-block partial results and the health counters.  Synchronous. */
+int tvd_create(tvd_ctx **out, int device);
+/* Free the context and its workspace; waits for the device first. */
+int tvd_destroy(tvd_ctx *ctx);
+/* Static text for a status code. */
+const char *tvd_status_string(int status);
+/* Text of the last failing call on this context (empty if none). */
+const char *tvd_last_error(const tvd_ctx *ctx);
+/* Grow the workspace to hold per-block partials of n_blocks blocks.  Entry
+ * points grow it on demand, but not while `stream` is being captured into a
+ * graph: reserve the largest batch before capturing.  Synchronous. */
+int tvd_reserve(tvd_ctx *ctx, int n_blocks);
+
+/* ---- the hot path --------------------------------------------------------- */
+
+/*
+ * One step of the relaxing TVD scheme on every block (Sec. 2.2; Sec. 3.1 for
+ * the one-block-per-workgroup design it re-thinks): per pencil, freezing
+ * speed c = |v_d| + c_s and split fluxes F^R, F^L (Eq. LRFlux), the
+ * first-order upwind half step (Eq. MidpointValue), fluxes recomputed at the
+ * midpoint and corrected to second order with the van Leer limiter (Eqs.
+ * 2ndTVDFluxCorr-2ndRFlux, the left-moving flux mirrored), and the full step
+ * from u^t (Eq. FullstepValue); three sweeps in the order xyz
+ * (sweep_order = TVD_XYZ) or zyx (TVD_ZYX) sharing one dt.
+ *   d_u_in   ghosted blocks (read only), d_u_out interior blocks (written);
+ *            the two must not overlap (TVD_ERR_ALIAS for equal base pointers
+ *            or overlapping dense extents).
+ *   gamma    ratio of specific heats (> 1, or exactly 1 for pressureless gas).
+ *   p_floor  pressure floor: fluxes and sound speeds use max(P, p_floor); the
+ *            stored energy is never changed.
+ *   flags    TVD_KERNEL_* (PLAIN requires TVD_F64 and uniform edge 8).
+ *            FP32 batches take edges 8 and 16, mixed through d_edge; FP64
+ *            batches take uniform edge 8 only (else TVD_ERR_UNSUPPORTED).
+ *   d_smax   optional (NULL = skip): receives max over the output interior of
+ *            c_s + max(|v_x|, |v_y|, |v_z|) in FP64 (Eq. CFL), fused.
+ *   d_sums   optional (NULL = skip): receives the five sums over the output
+ *            interior of u * dh_b^3, FP64 with Neumaier compensation and a
+ *            fixed reduction order (deterministic), fused.
+ * Output cells with rho <= 0 or non-finite values, and cells with
+ * P < p_floor, are counted on the device (see tvd_read_flags).
+ */
+int tvd_patch_advance(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u_in,
+                      void *d_u_out, int32_t sweep_order, double gamma,
+                      double p_floor, int32_t flags, double *d_smax,
+                      double *d_sums, void *stream);
+
+/*
+ * Eq. (CFL) signal speed: d_smax[0] = max over the interior cells of all
+ * blocks of c_s + max(|v_x|, |v_y|, |v_z|), with c_s from max(P, p_floor);
+ * evaluated in FP64 from the stored values.  layout selects ghosted or
+ * interior blocks (ghost cells are skipped).
+ */
+int tvd_max_signal_speed(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u,
+                         int32_t layout, double gamma, double p_floor,
+                         double *d_smax, void *stream);
+
+/*
+ * Time step from a signal speed (Eq. CFL with Courant number cfl, Sec. 3.3):
+ * d_dt_out[b] = cfl * dh_b / d_smax[0] for every block, on the device, so
+ * that the next advance can read it through batch->d_dt without a host
+ * round trip.
+ */
+int tvd_dt_from_speed(tvd_ctx *ctx, const tvd_batch *batch, const double *d_smax,
+                      double cfl, double *d_dt_out, void *stream);
+
+/*
+ * Conservation sums: d_sums[k] = sum over blocks b and interior cells of
+ * u_k * dh_b^3, k = 0..4, FP64, Neumaier-compensated, fixed order.
+ */
+int tvd_conservation_sums(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u,
+                          int32_t layout, double *d_sums, void *stream);
+
+/*
+ * Health counters accumulated by every advance since the last read: output
+ * cells with P < p_floor and output cells with rho <= 0 or non-finite values.
+ * Synchronises `stream`, then resets the counters.  Returns
+ * TVD_ERR_NONPHYSICAL if n_nonphysical > 0, else TVD_WARN_FLOORED if
+ * n_floored > 0, else TVD_OK.  Either output pointer may be NULL.
+ */
+int tvd_read_flags(tvd_ctx *ctx, int64_t *n_floored, int64_t *n_nonphysical,
+                   void *stream);
+
+/*
+ * Ghost-zone fill by sibling copy (Sec. 2.2: ghost zones of a patch are
+ * copied from its siblings when they exist).  For every block b of the batch
+ * and every ghost cell of its ghosted copy, the value is read from the
+ * interior of the block that covers that cell: d_nbr[27*b + r] names that
+ * block for the neighbour region r = (rx+1) + 3(ry+1) + 9(rz+1), rx, ry, rz in
+ * {-1, 0, 1} (r = 13 is b itself, whose interior is copied too).  A negative
+ * entry leaves that region untouched (the caller fills it, e.g. by
+ * interpolation from a coarser level).  A neighbour must be a block of the
+ * batch (index < n_blocks) with the same edge as b; otherwise the region is
+ * left untouched and counted as non-physical.  d_interior uses the batch's out offsets, d_ghosted its in
+ * offsets.
+ */
+int tvd_fill_ghosts(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
+                    const void *d_interior, void *d_ghosted, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVD_H */

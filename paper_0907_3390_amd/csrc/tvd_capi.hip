@@ -1,0 +1,375 @@
+// The C ABI of libtvd (declared in include/tvd.h): contexts, argument
+// validation, workspace management and kernel dispatch.  Every check that
+// can be made on the host is made before anything is launched.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "tvd.h"
+#include "tvd_internal.hpp"
+
+struct tvd_ctx {
+  int device = 0;
+  std::string err;
+  // workspace: per-block partials and health counters
+  double* ws_smax = nullptr;
+  double* ws_sums = nullptr;
+  unsigned long long* counters = nullptr;
+  int ws_blocks = 0;
+  // tuned variants, per dtype (index 0: FP32, 1: FP64) and edge (0: 8, 1: 16)
+  int tuned[2][2] = {{-1, -1}, {-1, -1}};
+};
+
+namespace {
+
+int fail(tvd_ctx* ctx, int status, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return status;
+}
+
+int hip_fail(tvd_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, TVD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Make `device` current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Grow the workspace to hold n blocks.  Not allowed while capturing.
+int reserve(tvd_ctx* ctx, int n, hipStream_t s) {
+  if (n <= ctx->ws_blocks) return TVD_OK;
+  if (stream_capturing(s))
+    return fail(ctx, TVD_ERR_STATE,
+                "workspace for %d blocks must be reserved before stream capture (have %d)", n,
+                ctx->ws_blocks);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+  (void)hipFree(ctx->ws_smax);
+  (void)hipFree(ctx->ws_sums);
+  ctx->ws_smax = nullptr;
+  ctx->ws_sums = nullptr;
+  ctx->ws_blocks = 0;
+  const int cap = n < 1024 ? 1024 : n;
+  e = hipMalloc(&ctx->ws_smax, sizeof(double) * (size_t)cap);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
+  e = hipMalloc(&ctx->ws_sums, sizeof(double) * 10 * (size_t)cap);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
+  ctx->ws_blocks = cap;
+  return TVD_OK;
+}
+
+size_t elem_size(int dtype) { return dtype == TVD_F32 ? 4 : 8; }
+
+// Host-side checks of a batch descriptor.
+int check_batch(tvd_ctx* ctx, const tvd_batch* b) {
+  if (!b) return fail(ctx, TVD_ERR_INVALID_ARG, "batch is NULL");
+  if (b->dtype != TVD_F32 && b->dtype != TVD_F64)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "dtype %d is neither TVD_F32 nor TVD_F64", b->dtype);
+  if (b->n_blocks < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_blocks %d < 0", b->n_blocks);
+  if (b->d_edge == nullptr) {
+    if (b->edge != 8 && b->edge != 16)
+      return fail(ctx, TVD_ERR_INVALID_ARG, "edge %d is not 8 or 16", b->edge);
+  } else if (b->d_in_off == nullptr || b->d_out_off == nullptr) {
+    return fail(ctx, TVD_ERR_INVALID_ARG, "mixed edges (d_edge) need d_in_off and d_out_off");
+  }
+  if (b->d_dt == nullptr && !(b->dt >= 0.0))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "dt %g must be >= 0", b->dt);
+  if (b->d_dh == nullptr && !(b->dh > 0.0))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "dh %g must be > 0", b->dh);
+  return TVD_OK;
+}
+
+int check_gamma(tvd_ctx* ctx, double gamma, double pfloor) {
+  if (!(gamma >= 1.0) || !(gamma < 1e6))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "gamma %g must be >= 1", gamma);
+  if (!(pfloor >= 0.0) || !(pfloor < 1e300))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "p_floor %g must be finite and >= 0", pfloor);
+  return TVD_OK;
+}
+
+tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void* uout,
+                         double gamma, double pfloor) {
+  tvd::KParams kp;
+  kp.uin = uin;
+  kp.uout = uout;
+  kp.d_edge = b->d_edge;
+  kp.in_off = b->d_in_off;
+  kp.out_off = b->d_out_off;
+  kp.d_dt = b->d_dt;
+  kp.d_dh = b->d_dh;
+  kp.dt = b->dt;
+  kp.dh = b->dh;
+  kp.gamma = gamma;
+  kp.pfloor = pfloor;
+  kp.nblocks = b->n_blocks;
+  kp.edge = b->d_edge ? 0 : b->edge;
+  kp.ws_smax = ctx->ws_smax;
+  kp.ws_sums = ctx->ws_sums;
+  kp.counters = ctx->counters;
+  return kp;
+}
+
+tvd::Variant default_variant(int dtype, int edge) {
+  if (edge == 16) return tvd::Variant{16, 512, 16};
+  return dtype == TVD_F32 ? tvd::Variant{8, 128, 8} : tvd::Variant{8, 256, 8};
+}
+
+tvd::Variant chosen_variant(const tvd_ctx* ctx, int dtype, int edge) {
+  const int t = ctx->tuned[dtype == TVD_F32 ? 0 : 1][edge == 16 ? 1 : 0];
+  if (t >= 0) return tvd::variant_at(t);
+  return default_variant(dtype, edge);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tvd_status_string(int status) {
+  switch (status) {
+    case TVD_OK: return "ok";
+    case TVD_WARN_FLOORED: return "warning: pressure floor applied";
+    case TVD_ERR_INVALID_ARG: return "invalid argument";
+    case TVD_ERR_UNSUPPORTED: return "unsupported";
+    case TVD_ERR_HIP: return "HIP runtime error";
+    case TVD_ERR_NONPHYSICAL: return "non-physical state";
+    case TVD_ERR_ALIAS: return "input and output overlap";
+    case TVD_ERR_STATE: return "call not allowed in this state";
+    default: return "unknown status";
+  }
+}
+
+const char* tvd_last_error(const tvd_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int tvd_create(tvd_ctx** out, int device) {
+  if (!out) return TVD_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return TVD_ERR_INVALID_ARG;
+  tvd_ctx* ctx = new tvd_ctx();
+  ctx->device = device;
+  DeviceGuard g(device);
+  if (!g.ok) {
+    delete ctx;
+    return TVD_ERR_HIP;
+  }
+  if (hipMalloc(&ctx->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      reserve(ctx, 1024, nullptr) != TVD_OK || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(ctx->counters);
+    (void)hipFree(ctx->ws_smax);
+    (void)hipFree(ctx->ws_sums);
+    delete ctx;
+    return TVD_ERR_HIP;
+  }
+  *out = ctx;
+  return TVD_OK;
+}
+
+int tvd_destroy(tvd_ctx* ctx) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ws_smax);
+    (void)hipFree(ctx->ws_sums);
+    (void)hipFree(ctx->counters);
+  }
+  delete ctx;
+  return TVD_OK;
+}
+
+int tvd_reserve(tvd_ctx* ctx, int n_blocks) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (n_blocks < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_blocks %d < 0", n_blocks);
+  DeviceGuard g(ctx->device);
+  return reserve(ctx, n_blocks, nullptr);
+}
+
+int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
+                      int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                      double* d_smax, double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if ((st = check_gamma(ctx, gamma, p_floor))) return st;
+  if (sweep_order != TVD_XYZ && sweep_order != TVD_ZYX)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "sweep_order %d", sweep_order);
+  if (flags != TVD_KERNEL_AUTO && flags != TVD_KERNEL_BATCHED && flags != TVD_KERNEL_PLAIN)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "flags %d", flags);
+  if (batch->n_blocks == 0) return TVD_OK;
+  if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
+  if (d_u_in == d_u_out) return fail(ctx, TVD_ERR_ALIAS, "d_u_in == d_u_out");
+  if (!batch->d_in_off && !batch->d_out_off && !batch->d_edge) {
+    const size_t es = elem_size(batch->dtype);
+    const size_t m = batch->edge + 6, n = batch->edge;
+    const char* a = (const char*)d_u_in;
+    const char* b = (const char*)d_u_out;
+    const size_t la = (size_t)batch->n_blocks * 5 * m * m * m * es;
+    const size_t lb = (size_t)batch->n_blocks * 5 * n * n * n * es;
+    if (a < b + lb && b < a + la) return fail(ctx, TVD_ERR_ALIAS, "input and output overlap");
+  }
+  if (flags == TVD_KERNEL_PLAIN) {
+    if (batch->dtype != TVD_F64 || batch->d_edge || batch->edge != 8)
+      return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel needs TVD_F64 and uniform edge 8");
+  }
+  if (batch->dtype == TVD_F64 && (batch->d_edge || batch->edge != 8))
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "FP64 batches take uniform edge 8 (edge 16 exceeds the 160 KB LDS)");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, TVD_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const bool fuse = d_smax || d_sums;
+  if (fuse && (st = reserve(ctx, batch->n_blocks, s))) return st;
+  const tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
+  hipError_t e;
+  if (flags == TVD_KERNEL_PLAIN) {
+    e = tvd::launch_plain_f64(sweep_order, fuse, kp, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "plain kernel launch");
+  } else if (batch->d_edge) {
+    // one launch per edge; a workgroup whose block has the other edge exits
+    for (int edge : {16, 8}) {
+      e = tvd::launch_batched(batch->dtype, sweep_order, chosen_variant(ctx, batch->dtype, edge),
+                              fuse, kp, s);
+      if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
+    }
+  } else {
+    e = tvd::launch_batched(batch->dtype, sweep_order,
+                            chosen_variant(ctx, batch->dtype, batch->edge), fuse, kp, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
+  }
+  if (d_smax) {
+    e = tvd::launch_finalize_max(ctx->ws_smax, batch->n_blocks, d_smax, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
+  }
+  if (d_sums) {
+    e = tvd::launch_finalize_sums(ctx->ws_sums, batch->n_blocks, d_sums, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
+  }
+  return TVD_OK;
+}
+
+int tvd_max_signal_speed(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, int32_t layout,
+                         double gamma, double p_floor, double* d_smax, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if ((st = check_gamma(ctx, gamma, p_floor))) return st;
+  if (layout != TVD_LAYOUT_GHOSTED && layout != TVD_LAYOUT_INTERIOR)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "layout %d", layout);
+  if (!d_u || !d_smax) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = reserve(ctx, batch->n_blocks, s))) return st;
+  const tvd::KParams kp = make_params(ctx, batch, d_u, nullptr, gamma, p_floor);
+  hipError_t e = hipSuccess;
+  if (batch->n_blocks > 0) e = tvd::launch_signal_speed(batch->dtype, layout, kp, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "signal speed launch");
+  e = tvd::launch_finalize_max(ctx->ws_smax, batch->n_blocks, d_smax, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
+  return TVD_OK;
+}
+
+int tvd_dt_from_speed(tvd_ctx* ctx, const tvd_batch* batch, const double* d_smax, double cfl,
+                      double* d_dt_out, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if (!(cfl > 0.0) || !(cfl <= 1.0))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "cfl %g must lie in (0, 1]", cfl);
+  if (!d_smax || !d_dt_out) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if (batch->n_blocks == 0) return TVD_OK;
+  DeviceGuard g(ctx->device);
+  const tvd::KParams kp = make_params(ctx, batch, nullptr, nullptr, 1.0, 0.0);
+  hipError_t e = tvd::launch_dt_from_speed(kp, d_smax, cfl, d_dt_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "dt launch");
+  return TVD_OK;
+}
+
+int tvd_conservation_sums(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, int32_t layout,
+                          double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if (layout != TVD_LAYOUT_GHOSTED && layout != TVD_LAYOUT_INTERIOR)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "layout %d", layout);
+  if (!d_u || !d_sums) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = reserve(ctx, batch->n_blocks, s))) return st;
+  const tvd::KParams kp = make_params(ctx, batch, d_u, nullptr, 1.0, 0.0);
+  hipError_t e = hipSuccess;
+  if (batch->n_blocks > 0) e = tvd::launch_cons_sums(batch->dtype, layout, kp, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sums launch");
+  e = tvd::launch_finalize_sums(ctx->ws_sums, batch->n_blocks, d_sums, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
+  return TVD_OK;
+}
+
+int tvd_read_flags(tvd_ctx* ctx, int64_t* n_floored, int64_t* n_nonphysical, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (stream_capturing(s)) return fail(ctx, TVD_ERR_STATE, "tvd_read_flags cannot be captured");
+  DeviceGuard g(ctx->device);
+  unsigned long long h[2] = {0, 0};
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  e = hipMemcpy(h, ctx->counters, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(counters)");
+  e = tvd::launch_zero_u64(ctx->counters, 2, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "counter reset launch");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  if (n_floored) *n_floored = (int64_t)h[0];
+  if (n_nonphysical) *n_nonphysical = (int64_t)h[1];
+  if (h[1]) return TVD_ERR_NONPHYSICAL;
+  if (h[0]) return TVD_WARN_FLOORED;
+  return TVD_OK;
+}
+
+int tvd_fill_ghosts(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                    const void* d_interior, void* d_ghosted, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if (batch->n_blocks == 0) return TVD_OK;
+  if (!d_nbr || !d_interior || !d_ghosted)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if (d_interior == d_ghosted) return fail(ctx, TVD_ERR_ALIAS, "interior == ghosted");
+  DeviceGuard g(ctx->device);
+  const tvd::KParams kp = make_params(ctx, batch, d_ghosted, const_cast<void*>(d_interior), 1.0,
+                                      0.0);
+  const int max_edge = batch->d_edge ? 16 : batch->edge;
+  hipError_t e = tvd::launch_fill_ghosts(batch->dtype, kp, d_nbr, max_edge, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "ghost fill launch");
+  return TVD_OK;
+}
+
+}  // extern "C"

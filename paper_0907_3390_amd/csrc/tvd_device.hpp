@@ -1,0 +1,176 @@
+// Device-side building blocks of the relaxing TVD patch advance for gfx950.
+//
+// One 1-D sweep of the scheme (Schive, Tsai & Chiueh, GAMER, Sec. 2.2) is
+// applied to a pencil of n+6 cells by a single thread that walks the pencil
+// once, keeping a rolling window of cell states and fluxes in registers: the
+// split fluxes of Eq. (LRFlux), the first-order upwind half step of
+// Eq. (MidpointValue), the recomputed midpoint fluxes with the van Leer
+// limited correction of Eqs. (2ndTVDFluxCorr)-(2ndRFlux) (left-moving flux
+// mirrored about the interface), and the full step of Eq. (FullstepValue).
+// Fluxes never leave registers, so a sweep needs no LDS traffic beyond one
+// read and one write of each cell state.  This replaces the paper's design of
+// one thread per cell with fluxes exchanged through shared memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tvd {
+
+constexpr int kNV = 5;     // rho, m_x, m_y, m_z, e
+constexpr int kG = 3;      // ghost zones per side (seven-point stencil)
+
+// Arithmetic of the bulk type.  FP32 uses the hardware reciprocal and square
+// root (about 1 ulp); FP64 keeps IEEE division and square root.
+template <typename T> struct Num;
+template <> struct Num<float> {
+  __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  __device__ static inline float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  __device__ static inline float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  __device__ static inline float abs(float x) { return __builtin_fabsf(x); }
+};
+template <> struct Num<double> {
+  __device__ static inline double rcp(double x) { return 1.0 / x; }
+  __device__ static inline double div(double a, double b) { return a / b; }
+  __device__ static inline double sqrt(double x) { return __builtin_sqrt(x); }
+  __device__ static inline double abs(double x) { return __builtin_fabs(x); }
+};
+
+// Per-block coefficients of one sweep.
+template <typename T> struct Coef {
+  T gamma;    // ratio of specific heats
+  T gm1;      // gamma - 1
+  T pfloor;   // pressure floor
+  T lam;      // dt / dh
+  T hlam;     // dt / (2 dh)
+};
+
+// Freezing speed and split fluxes of one cell, Eq. (LRFlux) multiplied out:
+// F^R = (c u + F)/2, F^L = (c u - F)/2 with c = |v_n| + c_s.  Components are
+// in pencil order: 0 rho, 1 normal momentum, 2-3 transverse momenta, 4 e.
+// The pressure entering F and c_s is max(P, p_floor).
+template <typename T>
+__device__ __forceinline__ void split_flux(const T u[kNV], const Coef<T>& cf, T FR[kNV],
+                                           T FL[kNV]) {
+  const T inv = Num<T>::rcp(u[0]);
+  const T vn = u[1] * inv;
+  const T m2 = u[1] * u[1] + (u[2] * u[2] + u[3] * u[3]);
+  T P = cf.gm1 * (u[4] - T(0.5) * m2 * inv);
+  P = P < cf.pfloor ? cf.pfloor : P;
+  const T cs = Num<T>::sqrt(cf.gamma * P * inv);
+  const T hc = T(0.5) * (Num<T>::abs(vn) + cs);
+  const T hv = T(0.5) * vn;
+  T hF[kNV];
+  hF[0] = T(0.5) * u[1];
+  hF[1] = u[1] * hv + T(0.5) * P;
+  hF[2] = u[2] * hv;
+  hF[3] = u[3] * hv;
+  hF[4] = (u[4] + P) * hv;
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) {
+    FR[k] = hc * u[k] + hF[k];
+    FL[k] = hc * u[k] - hF[k];
+  }
+}
+
+// Eq. (vanLeer) on the halved corrections (a/2, b/2): 2 (a/2)(b/2) / ((a+b)/2)
+// = ab / (a+b) when ab > 0, else 0.
+template <typename T>
+__device__ __forceinline__ T vanleer(T a, T b) {
+  const T p = a * b;
+  return p > T(0) ? Num<T>::div(p, a + b) : T(0);
+}
+
+// One sweep over a pencil of M = N+6 cells.  Src::load(j, u) fetches cell j
+// (0 .. M-1, ghosts included) in pencil component order; Dst::store(i, u)
+// writes interior cell i (0 .. N-1).  The loop is fully unrolled, so the
+// rolling windows (indexed modulo 4) live in registers.
+template <typename T, int N, class Src, class Dst>
+__device__ __forceinline__ void pencil_sweep(const Src& src, const Dst& dst, const Coef<T>& cf) {
+  constexpr int M = N + 2 * kG;
+  T q[4][kNV];     // cell states u^t, ring over j
+  T FRh[4][kNV];   // midpoint right-moving fluxes, ring over j
+  T FLh[4][kNV];   // midpoint left-moving fluxes, ring over j
+  T FRp[kNV];      // F^R of the previous cell
+  T Gp[kNV];       // first-order interface flux G_{j-3/2}
+  T Hp[kNV];       // second-order interface flux of the previous interface
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    T* qj = q[j & 3];
+    src.load(j, qj);
+    T FR[kNV], FL[kNV];
+    split_flux(qj, cf, FR, FL);
+    if (j >= 1) {
+      // first-order upwind flux at j-1/2: F^R_{j-1} - F^L_j
+      T G[kNV];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) G[k] = FRp[k] - FL[k];
+      if (j >= 2) {
+        // Eq. (MidpointValue) for cell j-1, then its midpoint fluxes
+        T h[kNV];
+        const T* qm = q[(j - 1) & 3];
+#pragma unroll
+        for (int k = 0; k < kNV; ++k) h[k] = qm[k] - cf.hlam * (G[k] - Gp[k]);
+        split_flux(h, cf, FRh[(j - 1) & 3], FLh[(j - 1) & 3]);
+      }
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) Gp[k] = G[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) FRp[k] = FR[k];
+    if (j >= 5) {
+      // second-order flux at interface (j-3)+1/2 from midpoint fluxes of
+      // cells j-4 .. j-1 (Eqs. 2ndFluxCorr, vanLeer, 2ndRFlux and mirror)
+      const int a = (j - 4) & 3, b = (j - 3) & 3, c = (j - 2) & 3, d = (j - 1) & 3;
+      T H[kNV];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
+        const T R = FRh[b][k] + vanleer(FRh[b][k] - FRh[a][k], FRh[c][k] - FRh[b][k]);
+        const T L = FLh[c][k] + vanleer(FLh[c][k] - FLh[d][k], FLh[b][k] - FLh[c][k]);
+        H[k] = R - L;
+      }
+      if (j >= 6) {
+        // Eq. (FullstepValue) for cell j-3 (interior cell j-6), from u^t
+        T out[kNV];
+        const T* q0 = q[(j - 3) & 3];
+#pragma unroll
+        for (int k = 0; k < kNV; ++k) out[k] = q0[k] - cf.lam * (H[k] - Hp[k]);
+        dst.store(j - 6, out);
+      }
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) Hp[k] = H[k];
+    }
+  }
+}
+
+// Global component index of pencil component k for a sweep along axis D.
+template <int D>
+__device__ __host__ constexpr int gcomp(int k) {
+  return k == 0 ? 0 : k == 4 ? 4 : k == 1 ? 1 + D : k == 2 ? 1 + (D + 1) % 3 : 1 + (D + 2) % 3;
+}
+
+// ---- FP64 compensated accumulation (Neumaier) and exact pair merge --------
+
+struct CSum {
+  double s, c;
+};
+
+__device__ __forceinline__ void csum_add(CSum& a, double v) {
+  const double t = a.s + v;
+  if (__builtin_fabs(a.s) >= __builtin_fabs(v))
+    a.c += (a.s - t) + v;
+  else
+    a.c += (v - t) + a.s;
+  a.s = t;
+}
+
+// Merge two compensated partial sums: the rounding error of s1 + s2 is
+// recovered exactly (TwoSum) and added to the compensations.
+__device__ __forceinline__ CSum csum_merge(CSum a, CSum b) {
+  const double s = a.s + b.s;
+  const double bb = s - a.s;
+  const double err = (a.s - (s - bb)) + (b.s - bb);
+  return CSum{s, (a.c + b.c) + err};
+}
+
+}  // namespace tvd

@@ -1,0 +1,53 @@
+// Internal interface between the C ABI (tvd_capi.hip) and the kernels
+// (tvd_kernels.hip).  Host-side only; no device code here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tvd {
+
+// Everything a batch kernel needs, passed by value as the kernel argument.
+struct KParams {
+  const void* uin;
+  void* uout;
+  const int32_t* d_edge;
+  const int64_t* in_off;
+  const int64_t* out_off;
+  const double* d_dt;
+  const double* d_dh;
+  double dt, dh, gamma, pfloor;
+  int nblocks;
+  int edge;                      // uniform edge (0 when d_edge is used)
+  double* ws_smax;               // [nblocks] per-block max signal speed
+  double* ws_sums;               // [nblocks][10] per-block (sum, comp) x 5
+  unsigned long long* counters;  // [0] floored, [1] non-physical
+};
+
+// Variant of the batched kernel (chosen by the tuner or by default).
+struct Variant {
+  int edge;      // 8 or 16
+  int threads;   // workgroup size
+  int pad;       // LDS row padding (layout variant)
+};
+
+// Launchers.  All return a hipError_t from the launch.
+hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, const KParams& kp,
+                          hipStream_t s);
+hipError_t launch_plain_f64(int order, bool fuse, const KParams& kp, hipStream_t s);
+hipError_t launch_signal_speed(int dtype, int layout, const KParams& kp, hipStream_t s);
+hipError_t launch_cons_sums(int dtype, int layout, const KParams& kp, hipStream_t s);
+hipError_t launch_finalize_max(const double* ws, int n, double* out, hipStream_t s);
+hipError_t launch_finalize_sums(const double* ws, int n, double* out, hipStream_t s);
+hipError_t launch_dt_from_speed(const KParams& kp, const double* smax, double cfl,
+                                double* dt_out, hipStream_t s);
+hipError_t launch_fill_ghosts(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
+                              hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+
+// Variants compiled into the library.
+int variant_count();
+Variant variant_at(int i);
+bool variant_supported(int dtype, const Variant& v);
+
+}  // namespace tvd

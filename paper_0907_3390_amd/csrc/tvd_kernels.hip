@@ -1,0 +1,617 @@
+// HIP kernels for gfx950: the batched and the plain relaxing-TVD advance,
+// the CFL signal speed, compensated conservation sums, their finalisation,
+// the device time step and the sibling ghost-zone fill.
+//
+// Scheme: Schive, Tsai & Chiueh, GAMER, Sec. 2.2 (equations cited in
+// tvd_device.hpp); signal speed Eq. (CFL), Sec. 3.3.
+#include <hip/hip_runtime.h>
+
+#include "tvd_device.hpp"
+#include "tvd_internal.hpp"
+
+namespace tvd {
+
+// ---------------------------------------------------------------------------
+// block-level reductions (fixed order, hence deterministic)
+// ---------------------------------------------------------------------------
+
+template <int NT>
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    r = red[0];
+    for (int i = 1; i < NT / 64; ++i) r = fmax(r, red[i]);
+  }
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+template <int NT>
+__device__ void block_csum(CSum a[kNV], CSum* red) {
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      CSum o{__shfl_xor(a[k].s, off), __shfl_xor(a[k].c, off)};
+      a[k] = csum_merge(a[k], o);
+    }
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0)
+    for (int k = 0; k < kNV; ++k) red[w * kNV + k] = a[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < kNV; ++k) {
+      CSum r = red[k];
+      for (int i = 1; i < NT / 64; ++i) r = csum_merge(r, red[i * kNV + k]);
+      a[k] = r;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// per-cell diagnostics on an output state (FP64): Eq. (CFL) speed, health
+// ---------------------------------------------------------------------------
+
+struct CellDiag {
+  double smax;
+  unsigned floored, bad;
+  CSum sum[kNV];
+};
+
+__device__ __forceinline__ void diag_init(CellDiag& d) {
+  d.smax = 0.0;
+  d.floored = d.bad = 0;
+  for (int k = 0; k < kNV; ++k) d.sum[k] = CSum{0.0, 0.0};
+}
+
+// Health check and, when FUSE, the signal speed and sums, of one cell.
+template <typename T, bool FUSE>
+__device__ __forceinline__ void diag_cell(CellDiag& d, const T u[kNV], double gamma,
+                                          double pfloor) {
+  if (FUSE) {
+    const double rho = u[0], mx = u[1], my = u[2], mz = u[3], e = u[4];
+    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+    const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
+    double P = (gamma - 1.0) * (e - kin);
+    d.floored += P < pfloor;
+    P = P < pfloor ? pfloor : P;
+    const double cs = __builtin_sqrt(gamma * P / rho);
+    const double s = cs + fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+    d.smax = s > d.smax ? s : d.smax;
+    d.bad += !(rho > 0.0) || !__builtin_isfinite(e) || !__builtin_isfinite(mx) ||
+             !__builtin_isfinite(my) || !__builtin_isfinite(mz) || !__builtin_isfinite(rho);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) csum_add(d.sum[k], (double)u[k]);
+  } else {
+    const T inv = Num<T>::rcp(u[0]);
+    const T m2 = u[1] * u[1] + (u[2] * u[2] + u[3] * u[3]);
+    const T P = T(gamma - 1.0) * (u[4] - T(0.5) * m2 * inv);
+    d.floored += P < T(pfloor);
+    d.bad += !(u[0] > T(0)) || !__builtin_isfinite(P);
+  }
+}
+
+// Reduce the diagnostics of a workgroup and publish them for block b.
+template <int NT, bool FUSE>
+__device__ void diag_publish(CellDiag& d, int b, double dh, const KParams& kp, void* scratch) {
+  unsigned fl = d.floored, bad = d.bad;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    fl += __shfl_xor(fl, off);
+    bad += __shfl_xor(bad, off);
+  }
+  if ((threadIdx.x & 63) == 0 && (fl | bad)) {
+    if (fl) atomicAdd(&kp.counters[0], (unsigned long long)fl);
+    if (bad) atomicAdd(&kp.counters[1], (unsigned long long)bad);
+  }
+  if (FUSE) {
+    double* redd = reinterpret_cast<double*>(scratch);
+    const double sm = block_max<NT>(d.smax, redd);
+    if (threadIdx.x == 0) kp.ws_smax[b] = sm;
+    CSum* redc = reinterpret_cast<CSum*>(scratch);
+    block_csum<NT>(d.sum, redc);
+    if (threadIdx.x == 0) {
+      const double w = dh * dh * dh;
+      for (int k = 0; k < kNV; ++k) {
+        // the block's compensated sum times dh^3 (exact for dyadic dh)
+        kp.ws_sums[(size_t)b * 2 * kNV + 2 * k] = d.sum[k].s * w;
+        kp.ws_sums[(size_t)b * 2 * kNV + 2 * k + 1] = d.sum[k].c * w;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int block_edge(const KParams& kp, int b) {
+  return kp.d_edge ? kp.d_edge[b] : kp.edge;
+}
+
+template <typename T>
+__device__ __forceinline__ Coef<T> make_coef(const KParams& kp, int b, double& dh_out) {
+  const double dt = kp.d_dt ? kp.d_dt[b] : kp.dt;
+  const double dh = kp.d_dh ? kp.d_dh[b] : kp.dh;
+  dh_out = dh;
+  const double lam = dt / dh;  // FP64, rounded once to T
+  Coef<T> cf;
+  cf.gamma = T(kp.gamma);
+  cf.gm1 = T(kp.gamma - 1.0);
+  cf.pfloor = T(kp.pfloor);
+  cf.lam = T(lam);
+  cf.hlam = T(0.5 * lam);
+  return cf;
+}
+
+// ---------------------------------------------------------------------------
+// batched kernel: sweep 0 streams pencils from HBM, sweeps 1-2 in LDS
+// ---------------------------------------------------------------------------
+//
+// LDS holds the block after sweep 0: only the n interior cells along the
+// first sweep axis are kept (n x (n+6) x (n+6) cells per variable), indexed
+// by (c0, c1, c2) = coordinates along the first, second and third sweep axes.
+// Rows along c0 are XOR-swizzled by (c1 + c2) and rows along c2 padded so
+// that the strided accesses of every sweep spread over the LDS banks.
+
+template <int N, int PAD>
+struct LdsLayout {
+  static constexpr int M = N + 2 * kG;
+  static constexpr int P1 = N;              // c1 pitch
+  static constexpr int P2 = N * M + PAD;    // c2 pitch
+  static constexpr int PLANE = P2 * M;      // one variable
+  __device__ static inline int idx(int c0, int c1, int c2) {
+    return (c0 ^ ((c1 + c2) & (N - 1))) + P1 * c1 + P2 * c2;
+  }
+};
+
+// Sweep 0 source: a pencil of the ghosted block in HBM.
+template <typename T, int M, int D>
+struct GlobalPencil {
+  const T* __restrict__ p;  // cell j = 0 of the pencil, variable 0
+  __device__ inline void load(int j, T u[kNV]) const {
+    constexpr int S = D == 0 ? 1 : D == 1 ? M : M * M;
+    constexpr int M3 = M * M * M;
+    const T* c = p + j * S;
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = c[gcomp<D>(k) * M3];
+  }
+};
+
+// Sweep 0 sink: interior cells along c0 into LDS.
+template <typename T, class L, int D>
+struct LdsSink0 {
+  T* s;
+  int c1, c2;
+  __device__ inline void store(int i, const T u[kNV]) const {
+    const int o = L::idx(i, c1, c2);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * L::PLANE + o] = u[k];
+  }
+};
+
+// Sweep 1: in-place pencil along c1 at (c0, c2).
+template <typename T, class L, int D>
+struct LdsPencil1 {
+  T* s;
+  int c0, c2;
+  __device__ inline void load(int j, T u[kNV]) const {
+    const int o = L::idx(c0, j, c2);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = s[gcomp<D>(k) * L::PLANE + o];
+  }
+  __device__ inline void store(int i, const T u[kNV]) const {
+    const int o = L::idx(c0, i + kG, c2);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * L::PLANE + o] = u[k];
+  }
+};
+
+// Sweep 2: in-place pencil along c2 at (c0, c1).
+template <typename T, class L, int D>
+struct LdsPencil2 {
+  T* s;
+  int c0, c1;
+  __device__ inline void load(int j, T u[kNV]) const {
+    const int o = L::idx(c0, c1, j);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = s[gcomp<D>(k) * L::PLANE + o];
+  }
+  __device__ inline void store(int i, const T u[kNV]) const {
+    const int o = L::idx(c0, c1, i + kG);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * L::PLANE + o] = u[k];
+  }
+};
+
+template <typename T, int N, int ORDER, int NT, int PAD, bool FUSE>
+__global__ __launch_bounds__(NT) void k_batched(KParams kp) {
+  using L = LdsLayout<N, PAD>;
+  constexpr int M = N + 2 * kG;
+  constexpr int M3 = M * M * M;
+  constexpr int N3 = N * N * N;
+  constexpr int D0 = ORDER == 0 ? 0 : 2;
+  constexpr int D1 = 1;
+  constexpr int D2 = ORDER == 0 ? 2 : 0;
+  __shared__ T S[kNV * L::PLANE];
+
+  const int b = blockIdx.x;
+  if (block_edge(kp, b) != N) return;  // block belongs to another edge's launch
+  const T* __restrict__ bin = reinterpret_cast<const T*>(kp.uin) +
+                              (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * M3);
+  T* __restrict__ bout = reinterpret_cast<T*>(kp.uout) +
+                         (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3);
+  double dh;
+  const Coef<T> cf = make_coef<T>(kp, b, dh);
+
+  // sweep 0: every (c1, c2) pencil, ghosts of the later axes included
+  for (int p = threadIdx.x; p < M * M; p += NT) {
+    int c1, c2, start;
+    if (ORDER == 0) {  // x pencils; consecutive threads step in y
+      c1 = p % M;
+      c2 = p / M;
+      start = c1 * M + c2 * M * M;
+    } else {           // z pencils; consecutive threads step in x
+      c2 = p % M;
+      c1 = p / M;
+      start = c2 + c1 * M;
+    }
+    const GlobalPencil<T, M, D0> src{bin + start};
+    const LdsSink0<T, L, D0> dst{S, c1, c2};
+    pencil_sweep<T, N>(src, dst, cf);
+  }
+  __syncthreads();
+  // sweep 1: interior along c0, all of c2
+  for (int p = threadIdx.x; p < N * M; p += NT) {
+    const LdsPencil1<T, L, D1> acc{S, p % N, p / N};
+    pencil_sweep<T, N>(acc, acc, cf);
+  }
+  __syncthreads();
+  // sweep 2: interior along c0 and c1
+  for (int p = threadIdx.x; p < N * N; p += NT) {
+    const LdsPencil2<T, L, D2> acc{S, p % N, p / N + kG};
+    pencil_sweep<T, N>(acc, acc, cf);
+  }
+  __syncthreads();
+
+  // copy the interior out (coalesced, x fastest) with the fused diagnostics
+  CellDiag dg;
+  diag_init(dg);
+  for (int i = threadIdx.x; i < N3; i += NT) {
+    const int x = i % N, y = (i / N) % N, z = i / (N * N);
+    const int o = ORDER == 0 ? L::idx(x, y + kG, z + kG) : L::idx(z, y + kG, x + kG);
+    T u[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      u[k] = S[k * L::PLANE + o];
+      bout[k * N3 + i] = u[k];
+    }
+    diag_cell<T, FUSE>(dg, u, kp.gamma, kp.pfloor);
+  }
+  __syncthreads();
+  diag_publish<NT, FUSE>(dg, b, dh, kp, S);
+}
+
+// ---------------------------------------------------------------------------
+// plain FP64 kernel: one workgroup per 8^3 block, whole ghosted block in LDS,
+// the three sweeps in place with the region rule
+// ---------------------------------------------------------------------------
+
+constexpr int kPlainN = 8;
+constexpr int kPlainM = kPlainN + 2 * kG;
+constexpr int kPlainM3 = kPlainM * kPlainM * kPlainM;
+constexpr int kPlainNT = 256;
+
+template <int D>
+struct PlainPencil {
+  double* s;
+  int base;  // cell j = 0 of the pencil
+  static constexpr int S = D == 0 ? 1 : D == 1 ? kPlainM : kPlainM * kPlainM;
+  __device__ inline void load(int j, double u[kNV]) const {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = s[gcomp<D>(k) * kPlainM3 + base + j * S];
+  }
+  __device__ inline void store(int i, const double u[kNV]) const {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * kPlainM3 + base + (i + kG) * S] = u[k];
+  }
+};
+
+// Sweep along D; the transverse axis A is kept whole (ghosts included) when
+// LATER_A is set, i.e. when A is swept later in this step, else restricted
+// to the interior.  The two transverse axes are (D+1)%3 and (D+2)%3.
+template <int D, bool LATER1, bool LATER2>
+__device__ void plain_sweep(double* s, const Coef<double>& cf) {
+  constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+  constexpr int lo1 = LATER1 ? 0 : kG, n1 = LATER1 ? kPlainM : kPlainN;
+  constexpr int lo2 = LATER2 ? 0 : kG, n2 = LATER2 ? kPlainM : kPlainN;
+  constexpr int st[3] = {1, kPlainM, kPlainM * kPlainM};
+  for (int p = threadIdx.x; p < n1 * n2; p += kPlainNT) {
+    const int a1 = lo1 + p % n1, a2 = lo2 + p / n1;
+    const PlainPencil<D> acc{s, a1 * st[A1] + a2 * st[A2]};
+    pencil_sweep<double, kPlainN>(acc, acc, cf);
+  }
+}
+
+template <int ORDER, bool FUSE>
+__global__ __launch_bounds__(kPlainNT) void k_plain_f64(KParams kp) {
+  constexpr int N3 = kPlainN * kPlainN * kPlainN;
+  __shared__ double S[kNV * kPlainM3];
+  const int b = blockIdx.x;
+  const double* __restrict__ bin = reinterpret_cast<const double*>(kp.uin) +
+                                   (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * kPlainM3);
+  double* __restrict__ bout = reinterpret_cast<double*>(kp.uout) +
+                              (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3);
+  double dh;
+  const Coef<double> cf = make_coef<double>(kp, b, dh);
+  for (int i = threadIdx.x; i < kNV * kPlainM3; i += kPlainNT) S[i] = bin[i];
+  __syncthreads();
+  if (ORDER == 0) {
+    plain_sweep<0, true, true>(S, cf);    // x: y, z later
+    __syncthreads();
+    plain_sweep<1, true, false>(S, cf);   // y: z later, x earlier
+    __syncthreads();
+    plain_sweep<2, false, false>(S, cf);  // z: x, y earlier
+  } else {
+    plain_sweep<2, true, true>(S, cf);    // z: x, y later
+    __syncthreads();
+    plain_sweep<1, false, true>(S, cf);   // y: z earlier, x later
+    __syncthreads();
+    plain_sweep<0, false, false>(S, cf);  // x: y, z earlier
+  }
+  __syncthreads();
+  CellDiag dg;
+  diag_init(dg);
+  for (int i = threadIdx.x; i < N3; i += kPlainNT) {
+    const int x = i % kPlainN, y = (i / kPlainN) % kPlainN, z = i / (kPlainN * kPlainN);
+    const int o = (x + kG) + kPlainM * ((y + kG) + kPlainM * (z + kG));
+    double u[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      u[k] = S[k * kPlainM3 + o];
+      bout[k * N3 + i] = u[k];
+    }
+    diag_cell<double, FUSE>(dg, u, kp.gamma, kp.pfloor);
+  }
+  __syncthreads();
+  diag_publish<kPlainNT, FUSE>(dg, b, dh, kp, S);
+}
+
+// ---------------------------------------------------------------------------
+// standalone signal speed and conservation sums (one workgroup per block)
+// ---------------------------------------------------------------------------
+
+constexpr int kRedNT = 256;
+
+template <typename T, bool SPEED>
+__global__ __launch_bounds__(kRedNT) void k_block_diag(KParams kp, int layout) {
+  __shared__ CSum red[kRedNT / 64 * kNV];
+  const int b = blockIdx.x;
+  const int n = block_edge(kp, b);
+  const int m = layout == 0 ? n + 2 * kG : n;
+  const int g = layout == 0 ? kG : 0;
+  const int64_t m3 = (int64_t)m * m * m;
+  const T* base = reinterpret_cast<const T*>(kp.uin) +
+                  (layout == 0 ? (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3)
+                               : (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * m3));
+  const double dh = kp.d_dh ? kp.d_dh[b] : kp.dh;
+  CellDiag dg;
+  diag_init(dg);
+  const int n3 = n * n * n;
+  for (int i = threadIdx.x; i < n3; i += kRedNT) {
+    const int x = i % n, y = (i / n) % n, z = i / (n * n);
+    const int64_t o = (x + g) + (int64_t)m * ((y + g) + (int64_t)m * (z + g));
+    T u[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = base[k * m3 + o];
+    diag_cell<T, true>(dg, u, kp.gamma, kp.pfloor);
+  }
+  if (SPEED) {
+    const double sm = block_max<kRedNT>(dg.smax, reinterpret_cast<double*>(red));
+    if (threadIdx.x == 0) kp.ws_smax[b] = sm;
+  } else {
+    block_csum<kRedNT>(dg.sum, red);
+    if (threadIdx.x == 0) {
+      const double w = dh * dh * dh;
+      for (int k = 0; k < kNV; ++k) {
+        kp.ws_sums[(size_t)b * 2 * kNV + 2 * k] = dg.sum[k].s * w;
+        kp.ws_sums[(size_t)b * 2 * kNV + 2 * k + 1] = dg.sum[k].c * w;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalisation: one workgroup, fixed partition and fixed tree
+// ---------------------------------------------------------------------------
+
+constexpr int kFinNT = 1024;
+
+__global__ __launch_bounds__(kFinNT) void k_finalize_max(const double* ws, int n, double* out) {
+  __shared__ double red[kFinNT / 64];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += kFinNT) m = fmax(m, ws[i]);
+  const double r = block_max<kFinNT>(m, red);
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+__global__ __launch_bounds__(kFinNT) void k_finalize_sums(const double* ws, int n, double* out) {
+  __shared__ CSum red[kFinNT / 64 * kNV];
+  CSum a[kNV];
+  for (int k = 0; k < kNV; ++k) a[k] = CSum{0.0, 0.0};
+  // contiguous chunk per thread, in block order
+  const int per = (n + kFinNT - 1) / kFinNT;
+  const int lo = threadIdx.x * per;
+  const int hi = min(n, lo + per);
+  for (int b = lo; b < hi; ++b)
+    for (int k = 0; k < kNV; ++k)
+      a[k] = csum_merge(a[k], CSum{ws[(size_t)b * 2 * kNV + 2 * k], ws[(size_t)b * 2 * kNV + 2 * k + 1]});
+  block_csum<kFinNT>(a, red);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kNV; ++k) out[k] = a[k].s + a[k].c;
+}
+
+__global__ void k_dt_from_speed(KParams kp, const double* smax, double cfl, double* dt_out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kp.nblocks) return;
+  const double dh = kp.d_dh ? kp.d_dh[b] : kp.dh;
+  dt_out[b] = cfl * dh / smax[0];
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// sibling ghost fill
+// ---------------------------------------------------------------------------
+
+constexpr int kFillNT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32_t* nbr,
+                                                        int chunks) {
+  const int b = blockIdx.x / chunks;
+  const int chunk = blockIdx.x % chunks;
+  const int n = block_edge(kp, b);
+  const int m = n + 2 * kG;
+  const int m3 = m * m * m;
+  const int n3 = n * n * n;
+  const int cell = chunk * kFillNT + threadIdx.x;
+  if (cell >= m3) return;
+  const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+  const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
+  const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
+  const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
+  const int src = nbr[27 * b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
+  if (src < 0) return;
+  if (src >= kp.nblocks || block_edge(kp, src) != n) {
+    atomicAdd(&kp.counters[1], 1ull);
+    return;
+  }
+  const int sx = x - kG - rx * n, sy = y - kG - ry * n, sz = z - kG - rz * n;
+  const int so = sx + n * (sy + n * sz);
+  const T* s = reinterpret_cast<const T*>(kp.uout) +
+               (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n3);
+  T* d = reinterpret_cast<T*>(const_cast<void*>(kp.uin)) +
+         (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = s[(int64_t)k * n3 + so];
+}
+
+// ---------------------------------------------------------------------------
+// launchers and the variant table
+// ---------------------------------------------------------------------------
+
+static const Variant kVariants[] = {
+    {16, 512, 16},  // default FP32 edge 16: one workgroup per CU
+    {16, 512, 0},
+    {8, 128, 8},
+    {8, 256, 8},
+    {8, 128, 0},
+    {8, 64, 8},
+};
+
+int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+Variant variant_at(int i) { return kVariants[i]; }
+
+bool variant_supported(int dtype, const Variant& v) {
+  // FP64 edge 16 does not fit the 160 KB LDS.
+  return !(dtype == 2 && v.edge == 16);
+}
+
+template <typename T, int N, int NT, int PAD>
+static hipError_t launch_b(int order, bool fuse, const KParams& kp, hipStream_t s) {
+  const dim3 grid(kp.nblocks), block(NT);
+  if (order == 0) {
+    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, true>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, false>), grid, block, 0, s, kp);
+  } else {
+    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, true>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, false>), grid, block, 0, s, kp);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_typed(int order, const Variant& v, bool fuse, const KParams& kp,
+                               hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {  // FP64 edge 16 does not fit in LDS
+    if (v.edge == 16 && v.threads == 512 && v.pad == 16) return launch_b<T, 16, 512, 16>(order, fuse, kp, s);
+    if (v.edge == 16 && v.threads == 512 && v.pad == 0) return launch_b<T, 16, 512, 0>(order, fuse, kp, s);
+  }
+  if (v.edge == 8 && v.threads == 128 && v.pad == 8) return launch_b<T, 8, 128, 8>(order, fuse, kp, s);
+  if (v.edge == 8 && v.threads == 256 && v.pad == 8) return launch_b<T, 8, 256, 8>(order, fuse, kp, s);
+  if (v.edge == 8 && v.threads == 128 && v.pad == 0) return launch_b<T, 8, 128, 0>(order, fuse, kp, s);
+  if (v.edge == 8 && v.threads == 64 && v.pad == 8) return launch_b<T, 8, 64, 8>(order, fuse, kp, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, const KParams& kp,
+                          hipStream_t s) {
+  if (dtype == 1) return launch_typed<float>(order, v, fuse, kp, s);
+  if (v.edge == 16) return hipErrorInvalidValue;
+  return launch_typed<double>(order, v, fuse, kp, s);
+}
+
+hipError_t launch_plain_f64(int order, bool fuse, const KParams& kp, hipStream_t s) {
+  const dim3 grid(kp.nblocks), block(kPlainNT);
+  if (order == 0) {
+    if (fuse) hipLaunchKernelGGL((k_plain_f64<0, true>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_plain_f64<0, false>), grid, block, 0, s, kp);
+  } else {
+    if (fuse) hipLaunchKernelGGL((k_plain_f64<1, true>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_plain_f64<1, false>), grid, block, 0, s, kp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_signal_speed(int dtype, int layout, const KParams& kp, hipStream_t s) {
+  if (dtype == 1) hipLaunchKernelGGL((k_block_diag<float, true>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
+  else hipLaunchKernelGGL((k_block_diag<double, true>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
+  return hipGetLastError();
+}
+
+hipError_t launch_cons_sums(int dtype, int layout, const KParams& kp, hipStream_t s) {
+  if (dtype == 1) hipLaunchKernelGGL((k_block_diag<float, false>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
+  else hipLaunchKernelGGL((k_block_diag<double, false>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_max(const double* ws, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_max, dim3(1), dim3(kFinNT), 0, s, ws, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_sums(const double* ws, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_sums, dim3(1), dim3(kFinNT), 0, s, ws, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_from_speed(const KParams& kp, const double* smax, double cfl, double* dt_out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_from_speed, dim3((kp.nblocks + 255) / 256), dim3(256), 0, s, kp, smax,
+                     cfl, dt_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_ghosts(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
+                              hipStream_t s) {
+  const int m = max_edge + 2 * kG;
+  const int chunks = (m * m * m + kFillNT - 1) / kFillNT;
+  const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
+  if (dtype == 1) hipLaunchKernelGGL((k_fill_ghosts<float>), grid, block, 0, s, kp, nbr, chunks);
+  else hipLaunchKernelGGL((k_fill_ghosts<double>), grid, block, 0, s, kp, nbr, chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace tvd

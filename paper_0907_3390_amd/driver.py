@@ -1,0 +1,110 @@
+"""Device-resident step sequencing over a set of blocks.
+
+Each step runs entirely in libtvd kernels on one stream, with no host round
+trip: before every even step the time step comes from the Eq. (CFL) signal
+speed of the current state (kept in device memory), the ghost zones are
+refilled from sibling interiors, and the state is advanced by one triple,
+forward xyz on even steps and backward zyx on odd steps, the pair sharing
+one dt (Sec. 2.2).  The signal speed of an odd step's output is fused into
+that step's advance, and the conservation sums can be fused into any step.
+torch only provides the device buffers and the stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import tvd
+from .layout import BlockSet
+
+
+class DeviceBlocks:
+    """Interior and ghosted buffers, tables and per-block dt/dh on one GPU."""
+
+    def __init__(self, ctx: tvd.Context, bs: BlockSet, dtype=torch.float32,
+                 device="cuda:0", gamma: float = 5.0 / 3.0, p_floor: float = 0.0,
+                 cfl: float = 0.5, kernel: int = tvd.TVD_KERNEL_AUTO):
+        self.ctx = ctx
+        self.bs = bs
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.gamma = gamma
+        self.p_floor = p_floor
+        self.cfl = cfl
+        self.kernel = kernel
+        dev = self.device
+        self.interior = torch.zeros(bs.out_total, dtype=dtype, device=dev)
+        self.ghosted = torch.zeros(bs.in_total, dtype=dtype, device=dev)
+        self.nbr = torch.from_numpy(bs.nbr).to(dev)
+        self.dh = torch.from_numpy(bs.dh).to(dev)
+        self.dt = torch.zeros(bs.n_blocks, dtype=torch.float64, device=dev)
+        self.smax = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.sums = torch.zeros(5, dtype=torch.float64, device=dev)
+        uniform = bs.uniform_edge
+        code = tvd.dtype_code(dtype)
+        if uniform is not None:
+            # dense packing, no offset tables
+            self.batch = tvd.Batch(code, bs.n_blocks, uniform, d_dt=self.dt, d_dh=self.dh)
+            self.batch_const = tvd.Batch(code, bs.n_blocks, uniform, d_dh=self.dh)
+        else:
+            self.edges = torch.from_numpy(bs.edges).to(dev)
+            self.in_off = torch.from_numpy(bs.in_off).to(dev)
+            self.out_off = torch.from_numpy(bs.out_off).to(dev)
+            self.batch = tvd.Batch(code, bs.n_blocks, 0, d_edge=self.edges, d_in_off=self.in_off,
+                                   d_out_off=self.out_off, d_dt=self.dt, d_dh=self.dh)
+            self.batch_const = self.batch
+        ctx.tvd_reserve(bs.n_blocks)
+        self.step_index = 0
+
+    # -- data movement (host <-> device), not part of a step ----------------
+    def upload(self, blocks):
+        flat = self.bs.pack_interior(blocks)
+        self.interior.copy_(torch.from_numpy(flat).to(self.dtype))
+
+    def download(self) -> list:
+        return self.bs.unpack_interior(self.interior.cpu().numpy())
+
+    # -- the step ---------------------------------------------------------------
+    def signal_speed(self):
+        self.ctx.tvd_max_signal_speed(self.batch, self.interior, tvd.TVD_LAYOUT_INTERIOR,
+                                      self.gamma, self.smax, self.p_floor)
+
+    def set_dt_from_speed(self):
+        self.ctx.tvd_dt_from_speed(self.batch, self.smax, self.cfl, self.dt)
+
+    def fill_ghosts(self):
+        self.ctx.tvd_fill_ghosts(self.batch, self.nbr, self.interior, self.ghosted)
+
+    def advance(self, order: int, fuse_speed: bool = False, fuse_sums: bool = False):
+        self.ctx.tvd_patch_advance(self.batch, self.ghosted, self.interior, order, self.gamma,
+                                   self.p_floor, self.kernel,
+                                   smax=self.smax if fuse_speed else None,
+                                   sums=self.sums if fuse_sums else None)
+
+    def step(self, fused: bool = True, sums: bool = False):
+        """One step; even steps take a fresh dt, odd steps reuse it."""
+        s = self.step_index
+        if s % 2 == 0:
+            if not (fused and s > 0):
+                self.signal_speed()
+            self.set_dt_from_speed()
+        self.fill_ghosts()
+        self.advance(s % 2, fuse_speed=fused and s % 2 == 1, fuse_sums=sums)
+        self.step_index += 1
+
+    def run(self, steps: int, fused: bool = True, sums_each_step: bool = False):
+        """Run steps; returns the per-step sums (device tensor) if requested."""
+        rec = torch.zeros((steps, 5), dtype=torch.float64, device=self.device) if sums_each_step else None
+        for i in range(steps):
+            self.step(fused=fused, sums=sums_each_step)
+            if rec is not None:
+                rec[i].copy_(self.sums)
+        return rec
+
+    def conservation_sums(self):
+        self.ctx.tvd_conservation_sums(self.batch, self.interior, tvd.TVD_LAYOUT_INTERIOR, self.sums)
+        return self.sums
+
+
+def timed_dt_host(dev: DeviceBlocks) -> np.ndarray:
+    return dev.dt.cpu().numpy()

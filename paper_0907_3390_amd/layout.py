@@ -1,0 +1,140 @@
+"""Host-side block bookkeeping: block grids, neighbour tables, offsets.
+
+Pure integer bookkeeping and array reshapes (no arithmetic of the scheme):
+a periodic domain, or a set of independent periodic boxes, is cut into cubic
+blocks of edge 8 or 16 (one 8^3 patch, or a 2^3 patch group as in the
+paper's Sec. 3.1); every block gets the 27-entry table of the blocks that
+cover its neighbourhood, which the device ghost fill reads.  Blocks are
+numbered x fastest, then y, then z, box after box.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NVAR = 5
+GHOST = 3
+
+
+def periodic_neighbors(nbx: int, nby: int, nbz: int, base: int = 0) -> np.ndarray:
+    """[nb, 27] int32 table for an nbx x nby x nbz periodic block grid.
+    Entry r = (rx+1) + 3(ry+1) + 9(rz+1) names the block at offset (rx, ry, rz)."""
+    bx, by, bz = np.meshgrid(np.arange(nbx), np.arange(nby), np.arange(nbz), indexing="ij")
+    bx, by, bz = bx.transpose(2, 1, 0).ravel(), by.transpose(2, 1, 0).ravel(), bz.transpose(2, 1, 0).ravel()
+    nb = nbx * nby * nbz
+    out = np.empty((nb, 27), dtype=np.int32)
+    for rz in (-1, 0, 1):
+        for ry in (-1, 0, 1):
+            for rx in (-1, 0, 1):
+                r = (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)
+                out[:, r] = base + ((bx + rx) % nbx) + nbx * (((by + ry) % nby) + nby * ((bz + rz) % nbz))
+    return out
+
+
+def grid_to_blocks(grid: np.ndarray, n: int) -> np.ndarray:
+    """(5, Nz, Ny, Nx) -> (B, 5, n, n, n) interiors, blocks x fastest."""
+    _, Nz, Ny, Nx = grid.shape
+    nbz, nby, nbx = Nz // n, Ny // n, Nx // n
+    if nbz * n != Nz or nby * n != Ny or nbx * n != Nx:
+        raise ValueError("grid extents must be multiples of the block edge")
+    g = grid.reshape(NVAR, nbz, n, nby, n, nbx, n)
+    return np.ascontiguousarray(g.transpose(1, 3, 5, 0, 2, 4, 6).reshape(nbz * nby * nbx, NVAR, n, n, n))
+
+
+def blocks_to_grid(blocks: np.ndarray, shape) -> np.ndarray:
+    """(B, 5, n, n, n) -> (5, Nz, Ny, Nx), the inverse of grid_to_blocks."""
+    _, Nz, Ny, Nx = shape
+    n = blocks.shape[2]
+    nbz, nby, nbx = Nz // n, Ny // n, Nx // n
+    g = blocks.reshape(nbz, nby, nbx, NVAR, n, n, n).transpose(3, 0, 4, 1, 5, 2, 6)
+    return np.ascontiguousarray(g.reshape(NVAR, Nz, Ny, Nx))
+
+
+class BlockSet:
+    """Layout of a ragged set of blocks: edges, offsets, zone sizes, neighbours.
+
+    ``in_off`` and ``out_off`` are element offsets of each block's ghosted
+    (5 (e+6)^3) and interior (5 e^3) data in two flat buffers, blocks packed
+    in order.  ``dh`` is the zone size of each block.
+    """
+
+    def __init__(self, edges, dh, nbr):
+        self.edges = np.asarray(edges, dtype=np.int32)
+        self.dh = np.asarray(dh, dtype=np.float64)
+        self.nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        n = self.edges.astype(np.int64)
+        in_sizes = NVAR * (n + 2 * GHOST) ** 3
+        out_sizes = NVAR * n ** 3
+        self.in_off = np.concatenate([[0], np.cumsum(in_sizes)[:-1]]).astype(np.int64)
+        self.out_off = np.concatenate([[0], np.cumsum(out_sizes)[:-1]]).astype(np.int64)
+        self.in_total = int(in_sizes.sum())
+        self.out_total = int(out_sizes.sum())
+
+    @property
+    def n_blocks(self) -> int:
+        return int(self.edges.size)
+
+    @property
+    def uniform_edge(self):
+        e = np.unique(self.edges)
+        return int(e[0]) if e.size == 1 else None
+
+    @property
+    def cells(self) -> int:
+        return int((self.edges.astype(np.int64) ** 3).sum())
+
+    def pack_interior(self, blocks) -> np.ndarray:
+        """List of (5, e, e, e) interiors -> flat buffer."""
+        return np.concatenate([np.ascontiguousarray(b).ravel() for b in blocks])
+
+    def unpack_interior(self, flat) -> list:
+        out = []
+        for b in range(self.n_blocks):
+            e = int(self.edges[b])
+            o = int(self.out_off[b])
+            out.append(flat[o:o + NVAR * e ** 3].reshape(NVAR, e, e, e))
+        return out
+
+
+def periodic_grid_blockset(N, n: int, dh: float | None = None) -> BlockSet:
+    """A periodic box of N^3 (or (Nz, Ny, Nx)) cells cut into n^3 blocks."""
+    Nz, Ny, Nx = (N, N, N) if np.isscalar(N) else N
+    nbx, nby, nbz = Nx // n, Ny // n, Nz // n
+    nbr = periodic_neighbors(nbx, nby, nbz)
+    nb = nbx * nby * nbz
+    return BlockSet(np.full(nb, n), np.full(nb, 1.0 / Nx if dh is None else dh), nbr)
+
+
+def boxes_blockset(box_edges, block_edge_for, dhs) -> BlockSet:
+    """Independent periodic boxes; box i of edge L_i is cut into blocks of
+    edge block_edge_for(L_i), each box periodic on itself."""
+    edges, dh, nbrs = [], [], []
+    base = 0
+    for L, h in zip(box_edges, dhs):
+        e = block_edge_for(int(L))
+        k = int(L) // e
+        nbrs.append(periodic_neighbors(k, k, k, base))
+        edges += [e] * k ** 3
+        dh += [h] * k ** 3
+        base += k ** 3
+    return BlockSet(edges, dh, np.concatenate(nbrs))
+
+
+def boxes_to_blocks(grids, block_edge_for) -> list:
+    """Interiors of every box cut into blocks, in BlockSet order."""
+    out = []
+    for g in grids:
+        L = g.shape[1]
+        e = block_edge_for(L)
+        out += list(grid_to_blocks(g, e))
+    return out
+
+
+def blocks_to_boxes(blocks, box_edges, block_edge_for) -> list:
+    out = []
+    i = 0
+    for L in box_edges:
+        e = block_edge_for(int(L))
+        k = int(L) // e
+        out.append(blocks_to_grid(np.stack(blocks[i:i + k ** 3]), (NVAR, L, L, L)))
+        i += k ** 3
+    return out

@@ -1,0 +1,212 @@
+"""Thin ctypes binding of libtvd (C ABI in ``include/tvd.h``).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of ``libtvd.so``.  torch tensors supply device memory and streams;
+their ``data_ptr()`` and the current HIP stream are passed through.  The
+library is loaded on first use; if it has not been built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libtvd.so")
+
+TVD_OK = 0
+TVD_WARN_FLOORED = 1
+TVD_ERR_INVALID_ARG = -1
+TVD_ERR_UNSUPPORTED = -2
+TVD_ERR_HIP = -3
+TVD_ERR_NONPHYSICAL = -4
+TVD_ERR_ALIAS = -5
+TVD_ERR_STATE = -6
+TVD_F32 = 1
+TVD_F64 = 2
+TVD_XYZ = 0
+TVD_ZYX = 1
+TVD_LAYOUT_GHOSTED = 0
+TVD_LAYOUT_INTERIOR = 1
+TVD_KERNEL_AUTO = 0
+TVD_KERNEL_BATCHED = 1
+TVD_KERNEL_PLAIN = 2
+
+EXPORTS = [
+    "tvd_create", "tvd_destroy", "tvd_status_string", "tvd_last_error", "tvd_reserve",
+    "tvd_patch_advance", "tvd_max_signal_speed", "tvd_dt_from_speed",
+    "tvd_conservation_sums", "tvd_read_flags", "tvd_fill_ghosts",
+]
+
+
+class TvdError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"libtvd status {status}: {text}")
+        self.status = status
+
+
+class tvd_batch(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
+                ("edge", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("d_edge", ctypes.c_void_p), ("d_in_off", ctypes.c_void_p),
+                ("d_out_off", ctypes.c_void_p), ("d_dt", ctypes.c_void_p),
+                ("d_dh", ctypes.c_void_p), ("dt", ctypes.c_double), ("dh", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtvd.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_0907_3390_amd.build` "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    bp = ctypes.POINTER(tvd_batch)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "tvd_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int]),
+        "tvd_destroy": (ctypes.c_int, [vp]),
+        "tvd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "tvd_last_error": (ctypes.c_char_p, [vp]),
+        "tvd_reserve": (ctypes.c_int, [vp, ctypes.c_int]),
+        "tvd_patch_advance": (ctypes.c_int, [vp, bp, vp, vp, i32, dbl, dbl, i32, vp, vp, vp]),
+        "tvd_max_signal_speed": (ctypes.c_int, [vp, bp, vp, i32, dbl, dbl, vp, vp]),
+        "tvd_dt_from_speed": (ctypes.c_int, [vp, bp, vp, dbl, vp, vp]),
+        "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
+        "tvd_read_flags": (ctypes.c_int, [vp, i64p, i64p, vp]),
+        "tvd_fill_ghosts": (ctypes.c_int, [vp, bp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().tvd_status_string(status).decode()
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Batch:
+    """A tvd_batch plus the device arrays it points to (kept alive here)."""
+
+    def __init__(self, dtype: int, n_blocks: int, edge: int = 8, dt: float = 0.0,
+                 dh: float = 1.0, d_edge=None, d_in_off=None, d_out_off=None,
+                 d_dt=None, d_dh=None):
+        self.arrays = (d_edge, d_in_off, d_out_off, d_dt, d_dh)
+        self.c = tvd_batch(dtype, n_blocks, edge if d_edge is None else 0, 0,
+                           _ptr(d_edge), _ptr(d_in_off), _ptr(d_out_off), _ptr(d_dt),
+                           _ptr(d_dh), dt, dh)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+class Context:
+    """Owns a tvd_ctx; methods carry the C entry points' names and arguments."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        st = lib.tvd_create(ctypes.byref(h), device)
+        if st != TVD_OK:
+            raise TvdError(st, "tvd_create failed: " + status_string(st))
+        self.h = h
+        self.lib = lib
+
+    def close(self):
+        if self.h:
+            self.lib.tvd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, allow_warn: bool = False):
+        if st == TVD_OK or (allow_warn and st > 0):
+            return st
+        raise TvdError(st, self.lib.tvd_last_error(self.h).decode() or status_string(st))
+
+    def last_error(self) -> str:
+        return self.lib.tvd_last_error(self.h).decode()
+
+    def tvd_reserve(self, n_blocks: int):
+        return self._check(self.lib.tvd_reserve(self.h, n_blocks))
+
+    def tvd_patch_advance(self, batch: Batch, u_in, u_out, sweep_order: int, gamma: float,
+                          p_floor: float = 0.0, flags: int = TVD_KERNEL_AUTO, smax=None,
+                          sums=None, stream=None, check: bool = True):
+        st = self.lib.tvd_patch_advance(self.h, batch.ref, _ptr(u_in), _ptr(u_out),
+                                        sweep_order, gamma, p_floor, flags, _ptr(smax),
+                                        _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_max_signal_speed(self, batch: Batch, u, layout: int, gamma: float, smax,
+                             p_floor: float = 0.0, stream=None):
+        return self._check(self.lib.tvd_max_signal_speed(
+            self.h, batch.ref, _ptr(u), layout, gamma, p_floor, _ptr(smax), _stream(stream)))
+
+    def tvd_dt_from_speed(self, batch: Batch, smax, cfl: float, dt_out, stream=None):
+        return self._check(self.lib.tvd_dt_from_speed(
+            self.h, batch.ref, _ptr(smax), cfl, _ptr(dt_out), _stream(stream)))
+
+    def tvd_conservation_sums(self, batch: Batch, u, layout: int, sums, stream=None):
+        return self._check(self.lib.tvd_conservation_sums(
+            self.h, batch.ref, _ptr(u), layout, _ptr(sums), _stream(stream)))
+
+    def tvd_read_flags(self, stream=None):
+        a = ctypes.c_int64(0)
+        b = ctypes.c_int64(0)
+        st = self.lib.tvd_read_flags(self.h, ctypes.byref(a), ctypes.byref(b), _stream(stream))
+        if st < 0 and st != TVD_ERR_NONPHYSICAL:
+            self._check(st)
+        return st, a.value, b.value
+
+    def tvd_fill_ghosts(self, batch: Batch, nbr, interior, ghosted, stream=None):
+        return self._check(self.lib.tvd_fill_ghosts(
+            self.h, batch.ref, _ptr(nbr), _ptr(interior), _ptr(ghosted), _stream(stream)))
+
+
+def exported_symbols(path: str = LIB_PATH):
+    """Names from EXPORTS that the built library exports (no device needed)."""
+    lib = ctypes.CDLL(path)
+    return [n for n in EXPORTS if hasattr(lib, n)]
+
+
+def dtype_code(torch_dtype) -> int:
+    import torch
+    if torch_dtype == torch.float32:
+        return TVD_F32
+    if torch_dtype == torch.float64:
+        return TVD_F64
+    raise ValueError("state tensors must be float32 or float64")
+
+
+def as_numpy(t) -> np.ndarray:
+    return t.detach().cpu().numpy()

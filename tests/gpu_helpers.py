@@ -1,0 +1,53 @@
+"""Shared glue for the GPU tests: error norms and oracle reference runs.
+
+The norms follow the parity definitions: relative L1 over the sum of |b| for
+density and energy, and for each momentum component the L1 difference over
+the sum of rho * c_s of the reference (the natural momentum scale), with the
+own-norm reported too.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+
+GAMMA = 5.0 / 3.0
+
+
+def note(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def norms(a, b, gamma=GAMMA):
+    """Per-variable error norms of a against reference b, both (5, ...)."""
+    a = np.asarray(a, dtype=np.float64).reshape(5, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(5, -1)
+    rho = b[0]
+    kin = 0.5 * (b[1] ** 2 + b[2] ** 2 + b[3] ** 2) / rho
+    P = np.maximum((gamma - 1.0) * (b[4] - kin), 0.0)
+    cs = np.sqrt(gamma * P / rho)
+    scale = np.sum(rho * cs)
+    out = {}
+    names = ["rho", "m_x", "m_y", "m_z", "e"]
+    for k, nm in enumerate(names):
+        d = np.abs(a[k] - b[k])
+        own = np.sum(np.abs(b[k]))
+        out[nm] = {
+            "relL1": d.sum() / (own if k in (0, 4) else max(scale, 1e-300)),
+            "relL1_own": d.sum() / max(own, 1e-300),
+            "relLinf": d.max() / max(np.abs(b[k]).max(), 1e-300),
+        }
+    return out
+
+
+def worst(nrm, key="relL1"):
+    return max(v[key] for v in nrm.values())
+
+
+def oracle_periodic(grid, steps, n=8, cfl=0.5, gamma=GAMMA, p_floor=0.0):
+    N = grid.shape[3]
+    return oracle.run_periodic(np.asarray(grid, dtype=np.float64), steps, cfl, 1.0 / N, gamma,
+                               n=n, p_floor=p_floor)

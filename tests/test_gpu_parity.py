@@ -1,0 +1,334 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (per variable, norms defined in gpu_helpers.norms):
+* FP64 GPU (plain and batched kernels): relative L1 <= 1e-12 against the
+  oracle after the stated number of steps (round-off of the same FP64
+  arithmetic in a different order; the scheme is Lipschitz, so differences
+  stay near 1e-15).
+* FP32 GPU on smooth data: relative L1 <= 1e-5 after 10 steps against the
+  oracle run from the same FP32-rounded initial state.
+* Pure copies (ghost fill) and exact invariants (uniform state) are
+  bit-exact; sums of dyadic data are exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import GAMMA, norms, note, oracle_periodic, worst
+from paper_0907_3390_amd import layout, tvd, workloads as wl
+from paper_0907_3390_amd.driver import DeviceBlocks
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    c = tvd.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu_periodic(ctx, grid, steps, n, dtype, kernel=tvd.TVD_KERNEL_AUTO, fused=True,
+                     p_floor=0.0, gamma=GAMMA):
+    N = grid.shape[3]
+    bs = layout.periodic_grid_blockset(N, n)
+    dev = DeviceBlocks(ctx, bs, dtype=dtype, gamma=gamma, p_floor=p_floor, kernel=kernel)
+    dev.upload(layout.grid_to_blocks(grid, n))
+    dev.run(steps, fused=fused)
+    torch.cuda.synchronize()
+    out = layout.blocks_to_grid(np.stack(dev.download()), grid.shape)
+    return out, dev
+
+
+# ---------------------------------------------------------------------------
+# exact invariants
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,kernel,n", [
+    (torch.float32, tvd.TVD_KERNEL_BATCHED, 8), (torch.float32, tvd.TVD_KERNEL_BATCHED, 16),
+    (torch.float64, tvd.TVD_KERNEL_BATCHED, 8), (torch.float64, tvd.TVD_KERNEL_PLAIN, 8)])
+def test_uniform_state_bitwise(ctx, dtype, kernel, n):
+    note(f"uniform state dtype={dtype} kernel={kernel} n={n}")
+    g = wl.uniform(32, rho=1.3, v=(0.2, -0.4, 0.1), P=0.8)
+    g = g.astype(np.float32).astype(np.float64) if dtype == torch.float32 else g
+    out, dev = run_gpu_periodic(ctx, g, 4, n, dtype, kernel)
+    assert np.array_equal(out, g)
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_OK and fl == 0 and bad == 0
+
+
+def test_fill_ghosts_bitwise(ctx):
+    note("ghost fill vs periodic copy, n=8 and 16, FP64")
+    g = wl.lognormal(32, seed=21)
+    for n in (8, 16):
+        bs = layout.periodic_grid_blockset(32, n)
+        dev = DeviceBlocks(ctx, bs, dtype=torch.float64)
+        dev.upload(layout.grid_to_blocks(g, n))
+        dev.fill_ghosts()
+        torch.cuda.synchronize()
+        m = n + 6
+        got = dev.ghosted.cpu().numpy().reshape(bs.n_blocks, 5, m, m, m)
+        want = oracle.periodic_ghosted_blocks(g, n)
+        assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# FP64 parity (<= 1e-12)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel", [tvd.TVD_KERNEL_PLAIN, tvd.TVD_KERNEL_BATCHED])
+def test_sod_32cube_fp64(ctx, kernel):
+    """Sod tube along x on a periodic 32^3 grid as 64 patches of 8^3, 10 steps
+    at CFL 0.5 (the paper's Sec. 4.2 states)."""
+    note(f"sod 32^3 fp64 kernel={kernel}")
+    g = wl.sod_x(32)
+    ref, dts = oracle_periodic(g, 10, n=8)
+    out, dev = run_gpu_periodic(ctx, g, 10, 8, torch.float64, kernel)
+    nrm = norms(out, ref)
+    note(str({k: v["relL1"] for k, v in nrm.items()}))
+    assert worst(nrm) <= 1e-12
+    np.testing.assert_allclose(dev.dt.cpu().numpy(), dts[-1], rtol=1e-14)
+
+
+@pytest.mark.parametrize("kernel", [tvd.TVD_KERNEL_PLAIN, tvd.TVD_KERNEL_BATCHED])
+def test_lognormal_fp64(ctx, kernel):
+    """Rough lognormal density (sigma_ln = 1) with Gaussian velocities, 32^3,
+    6 steps: the shape of the 256^3 throughput workload at a size the oracle
+    runs in seconds."""
+    note(f"lognormal 32^3 fp64 kernel={kernel}")
+    g = wl.lognormal(32, seed=7)
+    ref, _ = oracle_periodic(g, 6, n=8)
+    out, _ = run_gpu_periodic(ctx, g, 6, 8, torch.float64, kernel)
+    nrm = norms(out, ref)
+    note(str({k: v["relL1"] for k, v in nrm.items()}))
+    assert worst(nrm) <= 1e-12
+
+
+def test_plain_equals_batched_fp64(ctx):
+    note("plain vs batched fp64 (both against the oracle, and each other)")
+    g = wl.smooth_random(16, seed=3, amplitude=0.4)
+    a, _ = run_gpu_periodic(ctx, g, 4, 8, torch.float64, tvd.TVD_KERNEL_PLAIN)
+    b, _ = run_gpu_periodic(ctx, g, 4, 8, torch.float64, tvd.TVD_KERNEL_BATCHED)
+    assert worst(norms(a, b)) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# FP32 parity (<= 1e-5 on smooth data after 10 steps)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_smooth_fp32(ctx, n):
+    note(f"smooth 32^3 fp32 n={n}")
+    g = wl.smooth_random(32, seed=9, amplitude=0.1, vel=0.1)
+    g = g.astype(np.float32).astype(np.float64)
+    ref, _ = oracle_periodic(g, 10, n=8)
+    out, _ = run_gpu_periodic(ctx, g, 10, n, torch.float32)
+    nrm = norms(out, ref)
+    note(str({k: (v["relL1"], v["relL1_own"]) for k, v in nrm.items()}))
+    assert worst(nrm) <= 1e-5
+
+
+def test_uneven_boxes_fp32(ctx):
+    """Independent periodic boxes of 8^3, 16^3 and 32^3 (4:2:1) with sound
+    waves of amplitude 1e-3, one mixed-edge batch (8^3 boxes as edge-8
+    blocks, the others as edge-16 blocks), per-block dh, 10 steps."""
+    note("uneven boxes fp32 mixed edges")
+    boxes = wl.sound_wave_boxes(counts=(8, 4, 2), seed=4)
+    grids = [b.astype(np.float32).astype(np.float64) for b in boxes.grids]
+    edges = [g.shape[1] for g in grids]
+    efor = lambda L: 8 if L == 8 else 16
+    bs = layout.boxes_blockset(edges, efor, boxes.dh)
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float32)
+    dev.upload(layout.boxes_to_blocks(grids, efor))
+    dev.run(10)
+    torch.cuda.synchronize()
+    got = layout.blocks_to_boxes(dev.download(), edges, efor)
+    # oracle: every box on its own, with the global dt rule dt_b = C dh_b / S
+    # (S over all boxes), evaluated before even steps
+    state = [g.copy() for g in grids]
+    for s in range(10):
+        if s % 2 == 0:
+            S = max(oracle.max_signal_speed(g, GAMMA) for g in state)
+        state = [oracle.step_periodic(g, 8, s % 2, 0.5 * h / S, h, GAMMA)
+                 for g, h in zip(state, boxes.dh)]
+    a = np.concatenate([x.reshape(5, -1) for x in got], axis=1)
+    b = np.concatenate([x.reshape(5, -1) for x in state], axis=1)
+    nrm = norms(a, b)
+    note(str({k: (v["relL1"], v["relL1_own"]) for k, v in nrm.items()}))
+    assert worst(nrm) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# CFL speed, dt and sums
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_signal_speed_and_dt(ctx, dtype):
+    note(f"signal speed dtype={dtype}")
+    g = wl.lognormal(32, seed=5)
+    g = g.astype(np.float32).astype(np.float64) if dtype == torch.float32 else g
+    bs = layout.periodic_grid_blockset(32, 8)
+    dev = DeviceBlocks(ctx, bs, dtype=dtype)
+    dev.upload(layout.grid_to_blocks(g, 8))
+    dev.signal_speed()
+    dev.set_dt_from_speed()
+    torch.cuda.synchronize()
+    S = oracle.max_signal_speed(g, GAMMA)
+    assert dev.smax.item() == pytest.approx(S, rel=2e-15)
+    np.testing.assert_allclose(dev.dt.cpu().numpy(), 0.5 / 32 / S, rtol=4e-15)
+
+
+def test_conservation_sums_exact_on_dyadic_data(ctx):
+    note("conservation sums on dyadic data")
+    r = wl.rng(8)
+    g = r.integers(-2 ** 16, 2 ** 16, size=(5, 32, 32, 32)).astype(np.float64) * 2.0 ** -10
+    g[0] = np.abs(g[0]) + 1.0
+    bs = layout.periodic_grid_blockset(32, 8)
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float64)
+    dev.upload(layout.grid_to_blocks(g, 8))
+    sums = dev.conservation_sums().cpu().numpy()
+    w = (1.0 / 32) ** 3
+    for k in range(5):
+        assert sums[k] == math.fsum((g[k] * w).ravel())
+
+
+def test_fused_diagnostics_match_standalone(ctx):
+    note("fused speed/sums vs standalone kernels")
+    g = wl.lognormal(32, seed=12, sigma_ln=0.5)
+    for dtype, n in [(torch.float32, 16), (torch.float32, 8), (torch.float64, 8)]:
+        bs = layout.periodic_grid_blockset(32, n)
+        dev = DeviceBlocks(ctx, bs, dtype=dtype)
+        dev.upload(layout.grid_to_blocks(g, n))
+        dev.signal_speed()
+        dev.set_dt_from_speed()
+        dev.fill_ghosts()
+        dev.advance(0, fuse_speed=True, fuse_sums=True)
+        torch.cuda.synchronize()
+        s_fused, sums_fused = dev.smax.item(), dev.sums.cpu().numpy().copy()
+        dev.signal_speed()
+        sums = dev.conservation_sums().cpu().numpy()
+        assert dev.smax.item() == s_fused
+        np.testing.assert_allclose(sums_fused, sums, rtol=1e-14, atol=1e-300)
+        # and the sums equal the exactly rounded sums of the stored state
+        out = np.stack(dev.download()).astype(np.float64)
+        w = (1.0 / 32) ** 3
+        for k in range(5):
+            exact = math.fsum(out[:, k].ravel()) * w
+            assert abs(sums[k] - exact) <= 1e-14 * abs(exact) + 1e-300
+
+
+def test_conservation_over_steps_fp64(ctx):
+    note("conservation over 10 steps, fp64 batched")
+    g = wl.lognormal(32, seed=13)
+    bs = layout.periodic_grid_blockset(32, 8)
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float64)
+    dev.upload(layout.grid_to_blocks(g, 8))
+    rec = dev.run(10, sums_each_step=True).cpu().numpy()
+    w = (1.0 / 32) ** 3
+    s0 = np.array([math.fsum((g[k] * w).ravel()) for k in range(5)])
+    scale = np.array([np.abs(g[k]).sum() * w for k in range(5)])
+    assert np.all(np.abs(rec - s0) <= 1e-13 * scale)
+
+
+# ---------------------------------------------------------------------------
+# graph capture, flags, argument errors, empty batch
+# ---------------------------------------------------------------------------
+
+def test_graph_replay_matches_eager(ctx):
+    """A two-step sequence captured into a HIP graph (through torch's graph
+    wrapper) and replayed three times, with eager work in between, equals
+    the eager sequence bit for bit after every replay."""
+    note("graph capture of a 2-step sequence")
+    g = wl.smooth_random(32, seed=14, amplitude=0.2).astype(np.float32).astype(np.float64)
+    bs = layout.periodic_grid_blockset(32, 16)
+    eager = DeviceBlocks(ctx, bs, dtype=torch.float32)
+    graph = DeviceBlocks(ctx, bs, dtype=torch.float32)
+    eager.upload(layout.grid_to_blocks(g, 16))
+    graph.upload(layout.grid_to_blocks(g, 16))
+    # warm up the graph instance's first (even) step eagerly so that the
+    # captured pair starts with a fused speed available
+    for d in (eager, graph):
+        d.run(2)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg, stream=s):
+        graph.step()
+        graph.step()
+    torch.cuda.synchronize()
+    graph.step_index -= 2  # capture does not run the work
+    for rep in range(3):
+        eager.run(2)
+        torch.cuda.synchronize()
+        x = eager.interior.sum()  # eager work between replays
+        cg.replay()
+        graph.step_index += 2
+        torch.cuda.synchronize()
+        assert torch.equal(eager.interior, graph.interior), rep
+        assert torch.equal(eager.dt, graph.dt), rep
+        del x
+
+
+def test_health_flags(ctx):
+    note("health counters")
+    g = wl.uniform(16, rho=1.0, P=1.0)
+    g[0, 4, 4, 4] = -1.0  # one cell with negative density
+    bs = layout.periodic_grid_blockset(16, 8)
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float64)
+    dev.upload(layout.grid_to_blocks(g, 8))
+    ctx.tvd_read_flags()
+    dev.dt.fill_(1e-3)
+    dev.fill_ghosts()
+    dev.advance(0)
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_ERR_NONPHYSICAL and bad > 0
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_OK and bad == 0 and fl == 0  # reset after read
+    # pressure floor: cold cells below the floor are counted, not changed
+    g = wl.uniform(16, rho=1.0, P=1e-12)
+    dev.upload(layout.grid_to_blocks(g, 8))
+    dev.p_floor = 1e-10
+    dev.fill_ghosts()
+    dev.advance(0)
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_WARN_FLOORED and fl == 16 ** 3 and bad == 0
+
+
+def test_argument_errors(ctx):
+    note("argument validation")
+    dev_in = torch.zeros(5 * 14 ** 3, dtype=torch.float64, device="cuda")
+    dev_out = torch.zeros(5 * 8 ** 3, dtype=torch.float64, device="cuda")
+    ok = tvd.Batch(tvd.TVD_F64, 1, 8, dt=1e-3, dh=1.0)
+    E = tvd.TvdError
+    with pytest.raises(E) as e:
+        ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F64, 1, 12, dt=1e-3, dh=1.0), dev_in, dev_out, 0, GAMMA)
+    assert e.value.status == tvd.TVD_ERR_INVALID_ARG
+    with pytest.raises(E) as e:
+        ctx.tvd_patch_advance(ok, dev_in, dev_in, 0, GAMMA)
+    assert e.value.status == tvd.TVD_ERR_ALIAS
+    with pytest.raises(E) as e:
+        ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F64, 1, 16, dt=1e-3, dh=1.0), dev_in, dev_out, 0, GAMMA)
+    assert e.value.status == tvd.TVD_ERR_UNSUPPORTED
+    with pytest.raises(E) as e:
+        ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F32, 1, 8, dt=1e-3, dh=1.0), dev_in, dev_out, 0,
+                              GAMMA, flags=tvd.TVD_KERNEL_PLAIN)
+    assert e.value.status == tvd.TVD_ERR_UNSUPPORTED
+    for bad_gamma in (0.5, float("nan")):
+        with pytest.raises(E) as e:
+            ctx.tvd_patch_advance(ok, dev_in, dev_out, 0, bad_gamma)
+        assert e.value.status == tvd.TVD_ERR_INVALID_ARG
+    with pytest.raises(E) as e:
+        ctx.tvd_patch_advance(ok, dev_in, dev_out, 2, GAMMA)
+    assert e.value.status == tvd.TVD_ERR_INVALID_ARG
+    with pytest.raises(E) as e:
+        ctx.tvd_dt_from_speed(ok, dev_out, 1.5, dev_out)
+    assert e.value.status == tvd.TVD_ERR_INVALID_ARG
+    # empty batch: nothing to do, nothing launched
+    assert ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F64, 0, 8, dt=1e-3, dh=1.0), dev_in, dev_out, 0,
+                                 GAMMA) == tvd.TVD_OK
+    torch.cuda.synchronize()
