@@ -109,6 +109,18 @@ const char *tvd_last_error(const tvd_ctx *ctx);
  * graph: reserve the largest batch before capturing.  Synchronous. */
 int tvd_reserve(tvd_ctx *ctx, int n_blocks);
 
+/* ---- kernel variants (launch shape and LDS layout) ------------------------ */
+
+/* Number of batched-kernel variants compiled into the library. */
+int tvd_variant_count(void);
+/* Describe variant `index`: block edge, workgroup size and the padding of
+ * the LDS rows (layout).  TVD_ERR_INVALID_ARG for an index out of range. */
+int tvd_variant_info(int index, int32_t *edge, int32_t *threads, int32_t *lds_pad);
+/* Select the variant used by TVD_KERNEL_AUTO / TVD_KERNEL_BATCHED for blocks of
+ * (dtype, edge); index -1 restores the built-in default.  A variant of
+ * another edge, or FP64 with edge 16, is TVD_ERR_UNSUPPORTED. */
+int tvd_set_variant(tvd_ctx *ctx, int32_t dtype, int32_t edge, int32_t index);
+
 /* ---- the hot path --------------------------------------------------------- */
 
 /*

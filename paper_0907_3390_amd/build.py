@@ -17,9 +17,12 @@ LIB = os.path.join(HERE, "_lib", "libtvd.so")
 SOURCES = ["tvd_kernels.hip", "tvd_capi.hip"]
 ARCH = "gfx950"
 
-# packed FP32 instructions are turned off for every HIP translation unit
+# packed FP32 instructions are turned off for every HIP translation unit;
+# FMA contraction is off too: the kernels write every fused multiply-add
+# explicitly, so the same expression rounds the same way everywhere
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-ffp-contract=off",
          "-Wall", "-Wno-unused-function"]
 
 

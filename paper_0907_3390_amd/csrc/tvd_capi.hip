@@ -213,6 +213,34 @@ int tvd_reserve(tvd_ctx* ctx, int n_blocks) {
   return reserve(ctx, n_blocks, nullptr);
 }
 
+int tvd_variant_count(void) { return tvd::variant_count(); }
+
+int tvd_variant_info(int index, int32_t* edge, int32_t* threads, int32_t* lds_pad) {
+  if (index < 0 || index >= tvd::variant_count()) return TVD_ERR_INVALID_ARG;
+  const tvd::Variant v = tvd::variant_at(index);
+  if (edge) *edge = v.edge;
+  if (threads) *threads = v.threads;
+  if (lds_pad) *lds_pad = v.pad;
+  return TVD_OK;
+}
+
+int tvd_set_variant(tvd_ctx* ctx, int32_t dtype, int32_t edge, int32_t index) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (dtype != TVD_F32 && dtype != TVD_F64)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "dtype %d", dtype);
+  if (edge != 8 && edge != 16) return fail(ctx, TVD_ERR_INVALID_ARG, "edge %d", edge);
+  if (index < -1 || index >= tvd::variant_count())
+    return fail(ctx, TVD_ERR_INVALID_ARG, "variant index %d", index);
+  if (index >= 0) {
+    const tvd::Variant v = tvd::variant_at(index);
+    if (v.edge != edge || !tvd::variant_supported(dtype == TVD_F32 ? 1 : 2, v))
+      return fail(ctx, TVD_ERR_UNSUPPORTED, "variant %d does not serve dtype %d edge %d", index,
+                  dtype, edge);
+  }
+  ctx->tuned[dtype == TVD_F32 ? 0 : 1][edge == 16 ? 1 : 0] = index;
+  return TVD_OK;
+}
+
 int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
                       int32_t sweep_order, double gamma, double p_floor, int32_t flags,
                       double* d_smax, double* d_sums, void* stream) {
@@ -226,6 +254,13 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
     return fail(ctx, TVD_ERR_INVALID_ARG, "flags %d", flags);
   if (batch->n_blocks == 0) return TVD_OK;
   if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
+  if (flags == TVD_KERNEL_PLAIN) {
+    if (batch->dtype != TVD_F64 || batch->d_edge || batch->edge != 8)
+      return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel needs TVD_F64 and uniform edge 8");
+  }
+  if (batch->dtype == TVD_F64 && (batch->d_edge || batch->edge != 8))
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "FP64 batches take uniform edge 8 (edge 16 exceeds the 160 KB LDS)");
   if (d_u_in == d_u_out) return fail(ctx, TVD_ERR_ALIAS, "d_u_in == d_u_out");
   if (!batch->d_in_off && !batch->d_out_off && !batch->d_edge) {
     const size_t es = elem_size(batch->dtype);
@@ -236,13 +271,6 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
     const size_t lb = (size_t)batch->n_blocks * 5 * n * n * n * es;
     if (a < b + lb && b < a + la) return fail(ctx, TVD_ERR_ALIAS, "input and output overlap");
   }
-  if (flags == TVD_KERNEL_PLAIN) {
-    if (batch->dtype != TVD_F64 || batch->d_edge || batch->edge != 8)
-      return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel needs TVD_F64 and uniform edge 8");
-  }
-  if (batch->dtype == TVD_F64 && (batch->d_edge || batch->edge != 8))
-    return fail(ctx, TVD_ERR_UNSUPPORTED,
-                "FP64 batches take uniform edge 8 (edge 16 exceeds the 160 KB LDS)");
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, TVD_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t s = (hipStream_t)stream;

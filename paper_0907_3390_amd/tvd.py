@@ -37,6 +37,7 @@ EXPORTS = [
     "tvd_create", "tvd_destroy", "tvd_status_string", "tvd_last_error", "tvd_reserve",
     "tvd_patch_advance", "tvd_max_signal_speed", "tvd_dt_from_speed",
     "tvd_conservation_sums", "tvd_read_flags", "tvd_fill_ghosts",
+    "tvd_variant_count", "tvd_variant_info", "tvd_set_variant",
 ]
 
 
@@ -82,6 +83,11 @@ def load(path: str = LIB_PATH):
         "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
         "tvd_read_flags": (ctypes.c_int, [vp, i64p, i64p, vp]),
         "tvd_fill_ghosts": (ctypes.c_int, [vp, bp, vp, vp, vp, vp]),
+        "tvd_variant_count": (ctypes.c_int, []),
+        "tvd_variant_info": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+        "tvd_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -180,6 +186,9 @@ class Context:
         return self._check(self.lib.tvd_conservation_sums(
             self.h, batch.ref, _ptr(u), layout, _ptr(sums), _stream(stream)))
 
+    def tvd_set_variant(self, dtype: int, edge: int, index: int):
+        return self._check(self.lib.tvd_set_variant(self.h, dtype, edge, index))
+
     def tvd_read_flags(self, stream=None):
         a = ctypes.c_int64(0)
         b = ctypes.c_int64(0)
@@ -191,6 +200,17 @@ class Context:
     def tvd_fill_ghosts(self, batch: Batch, nbr, interior, ghosted, stream=None):
         return self._check(self.lib.tvd_fill_ghosts(
             self.h, batch.ref, _ptr(nbr), _ptr(interior), _ptr(ghosted), _stream(stream)))
+
+
+def variants():
+    """[(index, edge, threads, lds_pad)] of the compiled batched-kernel variants."""
+    lib = load()
+    out = []
+    for i in range(lib.tvd_variant_count()):
+        e, t, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        lib.tvd_variant_info(i, ctypes.byref(e), ctypes.byref(t), ctypes.byref(p))
+        out.append((i, e.value, t.value, p.value))
+    return out
 
 
 def exported_symbols(path: str = LIB_PATH):

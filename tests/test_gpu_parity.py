@@ -61,6 +61,55 @@ def test_uniform_state_bitwise(ctx, dtype, kernel, n):
     assert st == tvd.TVD_OK and fl == 0 and bad == 0
 
 
+def _rotate_state(g, perm):
+    arr_axes = [0] + [3 - perm[2 - i] for i in range(3)]
+    out = np.transpose(g, arr_axes).copy()
+    for a in range(3):
+        out[1 + a] = np.transpose(g[1 + perm[a]], [x - 1 for x in arr_axes[1:]])
+    return out
+
+
+@pytest.mark.parametrize("dtype,n", [(torch.float32, 16), (torch.float64, 8)])
+def test_mirror_and_transpose_bitwise(ctx, dtype, n):
+    """The GPU update commutes bit for bit with reflecting an axis (momentum
+    negated) and swapping x with z also swaps the sweep order (explicit FMAs,
+    symmetric transverse terms)."""
+    note(f"mirror/transpose dtype={dtype} n={n}")
+    g = wl.smooth_random(32, seed=15, amplitude=0.3)
+    if dtype == torch.float32:
+        g = g.astype(np.float32).astype(np.float64)
+    base, _ = run_gpu_periodic(ctx, g, 2, n, dtype)
+    for axis in range(3):
+        gm = np.flip(g, axis=3 - axis).copy()
+        gm[1 + axis] *= -1
+        outm, _ = run_gpu_periodic(ctx, gm, 2, n, dtype)
+        back = np.flip(outm, axis=3 - axis).copy()
+        back[1 + axis] *= -1
+        assert np.array_equal(back, base), axis
+    # one forward step on the transposed state == transpose of one backward step
+    bs = layout.periodic_grid_blockset(32, n)
+    res = []
+    for state, order in [(_rotate_state(g, [2, 1, 0]), 0), (g, 1)]:
+        dev = DeviceBlocks(ctx, bs, dtype=dtype)
+        dev.upload(layout.grid_to_blocks(state, n))
+        dev.dt.fill_(0.3 / 32)
+        dev.fill_ghosts()
+        dev.advance(order)
+        torch.cuda.synchronize()
+        res.append(layout.blocks_to_grid(np.stack(dev.download()), g.shape))
+    assert np.array_equal(res[0], _rotate_state(res[1], [2, 1, 0]))
+
+
+def test_edge8_equals_edge16_fp32(ctx):
+    """Decomposition invariance on the GPU: the same periodic grid advanced as
+    8^3 blocks and as 16^3 blocks gives identical FP32 results."""
+    note("edge 8 vs edge 16 fp32")
+    g = wl.lognormal(32, seed=16, sigma_ln=0.7).astype(np.float32).astype(np.float64)
+    a, _ = run_gpu_periodic(ctx, g, 4, 8, torch.float32)
+    b, _ = run_gpu_periodic(ctx, g, 4, 16, torch.float32)
+    assert np.array_equal(a, b)
+
+
 def test_fill_ghosts_bitwise(ctx):
     note("ghost fill vs periodic copy, n=8 and 16, FP64")
     g = wl.lognormal(32, seed=21)
@@ -311,8 +360,10 @@ def test_argument_errors(ctx):
     with pytest.raises(E) as e:
         ctx.tvd_patch_advance(ok, dev_in, dev_in, 0, GAMMA)
     assert e.value.status == tvd.TVD_ERR_ALIAS
+    big_in = torch.zeros(5 * 22 ** 3, dtype=torch.float64, device="cuda")
+    big_out = torch.zeros(5 * 16 ** 3, dtype=torch.float64, device="cuda")
     with pytest.raises(E) as e:
-        ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F64, 1, 16, dt=1e-3, dh=1.0), dev_in, dev_out, 0, GAMMA)
+        ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F64, 1, 16, dt=1e-3, dh=1.0), big_in, big_out, 0, GAMMA)
     assert e.value.status == tvd.TVD_ERR_UNSUPPORTED
     with pytest.raises(E) as e:
         ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F32, 1, 8, dt=1e-3, dh=1.0), dev_in, dev_out, 0,
