@@ -155,6 +155,24 @@ int tvd_patch_advance(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u_in,
                       double *d_sums, void *stream);
 
 /*
+ * The same step with the ghost zones gathered on the fly: d_u_in holds the
+ * blocks' interiors only (5 cubes of e_b^3 each, at the batch's out offsets,
+ * like d_u_out) and the first sweep of every block reads its ghost cells
+ * straight from the interiors of the 26 neighbouring blocks named by
+ * d_nbr[27*b + r] (region r as for tvd_fill_ghosts), which is the sibling
+ * copy of Sec. 2.2 done inside the advance instead of as a separate pass.
+ * Every neighbour must exist (index in [0, n_blocks)) and have the block's
+ * edge; a block for which one does not is not advanced, its output is left
+ * untouched and its e_b^3 cells are counted as non-physical.  d_u_in and
+ * d_u_out must be different buffers (the neighbours' inputs are read while
+ * outputs are written).  TVD_KERNEL_PLAIN is not available here.
+ */
+int tvd_patch_advance_gather(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
+                             const void *d_u_in, void *d_u_out, int32_t sweep_order,
+                             double gamma, double p_floor, int32_t flags, double *d_smax,
+                             double *d_sums, void *stream);
+
+/*
  * Eq. (CFL) signal speed: d_smax[0] = max over the interior cells of all
  * blocks of c_s + max(|v_x|, |v_y|, |v_z|), with c_s from max(P, p_floor);
  * evaluated in FP64 from the stored values.  layout selects ghosted or

@@ -130,6 +130,7 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
   kp.pfloor = pfloor;
   kp.nblocks = b->n_blocks;
   kp.edge = b->d_edge ? 0 : b->edge;
+  kp.nbr = nullptr;
   kp.ws_smax = ctx->ws_smax;
   kp.ws_sums = ctx->ws_sums;
   kp.counters = ctx->counters;
@@ -241,9 +242,15 @@ int tvd_set_variant(tvd_ctx* ctx, int32_t dtype, int32_t edge, int32_t index) {
   return TVD_OK;
 }
 
-int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
-                      int32_t sweep_order, double gamma, double p_floor, int32_t flags,
-                      double* d_smax, double* d_sums, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of tvd_patch_advance (nbr == NULL: ghosted input) and
+// tvd_patch_advance_gather (nbr != NULL: interior input, ghosts gathered).
+int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
+                 int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                 double* d_smax, double* d_sums, void* stream, const int32_t* d_nbr) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   int st = check_batch(ctx, batch);
   if (st) return st;
@@ -255,6 +262,7 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
   if (batch->n_blocks == 0) return TVD_OK;
   if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
   if (flags == TVD_KERNEL_PLAIN) {
+    if (d_nbr) return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel takes ghosted input only");
     if (batch->dtype != TVD_F64 || batch->d_edge || batch->edge != 8)
       return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel needs TVD_F64 and uniform edge 8");
   }
@@ -264,7 +272,7 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
   if (d_u_in == d_u_out) return fail(ctx, TVD_ERR_ALIAS, "d_u_in == d_u_out");
   if (!batch->d_in_off && !batch->d_out_off && !batch->d_edge) {
     const size_t es = elem_size(batch->dtype);
-    const size_t m = batch->edge + 6, n = batch->edge;
+    const size_t m = d_nbr ? batch->edge : batch->edge + 6, n = batch->edge;
     const char* a = (const char*)d_u_in;
     const char* b = (const char*)d_u_out;
     const size_t la = (size_t)batch->n_blocks * 5 * m * m * m * es;
@@ -276,7 +284,9 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
   hipStream_t s = (hipStream_t)stream;
   const bool fuse = d_smax || d_sums;
   if (fuse && (st = reserve(ctx, batch->n_blocks, s))) return st;
-  const tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
+  tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
+  kp.nbr = d_nbr;
+  const bool gather = d_nbr != nullptr;
   hipError_t e;
   if (flags == TVD_KERNEL_PLAIN) {
     e = tvd::launch_plain_f64(sweep_order, fuse, kp, s);
@@ -285,12 +295,12 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
     // one launch per edge; a workgroup whose block has the other edge exits
     for (int edge : {16, 8}) {
       e = tvd::launch_batched(batch->dtype, sweep_order, chosen_variant(ctx, batch->dtype, edge),
-                              fuse, kp, s);
+                              fuse, gather, kp, s);
       if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
     }
   } else {
     e = tvd::launch_batched(batch->dtype, sweep_order,
-                            chosen_variant(ctx, batch->dtype, batch->edge), fuse, kp, s);
+                            chosen_variant(ctx, batch->dtype, batch->edge), fuse, gather, kp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
   }
   if (d_smax) {
@@ -302,6 +312,27 @@ int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, 
     if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
   }
   return TVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
+                      int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                      double* d_smax, double* d_sums, void* stream) {
+  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
+                      d_sums, stream, nullptr);
+}
+
+int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                             const void* d_u_in, void* d_u_out, int32_t sweep_order,
+                             double gamma, double p_floor, int32_t flags, double* d_smax,
+                             double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
+  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
+                      d_sums, stream, d_nbr);
 }
 
 int tvd_max_signal_speed(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, int32_t layout,

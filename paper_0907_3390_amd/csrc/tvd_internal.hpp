@@ -19,6 +19,7 @@ struct KParams {
   double dt, dh, gamma, pfloor;
   int nblocks;
   int edge;                      // uniform edge (0 when d_edge is used)
+  const int32_t* nbr;            // [nblocks][27] neighbour table (gather mode)
   double* ws_smax;               // [nblocks] per-block max signal speed
   double* ws_sums;               // [nblocks][10] per-block (sum, comp) x 5
   unsigned long long* counters;  // [0] floored, [1] non-physical
@@ -32,8 +33,11 @@ struct Variant {
 };
 
 // Launchers.  All return a hipError_t from the launch.
-hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, const KParams& kp,
-                          hipStream_t s);
+// gather = true: the first sweep reads its pencils straight from the
+// interiors of the block and its 26 neighbours (kp.nbr) instead of a
+// ghosted copy; kp.uin then holds interior blocks at the out offsets.
+hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, bool gather,
+                          const KParams& kp, hipStream_t s);
 hipError_t launch_plain_f64(int order, bool fuse, const KParams& kp, hipStream_t s);
 hipError_t launch_signal_speed(int dtype, int layout, const KParams& kp, hipStream_t s);
 hipError_t launch_cons_sums(int dtype, int layout, const KParams& kp, hipStream_t s);

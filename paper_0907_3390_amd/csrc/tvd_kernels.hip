@@ -128,6 +128,16 @@ __device__ void diag_publish(CellDiag& d, int b, double dh, const KParams& kp, v
   }
 }
 
+// Workgroups are handed to the 8 XCDs round robin (workgroup i to XCD i % 8).
+// Give each XCD a contiguous range of blocks instead, so that neighbouring
+// blocks, which share ghost-zone data, meet in the same L2.
+__device__ __forceinline__ int xcd_block(int i, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd;
+  const int k = i % kXcd, t = i / kXcd;
+  return k * q + (k < r ? k : r) + t;
+}
+
 __device__ __forceinline__ int block_edge(const KParams& kp, int b) {
   return kp.d_edge ? kp.d_edge[b] : kp.edge;
 }
@@ -181,6 +191,26 @@ struct GlobalPencil {
   }
 };
 
+// Sweep 0 source in gather mode: the pencil crosses three blocks along its
+// axis D (0: x or 2: z); p[r] points at the pencil's row in the block at
+// offset r-1 along D (the west / own / east interior, or below / own / above).
+// Cells j < 3 come from the lower neighbour, j >= N+3 from the upper one.
+template <typename T, int N, int D>
+struct GatherPencil {
+  const T* p[3];
+  __device__ inline void load(int j, T u[kNV]) const {
+    constexpr int N3 = N * N * N;
+    constexpr int S = D == 0 ? 1 : N * N;
+    const int r = j < kG ? 0 : (j >= N + kG ? 2 : 1);
+    const int jl = j - kG - (r - 1) * N;
+    const T* c = p[r] + jl * S;
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = c[gcomp<D>(k) * N3];
+  }
+};
+
+__device__ __forceinline__ int ghost_region(int c, int n) { return c < kG ? -1 : (c >= n + kG ? 1 : 0); }
+
 // Sweep 0 sink: interior cells along c0 into LDS.
 template <typename T, class L, int D>
 struct LdsSink0 {
@@ -227,7 +257,7 @@ struct LdsPencil2 {
   }
 };
 
-template <typename T, int N, int ORDER, int NT, int PAD, bool FUSE>
+template <typename T, int N, int ORDER, int NT, int PAD, bool FUSE, bool GATHER>
 __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   using L = LdsLayout<N, PAD>;
   constexpr int M = N + 2 * kG;
@@ -237,31 +267,77 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   constexpr int D1 = 1;
   constexpr int D2 = ORDER == 0 ? 2 : 0;
   __shared__ T S[kNV * L::PLANE];
+  __shared__ int64_t nboff[GATHER ? 27 : 1];
+  __shared__ int nbad;
 
-  const int b = blockIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
   if (block_edge(kp, b) != N) return;  // block belongs to another edge's launch
-  const T* __restrict__ bin = reinterpret_cast<const T*>(kp.uin) +
-                              (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * M3);
   T* __restrict__ bout = reinterpret_cast<T*>(kp.uout) +
                          (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3);
   double dh;
   const Coef<T> cf = make_coef<T>(kp, b, dh);
 
-  // sweep 0: every (c1, c2) pencil, ghosts of the later axes included
-  for (int p = threadIdx.x; p < M * M; p += NT) {
-    int c1, c2, start;
-    if (ORDER == 0) {  // x pencils; consecutive threads step in y
-      c1 = p % M;
-      c2 = p / M;
-      start = c1 * M + c2 * M * M;
-    } else {           // z pencils; consecutive threads step in x
-      c2 = p % M;
-      c1 = p / M;
-      start = c2 + c1 * M;
+  if constexpr (GATHER) {
+    // offsets of the 27 blocks around b; a missing or mismatched neighbour
+    // makes the block unadvanceable here (counted, output left untouched)
+    if (threadIdx.x == 0) nbad = 0;
+    __syncthreads();
+    if (threadIdx.x < 27) {
+      const int nb = kp.nbr[27 * (int64_t)b + threadIdx.x];
+      const bool ok = nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == N;
+      if (!ok) atomicAdd(&nbad, 1);
+      nboff[threadIdx.x] = ok ? (kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * N3) : 0;
     }
-    const GlobalPencil<T, M, D0> src{bin + start};
-    const LdsSink0<T, L, D0> dst{S, c1, c2};
-    pencil_sweep<T, N>(src, dst, cf);
+    __syncthreads();
+    if (nbad) {
+      if (threadIdx.x == 0) atomicAdd(&kp.counters[1], (unsigned long long)N3);
+      return;
+    }
+    const T* __restrict__ uin = reinterpret_cast<const T*>(kp.uin);
+    // sweep 0 straight from the neighbours' interiors
+    for (int p = threadIdx.x; p < M * M; p += NT) {
+      int c1, c2;
+      if (ORDER == 0) {
+        c1 = p % M;
+        c2 = p / M;
+      } else {
+        c2 = p % M;
+        c1 = p / M;
+      }
+      GatherPencil<T, N, D0> src;
+      if (ORDER == 0) {  // x pencil at (y, z) = (c1, c2)
+        const int ry = ghost_region(c1, N), rz = ghost_region(c2, N);
+        const int t = N * (c1 - kG - ry * N) + N * N * (c2 - kG - rz * N);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) src.p[r] = uin + nboff[r + 3 * (ry + 1) + 9 * (rz + 1)] + t;
+      } else {           // z pencil at (x, y) = (c2, c1)
+        const int rx = ghost_region(c2, N), ry = ghost_region(c1, N);
+        const int t = (c2 - kG - rx * N) + N * (c1 - kG - ry * N);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) src.p[r] = uin + nboff[(rx + 1) + 3 * (ry + 1) + 9 * r] + t;
+      }
+      const LdsSink0<T, L, D0> dst{S, c1, c2};
+      pencil_sweep<T, N>(src, dst, cf);
+    }
+  } else {
+    const T* __restrict__ bin = reinterpret_cast<const T*>(kp.uin) +
+                                (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * M3);
+    // sweep 0: every (c1, c2) pencil, ghosts of the later axes included
+    for (int p = threadIdx.x; p < M * M; p += NT) {
+      int c1, c2, start;
+      if (ORDER == 0) {  // x pencils; consecutive threads step in y
+        c1 = p % M;
+        c2 = p / M;
+        start = c1 * M + c2 * M * M;
+      } else {           // z pencils; consecutive threads step in x
+        c2 = p % M;
+        c1 = p / M;
+        start = c2 + c1 * M;
+      }
+      const GlobalPencil<T, M, D0> src{bin + start};
+      const LdsSink0<T, L, D0> dst{S, c1, c2};
+      pencil_sweep<T, N>(src, dst, cf);
+    }
   }
   __syncthreads();
   // sweep 1: interior along c0, all of c2
@@ -524,38 +600,44 @@ bool variant_supported(int dtype, const Variant& v) {
   return !(dtype == 2 && v.edge == 16);
 }
 
-template <typename T, int N, int NT, int PAD>
+template <typename T, int N, int NT, int PAD, bool GATHER>
 static hipError_t launch_b(int order, bool fuse, const KParams& kp, hipStream_t s) {
   const dim3 grid(kp.nblocks), block(NT);
   if (order == 0) {
-    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, true>), grid, block, 0, s, kp);
-    else hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, false>), grid, block, 0, s, kp);
+    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, true, GATHER>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, false, GATHER>), grid, block, 0, s, kp);
   } else {
-    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, true>), grid, block, 0, s, kp);
-    else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, false>), grid, block, 0, s, kp);
+    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, true, GATHER>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, false, GATHER>), grid, block, 0, s, kp);
   }
   return hipGetLastError();
 }
 
+template <typename T, int N, int NT, int PAD>
+static hipError_t launch_g(int order, bool fuse, bool gather, const KParams& kp, hipStream_t s) {
+  return gather ? launch_b<T, N, NT, PAD, true>(order, fuse, kp, s)
+                : launch_b<T, N, NT, PAD, false>(order, fuse, kp, s);
+}
+
 template <typename T>
-static hipError_t launch_typed(int order, const Variant& v, bool fuse, const KParams& kp,
-                               hipStream_t s) {
+static hipError_t launch_typed(int order, const Variant& v, bool fuse, bool gather,
+                               const KParams& kp, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {  // FP64 edge 16 does not fit in LDS
-    if (v.edge == 16 && v.threads == 512 && v.pad == 16) return launch_b<T, 16, 512, 16>(order, fuse, kp, s);
-    if (v.edge == 16 && v.threads == 512 && v.pad == 0) return launch_b<T, 16, 512, 0>(order, fuse, kp, s);
+    if (v.edge == 16 && v.threads == 512 && v.pad == 16) return launch_g<T, 16, 512, 16>(order, fuse, gather, kp, s);
+    if (v.edge == 16 && v.threads == 512 && v.pad == 0) return launch_g<T, 16, 512, 0>(order, fuse, gather, kp, s);
   }
-  if (v.edge == 8 && v.threads == 128 && v.pad == 8) return launch_b<T, 8, 128, 8>(order, fuse, kp, s);
-  if (v.edge == 8 && v.threads == 256 && v.pad == 8) return launch_b<T, 8, 256, 8>(order, fuse, kp, s);
-  if (v.edge == 8 && v.threads == 128 && v.pad == 0) return launch_b<T, 8, 128, 0>(order, fuse, kp, s);
-  if (v.edge == 8 && v.threads == 64 && v.pad == 8) return launch_b<T, 8, 64, 8>(order, fuse, kp, s);
+  if (v.edge == 8 && v.threads == 128 && v.pad == 8) return launch_g<T, 8, 128, 8>(order, fuse, gather, kp, s);
+  if (v.edge == 8 && v.threads == 256 && v.pad == 8) return launch_g<T, 8, 256, 8>(order, fuse, gather, kp, s);
+  if (v.edge == 8 && v.threads == 128 && v.pad == 0) return launch_g<T, 8, 128, 0>(order, fuse, gather, kp, s);
+  if (v.edge == 8 && v.threads == 64 && v.pad == 8) return launch_g<T, 8, 64, 8>(order, fuse, gather, kp, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, const KParams& kp,
-                          hipStream_t s) {
-  if (dtype == 1) return launch_typed<float>(order, v, fuse, kp, s);
+hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, bool gather,
+                          const KParams& kp, hipStream_t s) {
+  if (dtype == 1) return launch_typed<float>(order, v, fuse, gather, kp, s);
   if (v.edge == 16) return hipErrorInvalidValue;
-  return launch_typed<double>(order, v, fuse, kp, s);
+  return launch_typed<double>(order, v, fuse, gather, kp, s);
 }
 
 hipError_t launch_plain_f64(int order, bool fuse, const KParams& kp, hipStream_t s) {

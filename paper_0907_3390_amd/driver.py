@@ -5,7 +5,9 @@ trip: before every even step the time step comes from the Eq. (CFL) signal
 speed of the current state (kept in device memory), the ghost zones are
 refilled from sibling interiors, and the state is advanced by one triple,
 forward xyz on even steps and backward zyx on odd steps, the pair sharing
-one dt (Sec. 2.2).  The signal speed of an odd step's output is fused into
+one dt (Sec. 2.2).  In gather mode the refill and the advance are one
+kernel: the advance reads ghost cells from the neighbours' interiors and
+writes the other of two interior buffers.  The signal speed of an odd step's output is fused into
 that step's advance, and the conservation sums can be fused into any step.
 torch only provides the device buffers and the stream.
 """
@@ -23,7 +25,7 @@ class DeviceBlocks:
 
     def __init__(self, ctx: tvd.Context, bs: BlockSet, dtype=torch.float32,
                  device="cuda:0", gamma: float = 5.0 / 3.0, p_floor: float = 0.0,
-                 cfl: float = 0.5, kernel: int = tvd.TVD_KERNEL_AUTO):
+                 cfl: float = 0.5, kernel: int = tvd.TVD_KERNEL_AUTO, gather: bool = False):
         self.ctx = ctx
         self.bs = bs
         self.dtype = dtype
@@ -32,9 +34,14 @@ class DeviceBlocks:
         self.p_floor = p_floor
         self.cfl = cfl
         self.kernel = kernel
+        self.gather = gather
         dev = self.device
         self.interior = torch.zeros(bs.out_total, dtype=dtype, device=dev)
-        self.ghosted = torch.zeros(bs.in_total, dtype=dtype, device=dev)
+        if gather:
+            self.spare = torch.zeros(bs.out_total, dtype=dtype, device=dev)
+            self.ghosted = None
+        else:
+            self.ghosted = torch.zeros(bs.in_total, dtype=dtype, device=dev)
         self.nbr = torch.from_numpy(bs.nbr).to(dev)
         self.dh = torch.from_numpy(bs.dh).to(dev)
         self.dt = torch.zeros(bs.n_blocks, dtype=torch.float64, device=dev)
@@ -76,10 +83,17 @@ class DeviceBlocks:
         self.ctx.tvd_fill_ghosts(self.batch, self.nbr, self.interior, self.ghosted)
 
     def advance(self, order: int, fuse_speed: bool = False, fuse_sums: bool = False):
-        self.ctx.tvd_patch_advance(self.batch, self.ghosted, self.interior, order, self.gamma,
-                                   self.p_floor, self.kernel,
-                                   smax=self.smax if fuse_speed else None,
-                                   sums=self.sums if fuse_sums else None)
+        smax = self.smax if fuse_speed else None
+        sums = self.sums if fuse_sums else None
+        if self.gather:
+            self.ctx.tvd_patch_advance_gather(self.batch, self.nbr, self.interior, self.spare,
+                                              order, self.gamma, self.p_floor, self.kernel,
+                                              smax=smax, sums=sums)
+            self.interior, self.spare = self.spare, self.interior
+        else:
+            self.ctx.tvd_patch_advance(self.batch, self.ghosted, self.interior, order,
+                                       self.gamma, self.p_floor, self.kernel, smax=smax,
+                                       sums=sums)
 
     def step(self, fused: bool = True, sums: bool = False):
         """One step; even steps take a fresh dt, odd steps reuse it."""
@@ -88,7 +102,8 @@ class DeviceBlocks:
             if not (fused and s > 0):
                 self.signal_speed()
             self.set_dt_from_speed()
-        self.fill_ghosts()
+        if not self.gather:
+            self.fill_ghosts()
         self.advance(s % 2, fuse_speed=fused and s % 2 == 1, fuse_sums=sums)
         self.step_index += 1
 

@@ -37,7 +37,7 @@ EXPORTS = [
     "tvd_create", "tvd_destroy", "tvd_status_string", "tvd_last_error", "tvd_reserve",
     "tvd_patch_advance", "tvd_max_signal_speed", "tvd_dt_from_speed",
     "tvd_conservation_sums", "tvd_read_flags", "tvd_fill_ghosts",
-    "tvd_variant_count", "tvd_variant_info", "tvd_set_variant",
+    "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
 ]
 
 
@@ -78,6 +78,8 @@ def load(path: str = LIB_PATH):
         "tvd_last_error": (ctypes.c_char_p, [vp]),
         "tvd_reserve": (ctypes.c_int, [vp, ctypes.c_int]),
         "tvd_patch_advance": (ctypes.c_int, [vp, bp, vp, vp, i32, dbl, dbl, i32, vp, vp, vp]),
+        "tvd_patch_advance_gather": (ctypes.c_int, [vp, bp, vp, vp, vp, i32, dbl, dbl, i32, vp,
+                                                    vp, vp]),
         "tvd_max_signal_speed": (ctypes.c_int, [vp, bp, vp, i32, dbl, dbl, vp, vp]),
         "tvd_dt_from_speed": (ctypes.c_int, [vp, bp, vp, dbl, vp, vp]),
         "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
@@ -171,6 +173,15 @@ class Context:
         st = self.lib.tvd_patch_advance(self.h, batch.ref, _ptr(u_in), _ptr(u_out),
                                         sweep_order, gamma, p_floor, flags, _ptr(smax),
                                         _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_patch_advance_gather(self, batch: Batch, nbr, u_in, u_out, sweep_order: int,
+                                 gamma: float, p_floor: float = 0.0,
+                                 flags: int = TVD_KERNEL_AUTO, smax=None, sums=None,
+                                 stream=None, check: bool = True):
+        st = self.lib.tvd_patch_advance_gather(self.h, batch.ref, _ptr(nbr), _ptr(u_in),
+                                               _ptr(u_out), sweep_order, gamma, p_floor, flags,
+                                               _ptr(smax), _ptr(sums), _stream(stream))
         return self._check(st) if check else st
 
     def tvd_max_signal_speed(self, batch: Batch, u, layout: int, gamma: float, smax,

@@ -110,6 +110,62 @@ def test_edge8_equals_edge16_fp32(ctx):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("dtype,n", [(torch.float32, 16), (torch.float32, 8), (torch.float64, 8)])
+def test_gather_equals_fill_then_advance(ctx, dtype, n):
+    """Gathering ghost cells inside the advance gives bit for bit the result
+    of filling a ghosted copy first (same arithmetic, same inputs)."""
+    note(f"gather vs fill+advance dtype={dtype} n={n}")
+    g = wl.lognormal(32, seed=17, sigma_ln=0.8)
+    if dtype == torch.float32:
+        g = g.astype(np.float32).astype(np.float64)
+    bs = layout.periodic_grid_blockset(32, n)
+    outs = []
+    for gather in (False, True):
+        dev = DeviceBlocks(ctx, bs, dtype=dtype, gather=gather)
+        dev.upload(layout.grid_to_blocks(g, n))
+        rec = dev.run(6, sums_each_step=True)
+        torch.cuda.synchronize()
+        outs.append((np.stack(dev.download()), dev.dt.cpu().numpy(), rec.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    np.testing.assert_allclose(outs[0][2], outs[1][2], rtol=1e-15)
+
+
+def test_gather_mixed_edges_fp32(ctx):
+    note("gather with mixed edges (boxes)")
+    boxes = wl.sound_wave_boxes(counts=(4, 2, 1), seed=6)
+    grids = [b.astype(np.float32).astype(np.float64) for b in boxes.grids]
+    edges = [g.shape[1] for g in grids]
+    efor = lambda L: 8 if L == 8 else 16
+    bs = layout.boxes_blockset(edges, efor, boxes.dh)
+    outs = []
+    for gather in (False, True):
+        dev = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=gather)
+        dev.upload(layout.boxes_to_blocks(grids, efor))
+        dev.run(4)
+        torch.cuda.synchronize()
+        outs.append(dev.interior.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_gather_missing_neighbour_is_flagged(ctx):
+    note("gather with a missing neighbour")
+    g = wl.uniform(16, rho=1.0, P=1.0)
+    bs = layout.periodic_grid_blockset(16, 8)
+    bs.nbr[3, 4] = -1
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=True)
+    dev.upload(layout.grid_to_blocks(g, 8))
+    dev.spare.fill_(7.0)
+    ctx.tvd_read_flags()
+    dev.dt.fill_(1e-3)
+    dev.advance(0)
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_ERR_NONPHYSICAL and bad == 8 ** 3
+    out = dev.interior.cpu().numpy().reshape(8, 5, 8, 8, 8)
+    assert np.all(out[3] == 7.0)                      # block 3 untouched
+    assert np.array_equal(out[0], layout.grid_to_blocks(g, 8)[0].astype(np.float32))
+
+
 def test_fill_ghosts_bitwise(ctx):
     note("ghost fill vs periodic copy, n=8 and 16, FP64")
     g = wl.lognormal(32, seed=21)
