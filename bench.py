@@ -39,11 +39,49 @@ SEED = 2024
 GAMMA = 5.0 / 3.0
 CFL = 0.5
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 (turned off in this build):
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batched_fp32_edge16_gather_256cube_traffic.txt")
+KERNEL_SOURCES = ["paper_0907_3390_amd/csrc/tvd_kernels.hip", "paper_0907_3390_amd/csrc/tvd_device.hpp"]
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 error; HBM GB/s % of peak"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def flops_per_block(n: int) -> int:
+    """Algorithmic FP32 work of one step on one block of edge n: a split-flux
+    evaluation is 45 flops, a pencil of M = n+6 cells 45M + 5(M-1) + 60(M-2)
+    + 65(n+1) + 15n (FMA = 2, add/mul/compare/reciprocal/sqrt = 1), and the
+    region rule needs (n+6)^2 + n(n+6) + n^2 pencils."""
+    M = n + 6
+    pencil = 45 * M + 5 * (M - 1) + 60 * (M - 2) + 65 * (n + 1) + 15 * n
+    return pencil * (M * M + n * M + n * n)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the advance from the committed rocprofv3 counter
+    summary, only if it was taken on the current kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return float(kv["hbm_bytes_per_launch_mean"]), "rocprofv3 FETCH_SIZE x2 + WRITE_SIZE"
 
 
 def make_ic():
@@ -52,29 +90,39 @@ def make_ic():
     return g.astype(np.float32)  # FP32-rounded; the FP64 runs start from the same values
 
 
-def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False):
+def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=False):
+    """Warm up, then time `steps` steps twice: eagerly with HIP events around
+    every advance launch (for the kernel's average duration), and as replays
+    of a HIP graph holding one xyz/zyx pair (for the step rate)."""
     import torch
-    from paper_0907_3390_amd import layout
+    from paper_0907_3390_amd import layout, tvd
     from paper_0907_3390_amd.driver import DeviceBlocks
     bs = layout.periodic_grid_blockset(N_GRID, n)
     dev = DeviceBlocks(ctx, bs, dtype=dtype, gamma=GAMMA, cfl=CFL, kernel=kernel, gather=gather)
     dev.upload(layout.grid_to_blocks(grid32.astype(np.float64), n))
-    for _ in range(warmup):
+    info = {"blocks": bs.n_blocks, "edge": n}
+    if tune:
+        # pick the launch variant on the real data (scratch output), untimed
+        dev.dt.fill_(CFL / N_GRID / 4.0)
+        scratch = dev.spare if gather else dev.interior.clone()
+        src = dev.interior if gather else dev.ghosted
+        if not gather:
+            dev.fill_ghosts()
+        idx, ms = ctx.tvd_autotune(dev.batch, dev.nbr if gather else None, src, scratch, GAMMA,
+                                   reps=3)
+        info["variant"] = dict(zip(("index", "edge", "threads", "lds_pad", "split"),
+                                   tvd.variants()[idx]))
+        info["variant"]["tuned_ms_per_pair"] = ms
+        log(f"bench: tuned variant {info['variant']}")
+    for _ in range(max(warmup, 2)):
         dev.step()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     adv_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
     for k in range(steps):
         s = dev.step_index
         if s % 2 == 0:
-            if s == 0:
-                dev.signal_speed()
             dev.set_dt_from_speed()
         if not gather:
             dev.fill_ghosts()
@@ -82,14 +130,25 @@ def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False):
         dev.advance(s % 2, fuse_speed=(s % 2 == 1))
         adv_ev[k][1].record(stream)
         dev.step_index += 1
-    stop.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(stop)
-    adv_ms = [a.elapsed_time(b) for a, b in adv_ev]
-    st, floored, bad = ctx.tvd_read_flags()
-    return dev, {"total_ms": total_ms, "wall_s": wall, "adv_ms": adv_ms, "floored": floored,
-                 "nonphysical": bad, "blocks": bs.n_blocks, "edge": n}
+    info["adv_ms"] = [a.elapsed_time(b) for a, b in adv_ev]
+    # graph-captured pair, replayed steps/2 times
+    side = torch.cuda.Stream()
+    graph = dev.capture(2, stream=side)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(side)
+    for _ in range(steps // 2):
+        dev.replay(graph, stream=side)
+    stop.record(side)
+    torch.cuda.synchronize()
+    info["wall_s"] = time.perf_counter() - t0
+    info["total_ms"] = start.elapsed_time(stop)
+    graph.close()
+    st, info["floored"], info["nonphysical"] = ctx.tvd_read_flags()
+    return dev, info
 
 
 def cpu_baseline(grid32, budget_s=15.0):
@@ -148,6 +207,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-variant tuner")
     ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
     ap.add_argument("--no-gather", action="store_true",
                     help="headline run with a separate ghost fill instead of the gathering advance")
@@ -170,7 +230,7 @@ def main():
     gather = not args.no_gather
     log(f"bench: FP32 batched, edge {args.edge}, gather={gather}, {args.warmup}+{args.steps} steps")
     dev32, r32 = run_gpu(ctx, grid32, args.edge, torch.float32, tvd.TVD_KERNEL_AUTO,
-                         args.steps, args.warmup, gather=gather)
+                         args.steps, args.warmup, gather=gather, tune=not args.no_tune)
     ms_step = r32["total_ms"] / args.steps
     value = cells * args.steps / (r32["total_ms"] * 1e-3)
     n = args.edge
@@ -180,6 +240,9 @@ def main():
     bytes_launch = nb * ((n + 6) ** 3 + n ** 3) * 5 * 4
     adv_avg_ms = float(np.mean(r32["adv_ms"]))
     achieved = bytes_launch / (adv_avg_ms * 1e-3) / 1e9
+    flops_launch = nb * flops_per_block(n)
+    tflops = flops_launch / (adv_avg_ms * 1e-3) / 1e12
+    traffic, traffic_note = measured_traffic() if (n == 16 and gather) else (None, "not profiled")
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -194,18 +257,26 @@ def main():
                                "seed 2024",
                    "cells": cells, "blocks": nb, "block_edge": n, "precision": "fp32",
                    "ghost_zones": "gathered inside the advance" if gather else "separate fill"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "traffic_source": traffic_note,
                      "kernel": f"k_batched<float,{n}>" + (" gather" if gather else ""),
                      "avg_launch_ms": adv_avg_ms,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": bytes_launch}},
         "advance_cell_updates_per_s": cells / (adv_avg_ms * 1e-3),
+        "timing": "steps replayed as a HIP graph of one xyz/zyx pair; advance duration from "
+                  "HIP events around eager launches of the same steps",
+        "variant": r32.get("variant"),
         "health": {"floored": r32["floored"], "nonphysical": r32["nonphysical"]},
     }
     log(f"bench: FP32 {value / 1e9:.2f} G cell-updates/s, advance {adv_avg_ms:.3f} ms "
-        f"({achieved:.0f} GB/s)")
+        f"({achieved:.0f} GB/s, {tflops:.1f} TFLOP/s)")
     out["hbm_copy_measured"] = copy_bandwidth()
-    out["roofline"]["frac_of_measured_copy"] = achieved / out["hbm_copy_measured"]["read_plus_write_GBs"]
+    out["roofline"]["hbm"]["frac_of_measured_copy"] = (
+        achieved / out["hbm_copy_measured"]["read_plus_write_GBs"])
     log(f"bench: plain 1 GiB copy {out['hbm_copy_measured']['read_plus_write_GBs']:.0f} GB/s")
 
     if not args.no_fp64:
@@ -236,7 +307,7 @@ def main():
                              "avg_launch_ms": a64, "blocks": r64["blocks"], "block_edge": 8}
         out["speedup_fp32_batched_vs_fp64_plain"] = value / v64
         out["l1_vs_fp64"] = {k: float(v) for k, v in nrm.items()}
-        out["l1_vs_fp64"]["after_steps"] = args.warmup + args.steps
+        out["l1_vs_fp64"]["after_steps"] = max(args.warmup, 2) + 2 * args.steps
         log(f"bench: FP64 plain {v64 / 1e9:.3f} G cell-updates/s; relL1 {nrm}")
     if not args.no_cpu_baseline:
         log("bench: FP64 oracle on the host cores (bounded sample)")

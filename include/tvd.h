@@ -113,13 +113,31 @@ int tvd_reserve(tvd_ctx *ctx, int n_blocks);
 
 /* Number of batched-kernel variants compiled into the library. */
 int tvd_variant_count(void);
-/* Describe variant `index`: block edge, workgroup size and the padding of
- * the LDS rows (layout).  TVD_ERR_INVALID_ARG for an index out of range. */
-int tvd_variant_info(int index, int32_t *edge, int32_t *threads, int32_t *lds_pad);
+/* Describe variant `index`: block edge, workgroup size, the padding of the
+ * LDS rows (layout) and how pencils map to threads (split bit 0: the tail of
+ * the second sweep is done as half pencils by two threads each; bit 1: the
+ * whole third sweep is).  TVD_ERR_INVALID_ARG for an index out of range.
+ * Any output pointer may be NULL. */
+int tvd_variant_info(int index, int32_t *edge, int32_t *threads, int32_t *lds_pad,
+                     int32_t *split);
 /* Select the variant used by TVD_KERNEL_AUTO / TVD_KERNEL_BATCHED for blocks of
  * (dtype, edge); index -1 restores the built-in default.  A variant of
  * another edge, or FP64 with edge 16, is TVD_ERR_UNSUPPORTED. */
 int tvd_set_variant(tvd_ctx *ctx, int32_t dtype, int32_t edge, int32_t index);
+
+/* Time every compiled variant serving the batch's (dtype, edge) on the
+ * caller's data and select the fastest for later advances of that
+ * (dtype, edge) on this context.  The time of a variant is the mean of `reps`
+ * forward+backward pairs after one untimed pair.  With d_nbr != NULL the
+ * gathering advance is timed (d_u_in interior blocks), else the advance of
+ * ghosted blocks.  d_u_out is scratch and its contents are overwritten;
+ * d_u_in is only read.  The batch must have a uniform edge.  Synchronous, on
+ * a private stream of default priority; not for use during graph capture.
+ * Writes the chosen variant index and its time per pair in ms (either
+ * pointer may be NULL). */
+int tvd_autotune(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
+                 const void *d_u_in, void *d_u_out, double gamma, double p_floor,
+                 int32_t reps, int32_t *chosen_index, float *best_ms);
 
 /* ---- the hot path --------------------------------------------------------- */
 
@@ -223,6 +241,25 @@ int tvd_read_flags(tvd_ctx *ctx, int64_t *n_floored, int64_t *n_nonphysical,
  */
 int tvd_fill_ghosts(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
                     const void *d_interior, void *d_ghosted, void *stream);
+
+/* ---- step sequences as HIP graphs --------------------------------------------- */
+
+typedef struct tvd_graph tvd_graph;
+
+/* Start capturing `stream` (a non-default hipStream_t) into a HIP graph, in
+ * thread-local mode: the library calls made on that stream until
+ * tvd_graph_end() are recorded, not run.  Every entry point except
+ * tvd_read_flags, tvd_autotune and the create/destroy/reserve calls may be
+ * recorded; reserve the workspace for the largest batch first.  The graph
+ * keeps the pointers and scalars of the recorded calls; per-step data that
+ * changes between replays (such as dt) must live in device memory. */
+int tvd_graph_begin(tvd_ctx *ctx, void *stream);
+/* Stop capturing and instantiate the graph; *out receives the handle. */
+int tvd_graph_end(tvd_ctx *ctx, void *stream, tvd_graph **out);
+/* Replay a recorded sequence on `stream` (asynchronous). */
+int tvd_graph_launch(tvd_graph *graph, void *stream);
+/* Free a recorded sequence (the caller ensures no replay is in flight). */
+int tvd_graph_destroy(tvd_graph *graph);
 
 #ifdef __cplusplus
 }

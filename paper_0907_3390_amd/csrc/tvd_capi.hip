@@ -12,6 +12,12 @@
 #include "tvd.h"
 #include "tvd_internal.hpp"
 
+struct tvd_graph {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct tvd_ctx {
   int device = 0;
   std::string err;
@@ -131,6 +137,7 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
   kp.nblocks = b->n_blocks;
   kp.edge = b->d_edge ? 0 : b->edge;
   kp.nbr = nullptr;
+  kp.diag = 0;
   kp.ws_smax = ctx->ws_smax;
   kp.ws_sums = ctx->ws_sums;
   kp.counters = ctx->counters;
@@ -138,8 +145,8 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
 }
 
 tvd::Variant default_variant(int dtype, int edge) {
-  if (edge == 16) return tvd::Variant{16, 512, 16};
-  return dtype == TVD_F32 ? tvd::Variant{8, 128, 8} : tvd::Variant{8, 256, 8};
+  if (edge == 16) return tvd::Variant{16, 512, 16, 1};
+  return dtype == TVD_F32 ? tvd::Variant{8, 128, 8, 0} : tvd::Variant{8, 256, 8, 0};
 }
 
 tvd::Variant chosen_variant(const tvd_ctx* ctx, int dtype, int edge) {
@@ -216,12 +223,14 @@ int tvd_reserve(tvd_ctx* ctx, int n_blocks) {
 
 int tvd_variant_count(void) { return tvd::variant_count(); }
 
-int tvd_variant_info(int index, int32_t* edge, int32_t* threads, int32_t* lds_pad) {
+int tvd_variant_info(int index, int32_t* edge, int32_t* threads, int32_t* lds_pad,
+                     int32_t* split) {
   if (index < 0 || index >= tvd::variant_count()) return TVD_ERR_INVALID_ARG;
   const tvd::Variant v = tvd::variant_at(index);
   if (edge) *edge = v.edge;
   if (threads) *threads = v.threads;
   if (lds_pad) *lds_pad = v.pad;
+  if (split) *split = v.split;
   return TVD_OK;
 }
 
@@ -286,21 +295,22 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   if (fuse && (st = reserve(ctx, batch->n_blocks, s))) return st;
   tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
   kp.nbr = d_nbr;
+  kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
   const bool gather = d_nbr != nullptr;
   hipError_t e;
   if (flags == TVD_KERNEL_PLAIN) {
-    e = tvd::launch_plain_f64(sweep_order, fuse, kp, s);
+    e = tvd::launch_plain_f64(sweep_order, kp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "plain kernel launch");
   } else if (batch->d_edge) {
     // one launch per edge; a workgroup whose block has the other edge exits
     for (int edge : {16, 8}) {
       e = tvd::launch_batched(batch->dtype, sweep_order, chosen_variant(ctx, batch->dtype, edge),
-                              fuse, gather, kp, s);
+                              gather, kp, s);
       if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
     }
   } else {
     e = tvd::launch_batched(batch->dtype, sweep_order,
-                            chosen_variant(ctx, batch->dtype, batch->edge), fuse, gather, kp, s);
+                            chosen_variant(ctx, batch->dtype, batch->edge), gather, kp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
   }
   if (d_smax) {
@@ -333,6 +343,115 @@ int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
   if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
   return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
                       d_sums, stream, d_nbr);
+}
+
+int tvd_autotune(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr, const void* d_u_in,
+                 void* d_u_out, double gamma, double p_floor, int32_t reps,
+                 int32_t* chosen_index, float* best_ms) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if ((st = check_gamma(ctx, gamma, p_floor))) return st;
+  if (batch->d_edge) return fail(ctx, TVD_ERR_UNSUPPORTED, "tune one edge at a time");
+  if (batch->n_blocks == 0 || !d_u_in || !d_u_out || d_u_in == d_u_out)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "autotune needs a non-empty batch and two buffers");
+  if (reps < 1 || reps > 1000) return fail(ctx, TVD_ERR_INVALID_ARG, "reps %d", reps);
+  const int dt = batch->dtype == TVD_F32 ? 1 : 2;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamCreate");
+  hipEvent_t a = nullptr, b = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
+  kp.nbr = d_nbr;
+  int best = -1;
+  float best_t = 0.f;
+  st = TVD_OK;
+  for (int i = 0; i < tvd::variant_count() && st == TVD_OK; ++i) {
+    const tvd::Variant v = tvd::variant_at(i);
+    if (v.edge != batch->edge || !tvd::variant_supported(dt, v)) continue;
+    // one untimed pair, then `reps` timed pairs (xyz + zyx)
+    for (int o = 0; o < 2; ++o) e = tvd::launch_batched(dt, o, v, d_nbr != nullptr, kp, s);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      for (int o = 0; o < 2 && e == hipSuccess; ++o)
+        e = tvd::launch_batched(dt, o, v, d_nbr != nullptr, kp, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) {
+      st = hip_fail(ctx, e, "autotune launch");
+      break;
+    }
+    ms /= (float)reps;
+    if (best < 0 || ms < best_t) {
+      best = i;
+      best_t = ms;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
+  if (st != TVD_OK) return st;
+  if (best < 0) return fail(ctx, TVD_ERR_UNSUPPORTED, "no variant serves this batch");
+  ctx->tuned[dt == 1 ? 0 : 1][batch->edge == 16 ? 1 : 0] = best;
+  if (chosen_index) *chosen_index = best;
+  if (best_ms) *best_ms = best_t;
+  return TVD_OK;
+}
+
+int tvd_graph_begin(tvd_ctx* ctx, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!stream) return fail(ctx, TVD_ERR_INVALID_ARG, "capture needs a non-default stream");
+  hipStream_t s = (hipStream_t)stream;
+  if (stream_capturing(s)) return fail(ctx, TVD_ERR_STATE, "stream is already capturing");
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
+  return TVD_OK;
+}
+
+int tvd_graph_end(tvd_ctx* ctx, void* stream, tvd_graph** out) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!stream || !out) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL stream or output");
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard g(ctx->device);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(ctx, e, "hipGraphInstantiate");
+  }
+  tvd_graph* gr = new tvd_graph();
+  gr->device = ctx->device;
+  gr->graph = graph;
+  gr->exec = exec;
+  *out = gr;
+  return TVD_OK;
+}
+
+int tvd_graph_launch(tvd_graph* graph, void* stream) {
+  if (!graph) return TVD_ERR_INVALID_ARG;
+  DeviceGuard g(graph->device);
+  return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? TVD_OK : TVD_ERR_HIP;
+}
+
+int tvd_graph_destroy(tvd_graph* graph) {
+  if (!graph) return TVD_ERR_INVALID_ARG;
+  {
+    DeviceGuard g(graph->device);
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+  }
+  delete graph;
+  return TVD_OK;
 }
 
 int tvd_max_signal_speed(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, int32_t layout,

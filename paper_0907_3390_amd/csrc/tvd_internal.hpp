@@ -7,6 +7,10 @@
 
 namespace tvd {
 
+// Fused diagnostics of an advance (KParams::diag bits).
+constexpr int kDiagSpeed = 1;  // per-block max signal speed into ws_smax
+constexpr int kDiagSums = 2;   // per-block compensated sums into ws_sums
+
 // Everything a batch kernel needs, passed by value as the kernel argument.
 struct KParams {
   const void* uin;
@@ -20,6 +24,7 @@ struct KParams {
   int nblocks;
   int edge;                      // uniform edge (0 when d_edge is used)
   const int32_t* nbr;            // [nblocks][27] neighbour table (gather mode)
+  int diag;                      // kDiagSpeed | kDiagSums
   double* ws_smax;               // [nblocks] per-block max signal speed
   double* ws_sums;               // [nblocks][10] per-block (sum, comp) x 5
   unsigned long long* counters;  // [0] floored, [1] non-physical
@@ -30,15 +35,16 @@ struct Variant {
   int edge;      // 8 or 16
   int threads;   // workgroup size
   int pad;       // LDS row padding (layout variant)
+  int split;     // bit 0: sweep-1 tail pencils in halves; bit 1: sweep-2 pencils in halves
 };
 
 // Launchers.  All return a hipError_t from the launch.
 // gather = true: the first sweep reads its pencils straight from the
 // interiors of the block and its 26 neighbours (kp.nbr) instead of a
 // ghosted copy; kp.uin then holds interior blocks at the out offsets.
-hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, bool gather,
-                          const KParams& kp, hipStream_t s);
-hipError_t launch_plain_f64(int order, bool fuse, const KParams& kp, hipStream_t s);
+hipError_t launch_batched(int dtype, int order, const Variant& v, bool gather, const KParams& kp,
+                          hipStream_t s);
+hipError_t launch_plain_f64(int order, const KParams& kp, hipStream_t s);
 hipError_t launch_signal_speed(int dtype, int layout, const KParams& kp, hipStream_t s);
 hipError_t launch_cons_sums(int dtype, int layout, const KParams& kp, hipStream_t s);
 hipError_t launch_finalize_max(const double* ws, int n, double* out, hipStream_t s);

@@ -71,35 +71,38 @@ __device__ __forceinline__ void diag_init(CellDiag& d) {
   for (int k = 0; k < kNV; ++k) d.sum[k] = CSum{0.0, 0.0};
 }
 
-// Health check and, when FUSE, the signal speed and sums, of one cell.
-template <typename T, bool FUSE>
-__device__ __forceinline__ void diag_cell(CellDiag& d, const T u[kNV], double gamma,
+// Health check of one output cell (in the bulk precision) and, as the
+// flags ask, its Eq. (CFL) signal speed (FP64, one division) and its share
+// of the compensated conservation sums.
+template <typename T>
+__device__ __forceinline__ void diag_cell(CellDiag& d, const T u[kNV], int flags, double gamma,
                                           double pfloor) {
-  if (FUSE) {
-    const double rho = u[0], mx = u[1], my = u[2], mz = u[3], e = u[4];
-    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
-    const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
-    double P = (gamma - 1.0) * (e - kin);
-    d.floored += P < pfloor;
-    P = P < pfloor ? pfloor : P;
-    const double cs = __builtin_sqrt(gamma * P / rho);
-    const double s = cs + fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
-    d.smax = s > d.smax ? s : d.smax;
-    d.bad += !(rho > 0.0) || !__builtin_isfinite(e) || !__builtin_isfinite(mx) ||
-             !__builtin_isfinite(my) || !__builtin_isfinite(mz) || !__builtin_isfinite(rho);
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) csum_add(d.sum[k], (double)u[k]);
-  } else {
+  {
     const T inv = Num<T>::rcp(u[0]);
-    const T m2 = u[1] * u[1] + (u[2] * u[2] + u[3] * u[3]);
-    const T P = T(gamma - 1.0) * (u[4] - T(0.5) * m2 * inv);
+    const T m2 = Num<T>::fma(u[1], u[1], u[2] * u[2] + u[3] * u[3]);
+    const T P = T(gamma - 1.0) * Num<T>::fma(T(-0.5) * m2, inv, u[4]);
     d.floored += P < T(pfloor);
     d.bad += !(u[0] > T(0)) || !__builtin_isfinite(P);
+  }
+  if (flags & kDiagSpeed) {
+    const double rho = u[0], mx = u[1], my = u[2], mz = u[3], e = u[4];
+    const double inv = 1.0 / rho;
+    const double vx = mx * inv, vy = my * inv, vz = mz * inv;
+    const double kin = 0.5 * (mx * vx + my * vy + mz * vz);
+    double P = (gamma - 1.0) * (e - kin);
+    P = P < pfloor ? pfloor : P;
+    const double cs = __builtin_sqrt(gamma * P * inv);
+    const double s = cs + fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+    d.smax = s > d.smax ? s : d.smax;
+  }
+  if (flags & kDiagSums) {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) csum_add(d.sum[k], (double)u[k]);
   }
 }
 
 // Reduce the diagnostics of a workgroup and publish them for block b.
-template <int NT, bool FUSE>
+template <int NT>
 __device__ void diag_publish(CellDiag& d, int b, double dh, const KParams& kp, void* scratch) {
   unsigned fl = d.floored, bad = d.bad;
 #pragma unroll
@@ -111,12 +114,12 @@ __device__ void diag_publish(CellDiag& d, int b, double dh, const KParams& kp, v
     if (fl) atomicAdd(&kp.counters[0], (unsigned long long)fl);
     if (bad) atomicAdd(&kp.counters[1], (unsigned long long)bad);
   }
-  if (FUSE) {
-    double* redd = reinterpret_cast<double*>(scratch);
-    const double sm = block_max<NT>(d.smax, redd);
+  if (kp.diag & kDiagSpeed) {
+    const double sm = block_max<NT>(d.smax, reinterpret_cast<double*>(scratch));
     if (threadIdx.x == 0) kp.ws_smax[b] = sm;
-    CSum* redc = reinterpret_cast<CSum*>(scratch);
-    block_csum<NT>(d.sum, redc);
+  }
+  if (kp.diag & kDiagSums) {
+    block_csum<NT>(d.sum, reinterpret_cast<CSum*>(scratch));
     if (threadIdx.x == 0) {
       const double w = dh * dh * dh;
       for (int k = 0; k < kNV; ++k) {
@@ -257,7 +260,42 @@ struct LdsPencil2 {
   }
 };
 
-template <typename T, int N, int ORDER, int NT, int PAD, bool FUSE, bool GATHER>
+// Half of a pencil: the interior cells [off, off + N/2) of an LDS pencil,
+// computed from its cells [off, off + N/2 + 6).  Two threads sharing a
+// pencil this way repeat the flux work of the six cells their halves overlap,
+// in exchange for twice the parallelism.  Each half reads cells the other
+// half updates, so the halves cannot update in place while they compute:
+// their results wait in registers (Held) until the whole workgroup has
+// passed a barrier.
+template <class A>
+struct Shifted {
+  A a;
+  int off;
+  template <typename T>
+  __device__ inline void load(int j, T u[kNV]) const { a.load(j + off, u); }
+  template <typename T>
+  __device__ inline void store(int i, const T u[kNV]) const { a.store(i + off, u); }
+};
+
+template <typename T, int NH>
+struct Held {
+  mutable T v[NH][kNV];
+  __device__ inline void store(int i, const T u[kNV]) const {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) v[i][k] = u[k];
+  }
+  template <class A>
+  __device__ inline void flush(const A& a) const {
+#pragma unroll
+    for (int i = 0; i < NH; ++i) a.store(i, v[i]);
+  }
+};
+
+// Sweep 1 (SPLIT bit 0): the first NT/2 threads take whole pencils, the
+// remaining pencils are split in halves over the other threads, so that all
+// four SIMDs carry about the same number of wave-pencils.
+// Sweep 2 (SPLIT bit 1): every pencil is split in halves over all threads.
+template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER>
 __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   using L = LdsLayout<N, PAD>;
   constexpr int M = N + 2 * kG;
@@ -341,15 +379,44 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   }
   __syncthreads();
   // sweep 1: interior along c0, all of c2
-  for (int p = threadIdx.x; p < N * M; p += NT) {
-    const LdsPencil1<T, L, D1> acc{S, p % N, p / N};
-    pencil_sweep<T, N>(acc, acc, cf);
+  if constexpr ((SPLIT & 1) != 0) {
+    constexpr int F = NT / 2;          // whole pencils
+    constexpr int R = N * M - F;       // pencils done in halves
+    static_assert(R > 0 && 2 * R <= NT - F, "split layout does not fit the workgroup");
+    const int t = threadIdx.x;
+    const bool half = t >= F && t - F < 2 * R;
+    const int p = t < F ? t : F + (t - F) / 2;
+    const Shifted<LdsPencil1<T, L, D1>> acc{{S, p % N, p / N}, ((t - F) & 1) * (N / 2)};
+    Held<T, N / 2> held;
+    if (t < F) {
+      pencil_sweep<T, N>(acc.a, acc.a, cf);
+    } else if (half) {
+      pencil_sweep<T, N / 2>(acc, held, cf);
+    }
+    __syncthreads();
+    if (half) held.flush(acc);
+  } else {
+    for (int p = threadIdx.x; p < N * M; p += NT) {
+      const LdsPencil1<T, L, D1> acc{S, p % N, p / N};
+      pencil_sweep<T, N>(acc, acc, cf);
+    }
   }
   __syncthreads();
   // sweep 2: interior along c0 and c1
-  for (int p = threadIdx.x; p < N * N; p += NT) {
-    const LdsPencil2<T, L, D2> acc{S, p % N, p / N + kG};
-    pencil_sweep<T, N>(acc, acc, cf);
+  if constexpr ((SPLIT & 2) != 0) {
+    static_assert(2 * N * N == NT, "sweep-2 halves need one thread each");
+    const int t = threadIdx.x;
+    const int p = t / 2;
+    const Shifted<LdsPencil2<T, L, D2>> acc{{S, p % N, p / N + kG}, (t & 1) * (N / 2)};
+    Held<T, N / 2> held;
+    pencil_sweep<T, N / 2>(acc, held, cf);
+    __syncthreads();
+    held.flush(acc);
+  } else {
+    for (int p = threadIdx.x; p < N * N; p += NT) {
+      const LdsPencil2<T, L, D2> acc{S, p % N, p / N + kG};
+      pencil_sweep<T, N>(acc, acc, cf);
+    }
   }
   __syncthreads();
 
@@ -365,10 +432,10 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
       u[k] = S[k * L::PLANE + o];
       bout[k * N3 + i] = u[k];
     }
-    diag_cell<T, FUSE>(dg, u, kp.gamma, kp.pfloor);
+    diag_cell<T>(dg, u, kp.diag, kp.gamma, kp.pfloor);
   }
   __syncthreads();
-  diag_publish<NT, FUSE>(dg, b, dh, kp, S);
+  diag_publish<NT>(dg, b, dh, kp, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,7 +479,7 @@ __device__ void plain_sweep(double* s, const Coef<double>& cf) {
   }
 }
 
-template <int ORDER, bool FUSE>
+template <int ORDER>
 __global__ __launch_bounds__(kPlainNT) void k_plain_f64(KParams kp) {
   constexpr int N3 = kPlainN * kPlainN * kPlainN;
   __shared__ double S[kNV * kPlainM3];
@@ -450,10 +517,10 @@ __global__ __launch_bounds__(kPlainNT) void k_plain_f64(KParams kp) {
       u[k] = S[k * kPlainM3 + o];
       bout[k * N3 + i] = u[k];
     }
-    diag_cell<double, FUSE>(dg, u, kp.gamma, kp.pfloor);
+    diag_cell<double>(dg, u, kp.diag, kp.gamma, kp.pfloor);
   }
   __syncthreads();
-  diag_publish<kPlainNT, FUSE>(dg, b, dh, kp, S);
+  diag_publish<kPlainNT>(dg, b, dh, kp, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -462,7 +529,7 @@ __global__ __launch_bounds__(kPlainNT) void k_plain_f64(KParams kp) {
 
 constexpr int kRedNT = 256;
 
-template <typename T, bool SPEED>
+template <typename T>
 __global__ __launch_bounds__(kRedNT) void k_block_diag(KParams kp, int layout) {
   __shared__ CSum red[kRedNT / 64 * kNV];
   const int b = blockIdx.x;
@@ -483,9 +550,9 @@ __global__ __launch_bounds__(kRedNT) void k_block_diag(KParams kp, int layout) {
     T u[kNV];
 #pragma unroll
     for (int k = 0; k < kNV; ++k) u[k] = base[k * m3 + o];
-    diag_cell<T, true>(dg, u, kp.gamma, kp.pfloor);
+    diag_cell<T>(dg, u, kp.diag, kp.gamma, kp.pfloor);
   }
-  if (SPEED) {
+  if (kp.diag & kDiagSpeed) {
     const double sm = block_max<kRedNT>(dg.smax, reinterpret_cast<double*>(red));
     if (threadIdx.x == 0) kp.ws_smax[b] = sm;
   } else {
@@ -584,12 +651,15 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32
 // ---------------------------------------------------------------------------
 
 static const Variant kVariants[] = {
-    {16, 512, 16},  // default FP32 edge 16: one workgroup per CU
-    {16, 512, 0},
-    {8, 128, 8},
-    {8, 256, 8},
-    {8, 128, 0},
-    {8, 64, 8},
+    {16, 512, 16, 1},  // FP32 edge 16: one workgroup per CU
+    {16, 512, 16, 0},
+    {16, 512, 16, 3},
+    {16, 512, 16, 2},
+    {16, 512, 0, 1},
+    {8, 128, 8, 0},
+    {8, 128, 8, 2},
+    {8, 256, 8, 0},
+    {8, 64, 8, 0},
 };
 
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -600,68 +670,67 @@ bool variant_supported(int dtype, const Variant& v) {
   return !(dtype == 2 && v.edge == 16);
 }
 
-template <typename T, int N, int NT, int PAD, bool GATHER>
-static hipError_t launch_b(int order, bool fuse, const KParams& kp, hipStream_t s) {
+template <typename T, int N, int NT, int PAD, int SPLIT>
+static hipError_t launch_b(int order, bool gather, const KParams& kp, hipStream_t s) {
   const dim3 grid(kp.nblocks), block(NT);
-  if (order == 0) {
-    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, true, GATHER>), grid, block, 0, s, kp);
-    else hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, false, GATHER>), grid, block, 0, s, kp);
+  if (gather) {
+    if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, true>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, true>), grid, block, 0, s, kp);
   } else {
-    if (fuse) hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, true, GATHER>), grid, block, 0, s, kp);
-    else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, false, GATHER>), grid, block, 0, s, kp);
+    if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, false>), grid, block, 0, s, kp);
+    else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, false>), grid, block, 0, s, kp);
   }
   return hipGetLastError();
 }
 
-template <typename T, int N, int NT, int PAD>
-static hipError_t launch_g(int order, bool fuse, bool gather, const KParams& kp, hipStream_t s) {
-  return gather ? launch_b<T, N, NT, PAD, true>(order, fuse, kp, s)
-                : launch_b<T, N, NT, PAD, false>(order, fuse, kp, s);
-}
-
 template <typename T>
-static hipError_t launch_typed(int order, const Variant& v, bool fuse, bool gather,
-                               const KParams& kp, hipStream_t s) {
+static hipError_t launch_typed(int order, const Variant& v, bool gather, const KParams& kp,
+                               hipStream_t s) {
+#define TVD_VARIANT(E, TH, P, SP)                                                   \
+  if (v.edge == E && v.threads == TH && v.pad == P && v.split == SP)                \
+    return launch_b<T, E, TH, P, SP>(order, gather, kp, s);
   if constexpr (sizeof(T) == 4) {  // FP64 edge 16 does not fit in LDS
-    if (v.edge == 16 && v.threads == 512 && v.pad == 16) return launch_g<T, 16, 512, 16>(order, fuse, gather, kp, s);
-    if (v.edge == 16 && v.threads == 512 && v.pad == 0) return launch_g<T, 16, 512, 0>(order, fuse, gather, kp, s);
+    TVD_VARIANT(16, 512, 16, 1)
+    TVD_VARIANT(16, 512, 16, 0)
+    TVD_VARIANT(16, 512, 16, 3)
+    TVD_VARIANT(16, 512, 16, 2)
+    TVD_VARIANT(16, 512, 0, 1)
   }
-  if (v.edge == 8 && v.threads == 128 && v.pad == 8) return launch_g<T, 8, 128, 8>(order, fuse, gather, kp, s);
-  if (v.edge == 8 && v.threads == 256 && v.pad == 8) return launch_g<T, 8, 256, 8>(order, fuse, gather, kp, s);
-  if (v.edge == 8 && v.threads == 128 && v.pad == 0) return launch_g<T, 8, 128, 0>(order, fuse, gather, kp, s);
-  if (v.edge == 8 && v.threads == 64 && v.pad == 8) return launch_g<T, 8, 64, 8>(order, fuse, gather, kp, s);
+  TVD_VARIANT(8, 128, 8, 0)
+  TVD_VARIANT(8, 128, 8, 2)
+  TVD_VARIANT(8, 256, 8, 0)
+  TVD_VARIANT(8, 64, 8, 0)
+#undef TVD_VARIANT
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batched(int dtype, int order, const Variant& v, bool fuse, bool gather,
-                          const KParams& kp, hipStream_t s) {
-  if (dtype == 1) return launch_typed<float>(order, v, fuse, gather, kp, s);
+hipError_t launch_batched(int dtype, int order, const Variant& v, bool gather, const KParams& kp,
+                          hipStream_t s) {
+  if (dtype == 1) return launch_typed<float>(order, v, gather, kp, s);
   if (v.edge == 16) return hipErrorInvalidValue;
-  return launch_typed<double>(order, v, fuse, gather, kp, s);
+  return launch_typed<double>(order, v, gather, kp, s);
 }
 
-hipError_t launch_plain_f64(int order, bool fuse, const KParams& kp, hipStream_t s) {
+hipError_t launch_plain_f64(int order, const KParams& kp, hipStream_t s) {
   const dim3 grid(kp.nblocks), block(kPlainNT);
-  if (order == 0) {
-    if (fuse) hipLaunchKernelGGL((k_plain_f64<0, true>), grid, block, 0, s, kp);
-    else hipLaunchKernelGGL((k_plain_f64<0, false>), grid, block, 0, s, kp);
-  } else {
-    if (fuse) hipLaunchKernelGGL((k_plain_f64<1, true>), grid, block, 0, s, kp);
-    else hipLaunchKernelGGL((k_plain_f64<1, false>), grid, block, 0, s, kp);
-  }
+  if (order == 0) hipLaunchKernelGGL((k_plain_f64<0>), grid, block, 0, s, kp);
+  else hipLaunchKernelGGL((k_plain_f64<1>), grid, block, 0, s, kp);
+  return hipGetLastError();
+}
+
+static hipError_t launch_diag(int dtype, int layout, KParams kp, int flags, hipStream_t s) {
+  kp.diag = flags;
+  if (dtype == 1) hipLaunchKernelGGL((k_block_diag<float>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
+  else hipLaunchKernelGGL((k_block_diag<double>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
   return hipGetLastError();
 }
 
 hipError_t launch_signal_speed(int dtype, int layout, const KParams& kp, hipStream_t s) {
-  if (dtype == 1) hipLaunchKernelGGL((k_block_diag<float, true>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
-  else hipLaunchKernelGGL((k_block_diag<double, true>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
-  return hipGetLastError();
+  return launch_diag(dtype, layout, kp, kDiagSpeed, s);
 }
 
 hipError_t launch_cons_sums(int dtype, int layout, const KParams& kp, hipStream_t s) {
-  if (dtype == 1) hipLaunchKernelGGL((k_block_diag<float, false>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
-  else hipLaunchKernelGGL((k_block_diag<double, false>), dim3(kp.nblocks), dim3(kRedNT), 0, s, kp, layout);
-  return hipGetLastError();
+  return launch_diag(dtype, layout, kp, kDiagSums, s);
 }
 
 hipError_t launch_finalize_max(const double* ws, int n, double* out, hipStream_t s) {

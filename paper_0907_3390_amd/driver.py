@@ -116,6 +116,37 @@ class DeviceBlocks:
                 rec[i].copy_(self.sums)
         return rec
 
+    def capture(self, steps: int, fused: bool = True, sums: bool = False, stream=None):
+        """Record `steps` steps (an even number, so that the pair structure
+        and the ping-pong buffers come back to where they started) into a HIP
+        graph through the library's native capture; returns the graph.  The
+        recorded work does not run: replay it with graph.replay()."""
+        if steps % 2:
+            raise ValueError("capture whole xyz/zyx pairs")
+        if self.step_index % 2:
+            raise ValueError("capture must start on an even step")
+        if self.step_index == 0 and fused:
+            raise ValueError("run one pair first: the fused speed of an odd step seeds dt")
+        s = torch.cuda.Stream() if stream is None else stream
+        s.wait_stream(torch.cuda.current_stream())
+        start = self.step_index
+        with torch.cuda.stream(s):
+            self.ctx.tvd_graph_begin(s)
+            try:
+                for _ in range(steps):
+                    self.step(fused=fused, sums=sums)
+            except Exception:
+                self.ctx.tvd_graph_end(s).close()
+                raise
+            g = self.ctx.tvd_graph_end(s)
+        self.step_index = start
+        self.graph_steps = steps
+        return g
+
+    def replay(self, graph, stream=None):
+        graph.replay(stream)
+        self.step_index += self.graph_steps
+
     def conservation_sums(self):
         self.ctx.tvd_conservation_sums(self.batch, self.interior, tvd.TVD_LAYOUT_INTERIOR, self.sums)
         return self.sums

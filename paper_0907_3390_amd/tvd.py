@@ -38,6 +38,7 @@ EXPORTS = [
     "tvd_patch_advance", "tvd_max_signal_speed", "tvd_dt_from_speed",
     "tvd_conservation_sums", "tvd_read_flags", "tvd_fill_ghosts",
     "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
+    "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
 ]
 
 
@@ -86,10 +87,15 @@ def load(path: str = LIB_PATH):
         "tvd_read_flags": (ctypes.c_int, [vp, i64p, i64p, vp]),
         "tvd_fill_ghosts": (ctypes.c_int, [vp, bp, vp, vp, vp, vp]),
         "tvd_variant_count": (ctypes.c_int, []),
-        "tvd_variant_info": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
-                                            ctypes.POINTER(ctypes.c_int32),
-                                            ctypes.POINTER(ctypes.c_int32)]),
+        "tvd_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 4),
         "tvd_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
+        "tvd_graph_begin": (ctypes.c_int, [vp, vp]),
+        "tvd_graph_end": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp)]),
+        "tvd_graph_launch": (ctypes.c_int, [vp, vp]),
+        "tvd_graph_destroy": (ctypes.c_int, [vp]),
+        "tvd_autotune": (ctypes.c_int, [vp, bp, vp, vp, vp, dbl, dbl, i32,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -200,6 +206,24 @@ class Context:
     def tvd_set_variant(self, dtype: int, edge: int, index: int):
         return self._check(self.lib.tvd_set_variant(self.h, dtype, edge, index))
 
+    def tvd_autotune(self, batch: Batch, nbr, u_in, u_out, gamma: float, p_floor: float = 0.0,
+                     reps: int = 3):
+        """Returns (chosen variant index, ms per xyz+zyx pair)."""
+        idx = ctypes.c_int32(-1)
+        ms = ctypes.c_float(0.0)
+        self._check(self.lib.tvd_autotune(self.h, batch.ref, _ptr(nbr), _ptr(u_in), _ptr(u_out),
+                                          gamma, p_floor, reps, ctypes.byref(idx),
+                                          ctypes.byref(ms)))
+        return idx.value, ms.value
+
+    def tvd_graph_begin(self, stream):
+        return self._check(self.lib.tvd_graph_begin(self.h, _stream(stream)))
+
+    def tvd_graph_end(self, stream):
+        g = ctypes.c_void_p()
+        self._check(self.lib.tvd_graph_end(self.h, _stream(stream), ctypes.byref(g)))
+        return Graph(self.lib, g)
+
     def tvd_read_flags(self, stream=None):
         a = ctypes.c_int64(0)
         b = ctypes.c_int64(0)
@@ -213,14 +237,40 @@ class Context:
             self.h, batch.ref, _ptr(nbr), _ptr(interior), _ptr(ghosted), _stream(stream)))
 
 
+class Graph:
+    """A recorded step sequence (tvd_graph); replay() launches it."""
+
+    def __init__(self, lib, handle):
+        self.lib = lib
+        self.h = handle
+
+    def tvd_graph_launch(self, stream=None):
+        st = self.lib.tvd_graph_launch(self.h, _stream(stream))
+        if st != TVD_OK:
+            raise TvdError(st, "tvd_graph_launch failed")
+
+    replay = tvd_graph_launch
+
+    def close(self):
+        if self.h:
+            self.lib.tvd_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def variants():
-    """[(index, edge, threads, lds_pad)] of the compiled batched-kernel variants."""
+    """[(index, edge, threads, lds_pad, split)] of the compiled batched-kernel variants."""
     lib = load()
     out = []
     for i in range(lib.tvd_variant_count()):
-        e, t, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        lib.tvd_variant_info(i, ctypes.byref(e), ctypes.byref(t), ctypes.byref(p))
-        out.append((i, e.value, t.value, p.value))
+        v = [ctypes.c_int32() for _ in range(4)]
+        lib.tvd_variant_info(i, *[ctypes.byref(x) for x in v])
+        out.append((i,) + tuple(x.value for x in v))
     return out
 
 

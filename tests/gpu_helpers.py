@@ -51,3 +51,27 @@ def oracle_periodic(grid, steps, n=8, cfl=0.5, gamma=GAMMA, p_floor=0.0):
     N = grid.shape[3]
     return oracle.run_periodic(np.asarray(grid, dtype=np.float64), steps, cfl, 1.0 / N, gamma,
                                n=n, p_floor=p_floor)
+
+
+def cone_blocks(grid, n, picks, steps, dt, dh, gamma=GAMMA, p_floor=0.0):
+    """Oracle outputs of the blocks `picks` (block indices, x fastest) of a
+    periodic grid cut into n^3 blocks after `steps` steps (xyz, zyx, ...) of
+    fixed dt, computed from each block's dependency cone only: a step needs
+    three ghost cells per side, so `steps` steps need a region of
+    n + 6 * steps cells around the block.  Returns {pick: (5, n, n, n)}."""
+    _, Nz, Ny, Nx = grid.shape
+    nbx, nby = Nx // n, Ny // n
+    out = {}
+    for b in picks:
+        bx, by, bz = b % nbx, (b // nbx) % nby, b // (nbx * nby)
+        h = 3 * steps
+        # region [start - h, start + n + h) with periodic wrap
+        idx = [np.arange(s * n - h, s * n + n + h) for s in (bz, by, bx)]
+        sub = grid[:, idx[0] % Nz][:, :, idx[1] % Ny][:, :, :, idx[2] % Nx]
+        for s in range(steps):
+            # the sub-grid is one ghosted block: a step keeps the cells with
+            # full support and drops three cells per side
+            sub = oracle.advance_blocks(np.ascontiguousarray(sub[None]), s % 2, dt, dh, gamma,
+                                        p_floor)[0]
+        out[b] = sub
+    return out

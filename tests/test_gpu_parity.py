@@ -343,20 +343,44 @@ def test_conservation_over_steps_fp64(ctx):
 # graph capture, flags, argument errors, empty batch
 # ---------------------------------------------------------------------------
 
-def test_graph_replay_matches_eager(ctx):
-    """A two-step sequence captured into a HIP graph (through torch's graph
-    wrapper) and replayed three times, with eager work in between, equals
-    the eager sequence bit for bit after every replay."""
-    note("graph capture of a 2-step sequence")
+@pytest.mark.parametrize("gather", [False, True])
+def test_graph_replay_matches_eager(ctx, gather):
+    """A two-step sequence recorded into a HIP graph by the library's native
+    capture and replayed three times, with eager work in between, equals the
+    eager sequence bit for bit after every replay."""
+    note(f"native graph capture of a 2-step sequence, gather={gather}")
     g = wl.smooth_random(32, seed=14, amplitude=0.2).astype(np.float32).astype(np.float64)
     bs = layout.periodic_grid_blockset(32, 16)
-    eager = DeviceBlocks(ctx, bs, dtype=torch.float32)
-    graph = DeviceBlocks(ctx, bs, dtype=torch.float32)
+    eager = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=gather)
+    graph = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=gather)
     eager.upload(layout.grid_to_blocks(g, 16))
     graph.upload(layout.grid_to_blocks(g, 16))
-    # warm up the graph instance's first (even) step eagerly so that the
-    # captured pair starts with a fused speed available
     for d in (eager, graph):
+        d.run(2)   # the first pair seeds the fused signal speed
+    torch.cuda.synchronize()
+    gr = graph.capture(2)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        eager.run(2)
+        torch.cuda.synchronize()
+        x = eager.interior.sum()  # eager work between replays
+        graph.replay(gr)
+        torch.cuda.synchronize()
+        assert torch.equal(eager.interior, graph.interior), rep
+        assert torch.equal(eager.dt, graph.dt), rep
+        del x
+    gr.close()
+
+
+def test_torch_graph_capture_also_works(ctx):
+    """The entry points are capture-safe under torch's graph wrapper too."""
+    note("torch graph capture")
+    g = wl.smooth_random(32, seed=18, amplitude=0.2).astype(np.float32).astype(np.float64)
+    bs = layout.periodic_grid_blockset(32, 16)
+    eager = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=True)
+    graph = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=True)
+    for d in (eager, graph):
+        d.upload(layout.grid_to_blocks(g, 16))
         d.run(2)
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
@@ -365,18 +389,46 @@ def test_graph_replay_matches_eager(ctx):
     with torch.cuda.graph(cg, stream=s):
         graph.step()
         graph.step()
-    torch.cuda.synchronize()
-    graph.step_index -= 2  # capture does not run the work
-    for rep in range(3):
+    graph.step_index -= 2
+    for rep in range(2):
         eager.run(2)
-        torch.cuda.synchronize()
-        x = eager.interior.sum()  # eager work between replays
         cg.replay()
         graph.step_index += 2
         torch.cuda.synchronize()
         assert torch.equal(eager.interior, graph.interior), rep
-        assert torch.equal(eager.dt, graph.dt), rep
-        del x
+
+
+@pytest.mark.parametrize("dtype,edge", [(torch.float32, 16), (torch.float32, 8), (torch.float64, 8)])
+def test_all_variants_bitwise_equal_and_autotune(ctx, dtype, edge):
+    """Every compiled launch variant (workgroup size, LDS padding, pencils per
+    thread) computes the same arithmetic per cell: results are bit-identical.
+    The tuner then picks one of them."""
+    note(f"variants and autotune dtype={dtype} edge={edge}")
+    code = tvd.dtype_code(dtype)
+    g = wl.lognormal(32, seed=19, sigma_ln=0.6)
+    if dtype == torch.float32:
+        g = g.astype(np.float32).astype(np.float64)
+    bs = layout.periodic_grid_blockset(32, edge)
+    ref = None
+    cands = [v for v in tvd.variants() if v[1] == edge]
+    assert cands
+    for v in cands:
+        ctx.tvd_set_variant(code, edge, v[0])
+        dev = DeviceBlocks(ctx, bs, dtype=dtype, gather=True)
+        dev.upload(layout.grid_to_blocks(g, edge))
+        dev.run(2)
+        torch.cuda.synchronize()
+        out = dev.interior.cpu().numpy()
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref), v
+    ctx.tvd_set_variant(code, edge, -1)
+    dev = DeviceBlocks(ctx, bs, dtype=dtype, gather=True)
+    dev.upload(layout.grid_to_blocks(g, edge))
+    dev.dt.fill_(1e-3)
+    idx, ms = ctx.tvd_autotune(dev.batch, dev.nbr, dev.interior, dev.spare, GAMMA, reps=2)
+    assert idx in [v[0] for v in cands] and ms > 0
+    ctx.tvd_set_variant(code, edge, -1)
 
 
 def test_health_flags(ctx):
@@ -439,3 +491,68 @@ def test_argument_errors(ctx):
     assert ctx.tvd_patch_advance(tvd.Batch(tvd.TVD_F64, 0, 8, dt=1e-3, dh=1.0), dev_in, dev_out, 0,
                                  GAMMA) == tvd.TVD_OK
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, sampled outputs from each block's dependency cone
+# ---------------------------------------------------------------------------
+
+def _full_size_sampled(ctx, grid, n, dtype, steps, dt, picks, p_floor=0.0, tol=1e-5):
+    N = grid.shape[3]
+    bs = layout.periodic_grid_blockset(N, n)
+    dev = DeviceBlocks(ctx, bs, dtype=dtype, gather=True, p_floor=p_floor)
+    dev.upload(layout.grid_to_blocks(grid, n))
+    dev.dt.fill_(dt)
+    ctx.tvd_read_flags()
+    for s in range(steps):
+        dev.advance(s % 2, fuse_sums=True)
+    torch.cuda.synchronize()
+    st, fl, bad = ctx.tvd_read_flags()
+    assert bad == 0
+    sums = dev.sums.cpu().numpy()
+    out = dev.interior.cpu().numpy()
+    from gpu_helpers import cone_blocks
+    ref = cone_blocks(grid, n, picks, steps, dt, 1.0 / N, p_floor=p_floor)
+    m3 = 5 * n ** 3
+    got = np.stack([out[p * m3:(p + 1) * m3].reshape(5, -1) for p in picks], 1).reshape(5, -1)
+    want = np.stack([ref[p].reshape(5, -1) for p in picks], 1).reshape(5, -1)
+    nrm = norms(got, want)
+    note(str({k: (f"{v['relL1']:.2e}", f"{v['relLinf']:.2e}") for k, v in nrm.items()}))
+    assert worst(nrm) <= tol
+    # conservation: the fused FP64 sums of the output against the input's exact
+    # sums, on each variable's own scale (momentum: sum of rho c_s)
+    w = (1.0 / N) ** 3
+    rho = grid[0]
+    kin = 0.5 * (grid[1] ** 2 + grid[2] ** 2 + grid[3] ** 2) / rho
+    P = np.maximum((GAMMA - 1.0) * (grid[4] - kin), p_floor)
+    mscale = np.sum(rho * np.sqrt(GAMMA * P / rho)) * w
+    for k in range(5):
+        s0 = math.fsum((grid[k].ravel() * w).tolist())
+        scale = np.abs(grid[k]).sum() * w if k in (0, 4) else mscale
+        assert abs(sums[k] - s0) <= (1e-6 if dtype == torch.float32 else 1e-13) * scale, k
+    return nrm
+
+
+def test_full_size_256cube_bench_config_fp32(ctx):
+    """The bench workload at full size (256^3, 4096 patch groups of 16^3, FP32,
+    gathering advance, the bench's launch variant): two steps (xyz, zyx),
+    24 sampled blocks against the oracle's dependency-cone result."""
+    note("full size 256^3 lognormal fp32, sampled blocks")
+    g = wl.lognormal(256, seed=2024).astype(np.float32).astype(np.float64)
+    S = oracle.max_signal_speed(g, GAMMA)
+    dt = 0.5 / 256 / S
+    picks = sorted(set(int(x) for x in wl.rng(1).integers(0, 4096, size=24)) | {0, 4095})
+    _full_size_sampled(ctx, g, 16, torch.float32, 2, dt, picks, tol=1e-5)
+
+
+def test_full_size_512cube_sedov_fp32(ctx):
+    """512^3 = 262144 patches of 8^3 (run as 16^3 groups), point blast on a
+    lognormal background with p_floor 1e-10, FP32: two steps, sampled blocks
+    including the blast centre, against the oracle."""
+    note("full size 512^3 sedov fp32, sampled blocks")
+    g = wl.sedov_lognormal(512, seed=5).astype(np.float32).astype(np.float64)
+    S = oracle.max_signal_speed(g, GAMMA, 1e-10)
+    dt = 0.5 / 512 / S
+    centre = 15 + 32 * (15 + 32 * 15)  # the 16^3 group holding cell 255
+    picks = sorted({centre, centre + 1, centre + 32 * 33, 0, 12345, 32767})
+    _full_size_sampled(ctx, g, 16, torch.float32, 2, dt, picks, p_floor=1e-10, tol=1e-4)
