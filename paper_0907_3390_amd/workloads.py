@@ -184,3 +184,133 @@ def sound_wave_boxes(counts=(2286, 1143, 571), edges=(8, 16, 32), seed: int = 4,
         out.grids.append(conserved(rho0 + drho, v[0], v[1], v[2], P0 + cs * cs * drho, gamma))
         out.dh.append(1.0 / n)
     return out
+
+
+# ---------------------------------------------------------------------------
+# multi-level patch hierarchy (static), ghost zones pre-filled
+# ---------------------------------------------------------------------------
+
+@dataclass
+class MultiLevel:
+    """A static octree of 8^3 patches over the periodic unit box.
+
+    ``patches`` lists (level, px, py, pz) patch coordinates; ``ghosted`` holds
+    the (5, 14, 14, 14) FP64 ghosted block of every patch; ``dh`` the zone
+    size of each patch (1 / (base * 2^level))."""
+    base: int
+    patches: list = field(default_factory=list)
+    ghosted: np.ndarray | None = None
+    dh: np.ndarray | None = None
+
+    @property
+    def levels(self):
+        return np.array([p[0] for p in self.patches])
+
+
+def _gaussian_field(centres, amps, radii):
+    def rho(x, y, z):
+        out = np.ones(np.broadcast(x, y, z).shape)
+        mx, my, mz = float(np.mean(x)), float(np.mean(y)), float(np.mean(z))
+        ext = max(float(np.ptp(x)), float(np.ptp(y)), float(np.ptp(z)))
+        for (cx, cy, cz), a, r in zip(centres, amps, radii):
+            # skip overdensities whose tail (exp(-32) relative) cannot reach
+            d = np.sqrt(sum(((m_ - c_ + 0.5) % 1.0 - 0.5) ** 2
+                            for m_, c_ in ((mx, cx), (my, cy), (mz, cz))))
+            if d - ext > 8.0 * r:
+                continue
+            # periodic distance to the centre
+            dx = (x - cx + 0.5) % 1.0 - 0.5
+            dy = (y - cy + 0.5) % 1.0 - 0.5
+            dz = (z - cz + 0.5) % 1.0 - 0.5
+            out = out + a * np.exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * r * r))
+        return out
+    return rho
+
+
+def multilevel(base: int = 128, n_over: int = 32, seed: int = 3, max_level: int = 3,
+               radius: float = 0.032, P0: float = 1.0, gamma: float = GAMMA) -> MultiLevel:
+    """Base grid of base^3 cells (8^3 patches) with up to ``max_level`` refined
+    levels around ``n_over`` Gaussian overdensities rho = 1 + sum A_k
+    exp(-r^2 / 2 r_k^2): centres uniform, A_k log-uniform in [10, 1e3], r_k =
+    radius * U(0.5, 1.5).  A patch of level l is refined into its 2^3
+    children when its densest cell reaches 8^(l+1) (the paper's cosmological
+    criterion rho_l >= 8^(l+1) rho_b, Sec. 5).  Gas at rest, P = P0.
+
+    Cells take the density at their centres on every level.  Ghost cells
+    covered by a patch of the same level are copied from it (sibling copy);
+    the others are trilinearly interpolated from the cell centres of the next
+    coarser level (conserved variables).  Ghost values therefore equal the
+    analytic field sampled at same-level centres, or its trilinear
+    interpolant one level down."""
+    r = rng(seed)
+    centres = r.uniform(0, 1, size=(n_over, 3))
+    amps = 10.0 ** r.uniform(1, 3, size=n_over)
+    radii = radius * r.uniform(0.5, 1.5, size=n_over)
+    rho_f = _gaussian_field(centres, amps, radii)
+    n = 8
+    ml = MultiLevel(base=base)
+    # level 0: every patch; refine level by level
+    npb = base // n
+    cur = [(0, px, py, pz) for pz in range(npb) for py in range(npb) for px in range(npb)]
+    allp = list(cur)
+    for lev in range(max_level):
+        nxt = []
+        h = 1.0 / (base * 2 ** lev)
+        c = (np.arange(n) + 0.5) * h
+        thr = 8.0 ** (lev + 1)
+        for (_, px, py, pz) in cur:
+            z, y, x = np.meshgrid(pz * n * h + c, py * n * h + c, px * n * h + c, indexing="ij")
+            if rho_f(x, y, z).max() >= thr:
+                for cz in range(2):
+                    for cy in range(2):
+                        for cx in range(2):
+                            nxt.append((lev + 1, 2 * px + cx, 2 * py + cy, 2 * pz + cz))
+        allp += nxt
+        cur = nxt
+    ml.patches = allp
+    present = set(allp)
+
+    def prim_to_cons(rho):
+        return conserved(rho, 0.0, 0.0, 0.0, np.full(rho.shape, P0), gamma)
+
+    m = n + 6
+    g = np.empty((len(allp), 5, m, m, m))
+    dh = np.empty(len(allp))
+    off = np.arange(m) - 3 + 0.5  # ghosted cell centres in units of h, relative to the patch
+    for i, (lev, px, py, pz) in enumerate(allp):
+        h = 1.0 / (base * 2 ** lev)
+        dh[i] = h
+        z, y, x = np.meshgrid((pz * n + off) * h, (py * n + off) * h, (px * n + off) * h,
+                              indexing="ij")
+        fine = rho_f(x % 1.0, y % 1.0, z % 1.0)
+        if lev > 0:
+            # cells whose same-level patch does not exist: interpolate from the
+            # coarser level's cell centres (trilinear, periodic)
+            npl = base * 2 ** lev // n
+            reg = np.where(np.arange(m) < 3, 0, np.where(np.arange(m) >= n + 3, 2, 1))
+            have = np.zeros((3, 3, 3), dtype=bool)
+            for rz in range(3):
+                for ry in range(3):
+                    for rx in range(3):
+                        have[rz, ry, rx] = ((lev, (px + rx - 1) % npl, (py + ry - 1) % npl,
+                                             (pz + rz - 1) % npl) in present)
+            cover = have[reg[:, None, None], reg[None, :, None], reg[None, None, :]]
+            if not cover.all():
+                H = 2.0 * h
+                fx, fy, fz = x / H - 0.5, y / H - 0.5, z / H - 0.5
+                ix, iy, iz = np.floor(fx), np.floor(fy), np.floor(fz)
+                tx, ty, tz = fx - ix, fy - iy, fz - iz
+                interp = np.zeros((m, m, m))
+                for dz_ in (0, 1):
+                    for dy_ in (0, 1):
+                        for dx_ in (0, 1):
+                            wgt = ((tx if dx_ else 1 - tx) * (ty if dy_ else 1 - ty) *
+                                   (tz if dz_ else 1 - tz))
+                            interp += wgt * rho_f(((ix + dx_ + 0.5) * H) % 1.0,
+                                                  ((iy + dy_ + 0.5) * H) % 1.0,
+                                                  ((iz + dz_ + 0.5) * H) % 1.0)
+                fine = np.where(cover, fine, interp)
+        g[i] = prim_to_cons(fine)
+    ml.ghosted = g
+    ml.dh = dh
+    return ml

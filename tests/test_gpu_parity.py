@@ -556,3 +556,62 @@ def test_full_size_512cube_sedov_fp32(ctx):
     centre = 15 + 32 * (15 + 32 * 15)  # the 16^3 group holding cell 255
     picks = sorted({centre, centre + 1, centre + 32 * 33, 0, 12345, 32767})
     _full_size_sampled(ctx, g, 16, torch.float32, 2, dt, picks, p_floor=1e-10, tol=1e-4)
+
+
+# ---------------------------------------------------------------------------
+# multi-level batch: per-block dt and dh in one launch
+# ---------------------------------------------------------------------------
+
+def test_multilevel_batch_one_launch(ctx):
+    """Patches of levels 0-3 (dh halving per level) around Gaussian
+    overdensities, ghosts pre-filled by sibling copy or trilinear coarse-to-
+    fine interpolation; dt_b = C dh_b / S_global computed on the device.  One
+    batched launch (FP32 and FP64) and the plain FP64 kernel launched level by
+    level all match the oracle."""
+    note("multi-level batch")
+    ml = wl.multilevel(base=32, n_over=4, seed=3, radius=0.05)
+    levels = ml.levels
+    assert set(np.unique(levels)) == {0, 1, 2, 3}
+    nb = len(ml.patches)
+    S = oracle.max_signal_speed(np.ascontiguousarray(
+        ml.ghosted[:, :, 3:-3, 3:-3, 3:-3].transpose(1, 0, 2, 3, 4)).reshape(5, -1), GAMMA)
+    dt = 0.5 * ml.dh / S
+    ref = np.stack(oracle.advance_ragged(list(ml.ghosted), 0, dt, ml.dh, GAMMA))
+    for dtype, kernel, tol in [(torch.float64, tvd.TVD_KERNEL_BATCHED, 1e-12),
+                               (torch.float32, tvd.TVD_KERNEL_BATCHED, 1e-5),
+                               (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)]:
+        code = tvd.dtype_code(dtype)
+        gin = ml.ghosted.astype(np.float32).astype(np.float64) if dtype == torch.float32 else ml.ghosted
+        u_in = torch.from_numpy(np.ascontiguousarray(gin)).to(dtype).cuda().reshape(-1)
+        u_out = torch.zeros(nb * 5 * 512, dtype=dtype, device="cuda")
+        d_dh = torch.from_numpy(ml.dh).cuda()
+        d_dt = torch.zeros(nb, dtype=torch.float64, device="cuda")
+        smax = torch.zeros(1, dtype=torch.float64, device="cuda")
+        b = tvd.Batch(code, nb, 8, d_dt=d_dt, d_dh=d_dh)
+        ctx.tvd_max_signal_speed(b, u_in, tvd.TVD_LAYOUT_GHOSTED, GAMMA, smax)
+        ctx.tvd_dt_from_speed(b, smax, 0.5, d_dt)
+        if kernel == tvd.TVD_KERNEL_PLAIN:
+            # one launch per level on that level's contiguous range of patches
+            for lev in range(4):
+                ids = np.nonzero(levels == lev)[0]
+                lo, hi = int(ids[0]), int(ids[-1]) + 1
+                assert hi - lo == ids.size
+                bl = tvd.Batch(code, hi - lo, 8, d_dt=d_dt[lo:hi], d_dh=d_dh[lo:hi])
+                ctx.tvd_patch_advance(bl, u_in[lo * 5 * 14 ** 3:], u_out[lo * 5 * 512:], 0, GAMMA,
+                                      flags=kernel)
+        else:
+            ctx.tvd_patch_advance(b, u_in, u_out, 0, GAMMA, flags=kernel)
+        torch.cuda.synchronize()
+        want, dt_ref = ref, dt
+        if dtype == torch.float32:
+            # the oracle's own dt and step from the same FP32-rounded input
+            S32 = oracle.max_signal_speed(np.ascontiguousarray(
+                gin[:, :, 3:-3, 3:-3, 3:-3].transpose(1, 0, 2, 3, 4)).reshape(5, -1), GAMMA)
+            dt_ref = 0.5 * ml.dh / S32
+            want = np.stack(oracle.advance_ragged(list(gin), 0, dt_ref, ml.dh, GAMMA))
+        np.testing.assert_allclose(d_dt.cpu().numpy(), dt_ref, rtol=1e-14)
+        got = u_out.cpu().numpy().reshape(nb, 5, 8, 8, 8)
+        nrm = norms(got.transpose(1, 0, 2, 3, 4).reshape(5, -1),
+                    want.transpose(1, 0, 2, 3, 4).reshape(5, -1))
+        note(f"{dtype} kernel {kernel}: " + str({k: f"{v['relL1']:.2e}" for k, v in nrm.items()}))
+        assert worst(nrm) <= tol
