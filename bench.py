@@ -69,9 +69,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(variant):
     """HBM bytes per launch of the advance from the committed rocprofv3 counter
-    summary, only if it was taken on the current kernel sources."""
+    summary, only if it was taken on the current kernel sources and the same
+    launch variant."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     kv = {}
@@ -81,7 +82,12 @@ def measured_traffic():
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
-    return float(kv["hbm_bytes_per_launch_mean"]), "rocprofv3 FETCH_SIZE x2 + WRITE_SIZE"
+    if variant is not None:
+        want = ",".join(str(variant[k]) for k in ("edge", "threads", "lds_pad", "split"))
+        if kv.get("variant") != want:
+            return None, f"counters were taken on variant {kv.get('variant')}, not {want}"
+    return float(kv["hbm_bytes_per_launch_mean"]), ("rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
+                                                    + os.path.relpath(TRAFFIC_FILE, ROOT))
 
 
 def make_ic():
@@ -242,7 +248,8 @@ def main():
     achieved = bytes_launch / (adv_avg_ms * 1e-3) / 1e9
     flops_launch = nb * flops_per_block(n)
     tflops = flops_launch / (adv_avg_ms * 1e-3) / 1e12
-    traffic, traffic_note = measured_traffic() if (n == 16 and gather) else (None, "not profiled")
+    traffic, traffic_note = (measured_traffic(r32.get("variant")) if (n == 16 and gather)
+                             else (None, "not profiled"))
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
