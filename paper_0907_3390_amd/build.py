@@ -26,9 +26,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=" + ARCH,
          "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
+def build(verbose: bool = False, extra=(), out: str = LIB) -> str:
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = (["hipcc"] + FLAGS + list(extra) + ["-I", INCLUDE, "-I", CSRC, "-o", tmp]
            + [os.path.join(CSRC, s) for s in SOURCES])
     if verbose:
@@ -37,8 +37,8 @@ def build(verbose: bool = False, extra=()) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libtvd.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

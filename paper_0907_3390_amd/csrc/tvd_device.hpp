@@ -29,6 +29,7 @@ template <> struct Num<float> {
   __device__ static inline float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
   __device__ static inline float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
   __device__ static inline float abs(float x) { return __builtin_fabsf(x); }
+  __device__ static inline float max(float a, float b) { return __builtin_fmaxf(a, b); }
 };
 template <> struct Num<double> {
   __device__ static inline double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -36,11 +37,13 @@ template <> struct Num<double> {
   __device__ static inline double div(double a, double b) { return a / b; }
   __device__ static inline double sqrt(double x) { return __builtin_sqrt(x); }
   __device__ static inline double abs(double x) { return __builtin_fabs(x); }
+  __device__ static inline double max(double a, double b) { return __builtin_fmax(a, b); }
 };
 
 // Per-block coefficients of one sweep.
 template <typename T> struct Coef {
   T gamma;    // ratio of specific heats
+  T qgamma;   // gamma / 4
   T gm1;      // gamma - 1
   T pfloor;   // pressure floor
   T lam;      // dt / dh
@@ -50,7 +53,9 @@ template <typename T> struct Coef {
 // Freezing speed and split fluxes of one cell, Eq. (LRFlux) multiplied out:
 // F^R = (c u + F)/2, F^L = (c u - F)/2 with c = |v_n| + c_s.  Components are
 // in pencil order: 0 rho, 1 normal momentum, 2-3 transverse momenta, 4 e.
-// The pressure entering F and c_s is max(P, p_floor).
+// The pressure entering F and c_s is max(P, p_floor) (the IEEE max, so a
+// pressure that is not a number becomes p_floor; such states are reported by
+// the health counters).
 //
 // The library is built without implicit FMA contraction; every fused
 // multiply-add here is explicit, so identical inputs give identical results
@@ -65,10 +70,10 @@ __device__ __forceinline__ void split_flux(const T u[kNV], const Coef<T>& cf, T 
   const T vn = u[1] * inv;
   const T mt2 = u[2] * u[2] + u[3] * u[3];
   const T m2 = F::fma(u[1], u[1], mt2);
-  T P = cf.gm1 * F::fma(T(-0.5) * m2, inv, u[4]);
-  P = P < cf.pfloor ? cf.pfloor : P;
-  const T cs = F::sqrt((cf.gamma * P) * inv);
-  const T hc = T(0.5) * (F::abs(vn) + cs);
+  const T P = F::max(cf.gm1 * F::fma(T(-0.5) * m2, inv, u[4]), cf.pfloor);
+  // c/2 = |v_n|/2 + sqrt(gamma P / (4 rho)); the halving is exact
+  const T hcs = F::sqrt((cf.qgamma * P) * inv);
+  const T hc = F::fma(T(0.5), F::abs(vn), hcs);
   const T hv = T(0.5) * vn;
   T hF[kNV];
   hF[0] = T(0.5) * u[1];
@@ -89,6 +94,15 @@ template <typename T>
 __device__ __forceinline__ T vanleer(T a, T b) {
   const T p = a * b;
   return p > T(0) ? Num<T>::div(p, a + b) : T(0);
+}
+// FP32, without a compare and select: max(ab, 0) times the reciprocal of
+// a+b clamped to finite values (a+b = 0 only happens with ab <= 0, where the
+// product must be 0, not 0 * inf); for ab > 0 this is ab * rcp(a+b) exactly.
+template <>
+__device__ __forceinline__ float vanleer<float>(float a, float b) {
+  constexpr float kBig = 3.402823466e38f;
+  const float r = __builtin_amdgcn_fmed3f(Num<float>::rcp(a + b), -kBig, kBig);
+  return Num<float>::max(a * b, 0.0f) * r;
 }
 
 // One sweep over a pencil of M = N+6 cells.  Src::load(j, u) fetches cell j

@@ -153,6 +153,7 @@ __device__ __forceinline__ Coef<T> make_coef(const KParams& kp, int b, double& d
   const double lam = dt / dh;  // FP64, rounded once to T
   Coef<T> cf;
   cf.gamma = T(kp.gamma);
+  cf.qgamma = T(0.25 * kp.gamma);
   cf.gm1 = T(kp.gamma - 1.0);
   cf.pfloor = T(kp.pfloor);
   cf.lam = T(lam);
@@ -257,6 +258,28 @@ struct LdsPencil2 {
     const int o = L::idx(c0, c1, i + kG);
 #pragma unroll
     for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * L::PLANE + o] = u[k];
+  }
+};
+
+// Sweep 2 sink: finished cells go straight to the block's interior in HBM
+// (axis D stride), in global component order, and feed the per-cell
+// diagnostics; no copy-out pass through LDS is needed.
+template <typename T, int N, int D>
+struct GlobalOut {
+  T* p;          // cell 0 of the output pencil, variable 0
+  CellDiag* dg;
+  int diag;
+  double gamma, pfloor;
+  __device__ inline void store(int i, const T u[kNV]) const {
+    constexpr int S = D == 0 ? 1 : D == 1 ? N : N * N;
+    constexpr int N3 = N * N * N;
+    T ug[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) ug[gcomp<D>(k)] = u[k];
+    T* c = p + i * S;
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) c[k * N3] = ug[k];
+    diag_cell<T>(*dg, ug, diag, gamma, pfloor);
   }
 };
 
@@ -402,37 +425,30 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
     }
   }
   __syncthreads();
-  // sweep 2: interior along c0 and c1
+  // sweep 2: interior along c0 and c1, results straight to HBM with the
+  // per-cell diagnostics (a pencil at (c0, c1) is the column x = c0,
+  // y = c1 - 3 along z for xyz, or z = c0, y = c1 - 3 along x for zyx)
+  CellDiag dg;
+  diag_init(dg);
+  auto out_pencil = [&](int c0, int c1) {
+    const int y = c1 - kG;
+    T* base = ORDER == 0 ? bout + c0 + N * y : bout + N * y + N * N * c0;
+    return GlobalOut<T, N, D2>{base, &dg, kp.diag, kp.gamma, kp.pfloor};
+  };
   if constexpr ((SPLIT & 2) != 0) {
     static_assert(2 * N * N == NT, "sweep-2 halves need one thread each");
     const int t = threadIdx.x;
-    const int p = t / 2;
-    const Shifted<LdsPencil2<T, L, D2>> acc{{S, p % N, p / N + kG}, (t & 1) * (N / 2)};
-    Held<T, N / 2> held;
-    pencil_sweep<T, N / 2>(acc, held, cf);
-    __syncthreads();
-    held.flush(acc);
+    const int p = t / 2, off = (t & 1) * (N / 2);
+    const int c0 = p % N, c1 = p / N + kG;
+    const Shifted<LdsPencil2<T, L, D2>> src{{S, c0, c1}, off};
+    const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
+    pencil_sweep<T, N / 2>(src, dst, cf);
   } else {
     for (int p = threadIdx.x; p < N * N; p += NT) {
-      const LdsPencil2<T, L, D2> acc{S, p % N, p / N + kG};
-      pencil_sweep<T, N>(acc, acc, cf);
+      const int c0 = p % N, c1 = p / N + kG;
+      const LdsPencil2<T, L, D2> src{S, c0, c1};
+      pencil_sweep<T, N>(src, out_pencil(c0, c1), cf);
     }
-  }
-  __syncthreads();
-
-  // copy the interior out (coalesced, x fastest) with the fused diagnostics
-  CellDiag dg;
-  diag_init(dg);
-  for (int i = threadIdx.x; i < N3; i += NT) {
-    const int x = i % N, y = (i / N) % N, z = i / (N * N);
-    const int o = ORDER == 0 ? L::idx(x, y + kG, z + kG) : L::idx(z, y + kG, x + kG);
-    T u[kNV];
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) {
-      u[k] = S[k * L::PLANE + o];
-      bout[k * N3 + i] = u[k];
-    }
-    diag_cell<T>(dg, u, kp.diag, kp.gamma, kp.pfloor);
   }
   __syncthreads();
   diag_publish<NT>(dg, b, dh, kp, S);
@@ -651,11 +667,12 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32
 // ---------------------------------------------------------------------------
 
 static const Variant kVariants[] = {
-    {16, 512, 16, 1},  // FP32 edge 16: one workgroup per CU
-    {16, 512, 16, 0},
+    {16, 512, 0, 1},  // FP32 edge 16: one workgroup per CU
+    {16, 512, 0, 3},
+    {16, 512, 0, 2},
+    {16, 512, 0, 0},
+    {16, 512, 16, 1},
     {16, 512, 16, 3},
-    {16, 512, 16, 2},
-    {16, 512, 0, 1},
     {8, 128, 8, 0},
     {8, 128, 8, 2},
     {8, 256, 8, 0},
@@ -690,11 +707,12 @@ static hipError_t launch_typed(int order, const Variant& v, bool gather, const K
   if (v.edge == E && v.threads == TH && v.pad == P && v.split == SP)                \
     return launch_b<T, E, TH, P, SP>(order, gather, kp, s);
   if constexpr (sizeof(T) == 4) {  // FP64 edge 16 does not fit in LDS
-    TVD_VARIANT(16, 512, 16, 1)
-    TVD_VARIANT(16, 512, 16, 0)
-    TVD_VARIANT(16, 512, 16, 3)
-    TVD_VARIANT(16, 512, 16, 2)
     TVD_VARIANT(16, 512, 0, 1)
+    TVD_VARIANT(16, 512, 0, 3)
+    TVD_VARIANT(16, 512, 0, 2)
+    TVD_VARIANT(16, 512, 0, 0)
+    TVD_VARIANT(16, 512, 16, 1)
+    TVD_VARIANT(16, 512, 16, 3)
   }
   TVD_VARIANT(8, 128, 8, 0)
   TVD_VARIANT(8, 128, 8, 2)
