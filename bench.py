@@ -18,7 +18,9 @@ Reported (one JSON line on stdout):
   the FP64 result after the same steps;
 * roofline: the advance kernel's algorithmic HBM bytes per launch over its
   average duration (HIP events on the launch stream) against 8 TB/s;
-* cpu_baseline: the FP64 oracle on the host cores over a bounded sample.
+* cpu_baseline: the FP64 oracle on the host cores over a bounded sample;
+* uneven_batch: cell-updates/s of 4000 periodic boxes of mixed sizes in one
+  persistent launch per step, 50-step HIP graphs, block edge tuned.
 """
 from __future__ import annotations
 
@@ -157,6 +159,54 @@ def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=Fal
     return dev, info
 
 
+def run_uneven(ctx, graph_steps=50):
+    """The uneven batch: 4000 independent periodic boxes (2286 of 8^3, 1143 of
+    16^3, 571 of 32^3) with sound waves of amplitude 1e-3, FP32, gathering
+    advance.  The block edge is chosen by measurement (every box as 8^3
+    patches, or the 16^3 and 32^3 boxes as 16^3 patch groups in one persistent
+    mixed-edge launch), then `graph_steps` steps are captured as one HIP graph
+    and replayed; the mixed layout is also timed with one launch per edge."""
+    import torch
+    from paper_0907_3390_amd import tvd, tuning, workloads as wl
+    boxes = wl.sound_wave_boxes(seed=4)
+    grids = [g.astype(np.float32).astype(np.float64) for g in boxes.grids]
+    cells = sum(g.shape[1] ** 3 for g in grids)
+    cands = {"all 8^3": lambda L: 8, "8^3 boxes as 8, others as 16^3 groups":
+             lambda L: 8 if L == 8 else 16}
+    best, times = tuning.tune_block_edge(ctx, grids, boxes.dh, cands, gamma=GAMMA, cfl=CFL)
+    log(f"bench: uneven batch, block-edge tuner {times} -> {best}")
+    res = {"workload": "4000 periodic boxes 2286 x 8^3 + 1143 x 16^3 + 571 x 32^3, sound waves "
+                       "amplitude 1e-3, FP32, gathering advance, seed 4",
+           "cells": cells, "block_edge_tuner_ms_per_step": times, "chosen_layout": best}
+    for name, kernel in (("persistent", tvd.TVD_KERNEL_AUTO),
+                         ("per_edge_launches", tvd.TVD_KERNEL_BATCHED)):
+        if name == "per_edge_launches" and best == "all 8^3":
+            continue
+        dev = tuning.boxes_device(ctx, grids, boxes.dh, cands[best], kernel=kernel, gamma=GAMMA,
+                                  cfl=CFL)
+        dev.run(2)
+        side = torch.cuda.Stream()
+        g = dev.capture(graph_steps, stream=side)
+        dev.replay(g, stream=side)  # untimed
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(side)
+        dev.replay(g, stream=side)
+        b.record(side)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        g.close()
+        res[name] = {"value": cells * graph_steps / (ms * 1e-3), "unit": "cell-updates/s",
+                     "ms_per_step": ms / graph_steps, "graph_steps": graph_steps,
+                     "blocks": dev.bs.n_blocks}
+        log(f"bench: uneven batch {name}: {res[name]['value'] / 1e9:.2f} G cell-updates/s")
+        del dev
+        torch.cuda.empty_cache()
+    st, fl, bad = ctx.tvd_read_flags()
+    res["health"] = {"floored": fl, "nonphysical": bad}
+    return res
+
+
 def cpu_baseline(grid32, budget_s=15.0):
     """The FP64 oracle (as it stands) on the host cores over a bounded sample
     of the same workload: whole steps of the 256^3 grid as 32768 patches of
@@ -214,6 +264,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-variant tuner")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-batch (4000 mixed boxes) throughput")
     ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
     ap.add_argument("--no-gather", action="store_true",
                     help="headline run with a separate ghost fill instead of the gathering advance")
@@ -316,6 +368,10 @@ def main():
         out["l1_vs_fp64"] = {k: float(v) for k, v in nrm.items()}
         out["l1_vs_fp64"]["after_steps"] = max(args.warmup, 2) + 2 * args.steps
         log(f"bench: FP64 plain {v64 / 1e9:.3f} G cell-updates/s; relL1 {nrm}")
+    if not args.no_uneven:
+        log("bench: uneven batch of 4000 boxes")
+        torch.cuda.empty_cache()
+        out["uneven_batch"] = run_uneven(ctx)
     if not args.no_cpu_baseline:
         log("bench: FP64 oracle on the host cores (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(grid32)

@@ -28,7 +28,10 @@
  * - The element type of every state buffer is the batch dtype (TVD_F32:
  *   float, TVD_F64: double); time steps, zone sizes, gamma, speeds and sums
  *   are always double.
- * - A context is not thread safe: use one per host thread.
+ * - A context is not thread safe: use one per host thread.  Its workspace
+ *   (per-block partials, the persistent kernel's work plan) is shared by the
+ *   calls made on it, so calls on one context that could run at the same time
+ *   on different streams race: order them (one stream, or events).
  */
 #ifndef TVD_H
 #define TVD_H
@@ -57,9 +60,14 @@ enum { TVD_LAYOUT_GHOSTED = 0, TVD_LAYOUT_INTERIOR = 1 };
 
 /* flags of tvd_patch_advance: which kernel runs */
 enum {
-    TVD_KERNEL_AUTO = 0,      /* the batched kernel, tuned variant if tuned      */
-    TVD_KERNEL_BATCHED = 1,   /* LDS-staged batched kernel, FP32 or FP64          */
-    TVD_KERNEL_PLAIN = 2      /* plain FP64 kernel, one workgroup per 8^3 block  */
+    TVD_KERNEL_AUTO = 0,       /* uniform edge: BATCHED; mixed edges: PERSISTENT  */
+    TVD_KERNEL_BATCHED = 1,    /* LDS-staged batched kernel, FP32 or FP64; with
+                                  mixed edges one launch per edge               */
+    TVD_KERNEL_PLAIN = 2,      /* plain FP64 kernel, one workgroup per 8^3 block  */
+    TVD_KERNEL_PERSISTENT = 3  /* FP32, any edges, in one persistent launch:
+                                  one workgroup per CU draws blocks from
+                                  per-XCD work queues, edge 16 first; an
+                                  edge-8 block takes a quarter of a workgroup */
 };
 
 typedef struct tvd_ctx tvd_ctx;
@@ -156,9 +164,15 @@ int tvd_autotune(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
  *   gamma    ratio of specific heats (> 1, or exactly 1 for pressureless gas).
  *   p_floor  pressure floor: fluxes and sound speeds use max(P, p_floor); the
  *            stored energy is never changed.
- *   flags    TVD_KERNEL_* (PLAIN requires TVD_F64 and uniform edge 8).
+ *   flags    TVD_KERNEL_* (PLAIN requires TVD_F64 and uniform edge 8;
+ *            PERSISTENT requires TVD_F32).
  *            FP32 batches take edges 8 and 16, mixed through d_edge; FP64
  *            batches take uniform edge 8 only (else TVD_ERR_UNSUPPORTED).
+ *            With mixed edges a block whose d_edge entry is neither 8 nor
+ *            16 is not advanced (the persistent kernel also counts it once
+ *            as non-physical).  The persistent kernel uses workspace of
+ *            n_blocks entries: reserve it (tvd_reserve) before capturing
+ *            such an advance.
  *   d_smax   optional (NULL = skip): receives max over the output interior of
  *            c_s + max(|v_x|, |v_y|, |v_z|) in FP64 (Eq. CFL), fused.
  *   d_sums   optional (NULL = skip): receives the five sums over the output

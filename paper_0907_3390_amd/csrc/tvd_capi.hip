@@ -26,6 +26,10 @@ struct tvd_ctx {
   double* ws_sums = nullptr;
   unsigned long long* counters = nullptr;
   int ws_blocks = 0;
+  // work plan of the persistent launch: list [ws_blocks], count [2], next [8]
+  int32_t* plan_list = nullptr;
+  int32_t* plan_small = nullptr;  // count[2] then next[8] (as unsigned)
+  int cus = 256;                  // compute units (one persistent workgroup each)
   // tuned variants, per dtype (index 0: FP32, 1: FP64) and edge (0: 8, 1: 16)
   int tuned[2][2] = {{-1, -1}, {-1, -1}};
 };
@@ -79,13 +83,17 @@ int reserve(tvd_ctx* ctx, int n, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
   (void)hipFree(ctx->ws_smax);
   (void)hipFree(ctx->ws_sums);
+  (void)hipFree(ctx->plan_list);
   ctx->ws_smax = nullptr;
   ctx->ws_sums = nullptr;
+  ctx->plan_list = nullptr;
   ctx->ws_blocks = 0;
   const int cap = n < 1024 ? 1024 : n;
   e = hipMalloc(&ctx->ws_smax, sizeof(double) * (size_t)cap);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
   e = hipMalloc(&ctx->ws_sums, sizeof(double) * 10 * (size_t)cap);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
+  e = hipMalloc(&ctx->plan_list, sizeof(int32_t) * (size_t)cap);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(workspace)");
   ctx->ws_blocks = cap;
   return TVD_OK;
@@ -188,10 +196,18 @@ int tvd_create(tvd_ctx** out, int device) {
     delete ctx;
     return TVD_ERR_HIP;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    ctx->cus = cus;
   if (hipMalloc(&ctx->counters, 4 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&ctx->plan_small, 16 * sizeof(int32_t)) != hipSuccess ||
+      hipMemset(ctx->plan_small, 0, 16 * sizeof(int32_t)) != hipSuccess ||
       reserve(ctx, 1024, nullptr) != TVD_OK || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(ctx->counters);
+    (void)hipFree(ctx->plan_small);
+    (void)hipFree(ctx->plan_list);
     (void)hipFree(ctx->ws_smax);
     (void)hipFree(ctx->ws_sums);
     delete ctx;
@@ -208,6 +224,8 @@ int tvd_destroy(tvd_ctx* ctx) {
     (void)hipDeviceSynchronize();
     (void)hipFree(ctx->ws_smax);
     (void)hipFree(ctx->ws_sums);
+    (void)hipFree(ctx->plan_list);
+    (void)hipFree(ctx->plan_small);
     (void)hipFree(ctx->counters);
   }
   delete ctx;
@@ -266,7 +284,8 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   if ((st = check_gamma(ctx, gamma, p_floor))) return st;
   if (sweep_order != TVD_XYZ && sweep_order != TVD_ZYX)
     return fail(ctx, TVD_ERR_INVALID_ARG, "sweep_order %d", sweep_order);
-  if (flags != TVD_KERNEL_AUTO && flags != TVD_KERNEL_BATCHED && flags != TVD_KERNEL_PLAIN)
+  if (flags != TVD_KERNEL_AUTO && flags != TVD_KERNEL_BATCHED && flags != TVD_KERNEL_PLAIN &&
+      flags != TVD_KERNEL_PERSISTENT)
     return fail(ctx, TVD_ERR_INVALID_ARG, "flags %d", flags);
   if (batch->n_blocks == 0) return TVD_OK;
   if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
@@ -275,6 +294,8 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
     if (batch->dtype != TVD_F64 || batch->d_edge || batch->edge != 8)
       return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel needs TVD_F64 and uniform edge 8");
   }
+  if (flags == TVD_KERNEL_PERSISTENT && batch->dtype != TVD_F32)
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "the persistent kernel needs TVD_F32");
   if (batch->dtype == TVD_F64 && (batch->d_edge || batch->edge != 8))
     return fail(ctx, TVD_ERR_UNSUPPORTED,
                 "FP64 batches take uniform edge 8 (edge 16 exceeds the 160 KB LDS)");
@@ -292,7 +313,9 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   if (!g.ok) return fail(ctx, TVD_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t s = (hipStream_t)stream;
   const bool fuse = d_smax || d_sums;
-  if (fuse && (st = reserve(ctx, batch->n_blocks, s))) return st;
+  const bool persistent = flags == TVD_KERNEL_PERSISTENT ||
+                          (batch->d_edge && flags == TVD_KERNEL_AUTO);
+  if ((fuse || persistent) && (st = reserve(ctx, batch->n_blocks, s))) return st;
   tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
   kp.nbr = d_nbr;
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
@@ -301,6 +324,16 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   if (flags == TVD_KERNEL_PLAIN) {
     e = tvd::launch_plain_f64(sweep_order, kp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "plain kernel launch");
+  } else if (persistent) {
+    tvd::FusedPlan pl;
+    pl.list = ctx->plan_list;
+    pl.count = ctx->plan_small;
+    pl.next = reinterpret_cast<unsigned*>(ctx->plan_small + 2);
+    // one workgroup per CU (the LDS of one edge-16 block fills a CU), never
+    // more than there are blocks
+    const int wg = batch->n_blocks < ctx->cus ? batch->n_blocks : ctx->cus;
+    e = tvd::launch_fused(batch->dtype, sweep_order, gather, kp, pl, wg, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "persistent kernel launch");
   } else if (batch->d_edge) {
     // one launch per edge; a workgroup whose block has the other edge exits
     for (int edge : {16, 8}) {

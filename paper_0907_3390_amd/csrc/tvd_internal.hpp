@@ -38,12 +38,23 @@ struct Variant {
   int split;     // bit 0: sweep-1 tail pencils in halves; bit 1: sweep-2 pencils in halves
 };
 
+// Work plan of the persistent launch over mixed edges (device memory).
+struct FusedPlan {
+  int32_t* list;       // [nblocks] edge-16 blocks, then edge-8 blocks
+  int32_t* count;      // [2] number of edge-16 and edge-8 blocks
+  unsigned* next;      // [8] work counter of each XCD's queue
+};
+
 // Launchers.  All return a hipError_t from the launch.
 // gather = true: the first sweep reads its pencils straight from the
 // interiors of the block and its 26 neighbours (kp.nbr) instead of a
 // ghosted copy; kp.uin then holds interior blocks at the out offsets.
 hipError_t launch_batched(int dtype, int order, const Variant& v, bool gather, const KParams& kp,
                           hipStream_t s);
+// Mixed edges (kp.d_edge, or a uniform kp.edge) in one persistent launch of `workgroups`
+// workgroups, after a one-workgroup planning launch.  FP32 only.
+hipError_t launch_fused(int dtype, int order, bool gather, const KParams& kp, const FusedPlan& pl,
+                        int workgroups, hipStream_t s);
 hipError_t launch_plain_f64(int order, const KParams& kp, hipStream_t s);
 hipError_t launch_signal_speed(int dtype, int layout, const KParams& kp, hipStream_t s);
 hipError_t launch_cons_sums(int dtype, int layout, const KParams& kp, hipStream_t s);

@@ -15,15 +15,17 @@ namespace tvd {
 // block-level reductions (fixed order, hence deterministic)
 // ---------------------------------------------------------------------------
 
+// NT threads with indices tid in [0, NT) reduce; when several groups share a
+// workgroup (each with its own `red`), every thread of the workgroup calls.
 template <int NT>
-__device__ double block_max(double v, double* red) {
+__device__ double block_max(double v, double* red, int tid) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = tid >> 6, l = tid & 63;
   if (l == 0) red[w] = v;
   __syncthreads();
   double r = 0.0;
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     r = red[0];
     for (int i = 1; i < NT / 64; ++i) r = fmax(r, red[i]);
   }
@@ -32,7 +34,7 @@ __device__ double block_max(double v, double* red) {
 }
 
 template <int NT>
-__device__ void block_csum(CSum a[kNV], CSum* red) {
+__device__ void block_csum(CSum a[kNV], CSum* red, int tid) {
 #pragma unroll
   for (int k = 0; k < kNV; ++k) {
 #pragma unroll
@@ -41,11 +43,11 @@ __device__ void block_csum(CSum a[kNV], CSum* red) {
       a[k] = csum_merge(a[k], o);
     }
   }
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = tid >> 6, l = tid & 63;
   if (l == 0)
     for (int k = 0; k < kNV; ++k) red[w * kNV + k] = a[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     for (int k = 0; k < kNV; ++k) {
       CSum r = red[k];
       for (int i = 1; i < NT / 64; ++i) r = csum_merge(r, red[i * kNV + k]);
@@ -101,26 +103,28 @@ __device__ __forceinline__ void diag_cell(CellDiag& d, const T u[kNV], int flags
   }
 }
 
-// Reduce the diagnostics of a workgroup and publish them for block b.
+// Reduce the diagnostics of the NT threads working on block b (b < 0: no
+// block, the thread group only takes part in the barriers) and publish them.
 template <int NT>
-__device__ void diag_publish(CellDiag& d, int b, double dh, const KParams& kp, void* scratch) {
+__device__ void diag_publish(CellDiag& d, int b, double dh, const KParams& kp, void* scratch,
+                             int tid) {
   unsigned fl = d.floored, bad = d.bad;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     fl += __shfl_xor(fl, off);
     bad += __shfl_xor(bad, off);
   }
-  if ((threadIdx.x & 63) == 0 && (fl | bad)) {
+  if ((tid & 63) == 0 && (fl | bad)) {
     if (fl) atomicAdd(&kp.counters[0], (unsigned long long)fl);
     if (bad) atomicAdd(&kp.counters[1], (unsigned long long)bad);
   }
   if (kp.diag & kDiagSpeed) {
-    const double sm = block_max<NT>(d.smax, reinterpret_cast<double*>(scratch));
-    if (threadIdx.x == 0) kp.ws_smax[b] = sm;
+    const double sm = block_max<NT>(d.smax, reinterpret_cast<double*>(scratch), tid);
+    if (tid == 0 && b >= 0) kp.ws_smax[b] = sm;
   }
   if (kp.diag & kDiagSums) {
-    block_csum<NT>(d.sum, reinterpret_cast<CSum*>(scratch));
-    if (threadIdx.x == 0) {
+    block_csum<NT>(d.sum, reinterpret_cast<CSum*>(scratch), tid);
+    if (tid == 0 && b >= 0) {
       const double w = dh * dh * dh;
       for (int k = 0; k < kNV; ++k) {
         // the block's compensated sum times dh^3 (exact for dyadic dh)
@@ -314,12 +318,28 @@ struct Held {
   }
 };
 
+// LDS a thread group needs for one block: the block after sweep 0, the 27
+// neighbour offsets of gather mode and a flag word.
+template <typename T, int N, int PAD>
+struct BlockLds {
+  T s[kNV * LdsLayout<N, PAD>::PLANE];
+  int64_t nboff[27];
+  int nbad;
+};
+
+// One step (one sweep triple) of block b by the NT threads tid = 0..NT-1 of
+// a thread group, which may be the whole workgroup or a slice of it; every
+// thread of the workgroup calls with the same template arguments, so that
+// all of them meet the same barriers.  b < 0 means no block: the group only
+// takes part in the barriers.
+//
 // Sweep 1 (SPLIT bit 0): the first NT/2 threads take whole pencils, the
 // remaining pencils are split in halves over the other threads, so that all
 // four SIMDs carry about the same number of wave-pencils.
 // Sweep 2 (SPLIT bit 1): every pencil is split in halves over all threads.
 template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER>
-__global__ __launch_bounds__(NT) void k_batched(KParams kp) {
+__device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
+                                              BlockLds<T, N, PAD>& sm) {
   using L = LdsLayout<N, PAD>;
   constexpr int M = N + 2 * kG;
   constexpr int M3 = M * M * M;
@@ -327,36 +347,36 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   constexpr int D0 = ORDER == 0 ? 0 : 2;
   constexpr int D1 = 1;
   constexpr int D2 = ORDER == 0 ? 2 : 0;
-  __shared__ T S[kNV * L::PLANE];
-  __shared__ int64_t nboff[GATHER ? 27 : 1];
-  __shared__ int nbad;
+  T* const S = sm.s;
 
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  if (block_edge(kp, b) != N) return;  // block belongs to another edge's launch
-  T* __restrict__ bout = reinterpret_cast<T*>(kp.uout) +
-                         (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3);
-  double dh;
-  const Coef<T> cf = make_coef<T>(kp, b, dh);
+  bool active = b >= 0;
+  T* __restrict__ bout = nullptr;
+  double dh = 1.0;
+  Coef<T> cf{};
+  if (active) {
+    bout = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3);
+    cf = make_coef<T>(kp, b, dh);
+  }
 
   if constexpr (GATHER) {
     // offsets of the 27 blocks around b; a missing or mismatched neighbour
     // makes the block unadvanceable here (counted, output left untouched)
-    if (threadIdx.x == 0) nbad = 0;
+    if (tid == 0) sm.nbad = 0;
     __syncthreads();
-    if (threadIdx.x < 27) {
-      const int nb = kp.nbr[27 * (int64_t)b + threadIdx.x];
+    if (active && tid < 27) {
+      const int nb = kp.nbr[27 * (int64_t)b + tid];
       const bool ok = nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == N;
-      if (!ok) atomicAdd(&nbad, 1);
-      nboff[threadIdx.x] = ok ? (kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * N3) : 0;
+      if (!ok) atomicAdd(&sm.nbad, 1);
+      sm.nboff[tid] = ok ? (kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * N3) : 0;
     }
     __syncthreads();
-    if (nbad) {
-      if (threadIdx.x == 0) atomicAdd(&kp.counters[1], (unsigned long long)N3);
-      return;
+    if (active && sm.nbad) {
+      if (tid == 0) atomicAdd(&kp.counters[1], (unsigned long long)N3);
+      active = false;
     }
     const T* __restrict__ uin = reinterpret_cast<const T*>(kp.uin);
     // sweep 0 straight from the neighbours' interiors
-    for (int p = threadIdx.x; p < M * M; p += NT) {
+    for (int p = tid; active && p < M * M; p += NT) {
       int c1, c2;
       if (ORDER == 0) {
         c1 = p % M;
@@ -370,21 +390,23 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
         const int ry = ghost_region(c1, N), rz = ghost_region(c2, N);
         const int t = N * (c1 - kG - ry * N) + N * N * (c2 - kG - rz * N);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) src.p[r] = uin + nboff[r + 3 * (ry + 1) + 9 * (rz + 1)] + t;
+        for (int r = 0; r < 3; ++r) src.p[r] = uin + sm.nboff[r + 3 * (ry + 1) + 9 * (rz + 1)] + t;
       } else {           // z pencil at (x, y) = (c2, c1)
         const int rx = ghost_region(c2, N), ry = ghost_region(c1, N);
         const int t = (c2 - kG - rx * N) + N * (c1 - kG - ry * N);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) src.p[r] = uin + nboff[(rx + 1) + 3 * (ry + 1) + 9 * r] + t;
+        for (int r = 0; r < 3; ++r) src.p[r] = uin + sm.nboff[(rx + 1) + 3 * (ry + 1) + 9 * r] + t;
       }
       const LdsSink0<T, L, D0> dst{S, c1, c2};
       pencil_sweep<T, N>(src, dst, cf);
     }
   } else {
-    const T* __restrict__ bin = reinterpret_cast<const T*>(kp.uin) +
-                                (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * M3);
+    const T* __restrict__ bin =
+        active ? reinterpret_cast<const T*>(kp.uin) +
+                     (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * M3)
+               : nullptr;
     // sweep 0: every (c1, c2) pencil, ghosts of the later axes included
-    for (int p = threadIdx.x; p < M * M; p += NT) {
+    for (int p = tid; active && p < M * M; p += NT) {
       int c1, c2, start;
       if (ORDER == 0) {  // x pencils; consecutive threads step in y
         c1 = p % M;
@@ -405,13 +427,13 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   if constexpr ((SPLIT & 1) != 0) {
     constexpr int F = NT / 2;          // whole pencils
     constexpr int R = N * M - F;       // pencils done in halves
-    static_assert(R > 0 && 2 * R <= NT - F, "split layout does not fit the workgroup");
-    const int t = threadIdx.x;
-    const bool half = t >= F && t - F < 2 * R;
+    static_assert(R > 0 && 2 * R <= NT - F, "split layout does not fit the thread group");
+    const int t = tid;
+    const bool half = active && t >= F && t - F < 2 * R;
     const int p = t < F ? t : F + (t - F) / 2;
     const Shifted<LdsPencil1<T, L, D1>> acc{{S, p % N, p / N}, ((t - F) & 1) * (N / 2)};
     Held<T, N / 2> held;
-    if (t < F) {
+    if (active && t < F) {
       pencil_sweep<T, N>(acc.a, acc.a, cf);
     } else if (half) {
       pencil_sweep<T, N / 2>(acc, held, cf);
@@ -419,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
     __syncthreads();
     if (half) held.flush(acc);
   } else {
-    for (int p = threadIdx.x; p < N * M; p += NT) {
+    for (int p = tid; active && p < N * M; p += NT) {
       const LdsPencil1<T, L, D1> acc{S, p % N, p / N};
       pencil_sweep<T, N>(acc, acc, cf);
     }
@@ -437,21 +459,182 @@ __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   };
   if constexpr ((SPLIT & 2) != 0) {
     static_assert(2 * N * N == NT, "sweep-2 halves need one thread each");
-    const int t = threadIdx.x;
-    const int p = t / 2, off = (t & 1) * (N / 2);
-    const int c0 = p % N, c1 = p / N + kG;
-    const Shifted<LdsPencil2<T, L, D2>> src{{S, c0, c1}, off};
-    const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
-    pencil_sweep<T, N / 2>(src, dst, cf);
+    if (active) {
+      const int p = tid / 2, off = (tid & 1) * (N / 2);
+      const int c0 = p % N, c1 = p / N + kG;
+      const Shifted<LdsPencil2<T, L, D2>> src{{S, c0, c1}, off};
+      const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
+      pencil_sweep<T, N / 2>(src, dst, cf);
+    }
   } else {
-    for (int p = threadIdx.x; p < N * N; p += NT) {
+    for (int p = tid; active && p < N * N; p += NT) {
       const int c0 = p % N, c1 = p / N + kG;
       const LdsPencil2<T, L, D2> src{S, c0, c1};
       pencil_sweep<T, N>(src, out_pencil(c0, c1), cf);
     }
   }
   __syncthreads();
-  diag_publish<NT>(dg, b, dh, kp, S);
+  diag_publish<NT>(dg, active ? b : -1, dh, kp, S, tid);
+}
+
+// One workgroup per block, blocks spread over the XCDs in contiguous ranges.
+// With mixed edges each edge has its own launch and a workgroup whose block
+// has the other edge exits at once.
+template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER>
+__global__ __launch_bounds__(NT) void k_batched(KParams kp) {
+  __shared__ BlockLds<T, N, PAD> sm;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (block_edge(kp, b) != N) return;  // uniform over the workgroup
+  advance_block<T, N, ORDER, NT, PAD, SPLIT, GATHER>(kp, b, threadIdx.x, sm);
+}
+
+// ---------------------------------------------------------------------------
+// persistent launch over a batch of mixed edges
+// ---------------------------------------------------------------------------
+//
+// The plan kernel partitions the blocks by edge (kp.d_edge, or the uniform
+// kp.edge for all), stably: edge-16 blocks first,
+// then edge-8 blocks, in block order (list), with their counts (count[0],
+// count[1]), and clears the work counters (next).  A block of any other edge
+// is skipped and counted once in the non-physical counter.
+//
+// Work items: item w < n16 is edge-16 block list[w], advanced by the whole
+// workgroup; item w >= n16 is the quad of edge-8 blocks
+// list[n16 + 4(w - n16) + q], q = 0..3, one per quarter of the workgroup,
+// each quarter with its own LDS.  The items are cut into one queue per XCD
+// (contiguous ranges, so neighbouring blocks meet in one L2, each range
+// edge-16 blocks first); a workgroup drains its XCD's queue and then helps
+// the others.
+
+constexpr int kPlanNT = 1024;
+constexpr int kXcds = 8;
+// the variants the persistent kernel runs (edge 16 on the whole workgroup,
+// edge 8 on each quarter)
+constexpr int kFusedPad16 = 16, kFusedSplit16 = 3;
+constexpr int kFusedPad8 = 8, kFusedSplit8 = 0;
+
+__global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ edge, int uniform,
+                                                  int n, FusedPlan pl,
+                                                  unsigned long long* counters) {
+  __shared__ int w16[kPlanNT / 64], w8[kPlanNT / 64];
+  __shared__ int tot16, tot8;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  int c16 = 0, c8 = 0;
+  for (int i = t; i < n; i += kPlanNT) {
+    const int e = edge ? edge[i] : uniform;
+    c16 += e == 16;
+    c8 += e == 8;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c16 += __shfl_xor(c16, off);
+    c8 += __shfl_xor(c8, off);
+  }
+  if (l == 0) {
+    w16[w] = c16;
+    w8[w] = c8;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int a = 0, c = 0;
+    for (int k = 0; k < kPlanNT / 64; ++k) {
+      a += w16[k];
+      c += w8[k];
+    }
+    tot16 = a;
+    tot8 = c;
+    pl.count[0] = a;
+    pl.count[1] = c;
+    if (n - a - c > 0) atomicAdd(&counters[1], (unsigned long long)(n - a - c));
+  }
+  if (t < kXcds) pl.next[t] = 0u;
+  __syncthreads();
+  const int n16 = tot16;
+  int run16 = 0, run8 = 0;
+  const unsigned long long below = l == 0 ? 0ull : (~0ull >> (64 - l));
+  for (int base = 0; base < n; base += kPlanNT) {
+    const int i = base + t;
+    const int e = i < n ? (edge ? edge[i] : uniform) : 0;
+    const unsigned long long m16 = __ballot(e == 16), m8 = __ballot(e == 8);
+    __syncthreads();  // the previous chunk's totals have been read
+    if (l == 0) {
+      w16[w] = __popcll(m16);
+      w8[w] = __popcll(m8);
+    }
+    __syncthreads();
+    int o16 = 0, o8 = 0, a16 = 0, a8 = 0;
+    for (int k = 0; k < kPlanNT / 64; ++k) {
+      if (k < w) {
+        o16 += w16[k];
+        o8 += w8[k];
+      }
+      a16 += w16[k];
+      a8 += w8[k];
+    }
+    if (e == 16) pl.list[run16 + o16 + __popcll(m16 & below)] = i;
+    if (e == 8) pl.list[n16 + run8 + o8 + __popcll(m8 & below)] = i;
+    run16 += a16;
+    run8 += a8;
+  }
+}
+
+// [lo, hi) of part k when n items are cut into kXcds contiguous parts
+__device__ __forceinline__ int part_lo(int n, int k) {
+  const int q = n / kXcds, r = n % kXcds;
+  return k * q + (k < r ? k : r);
+}
+
+template <typename T, int ORDER, bool GATHER>
+__global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
+  using B16 = BlockLds<T, 16, kFusedPad16>;
+  using B8 = BlockLds<T, 8, kFusedPad8>;
+  static_assert(4 * sizeof(B8) <= sizeof(B16), "four edge-8 blocks share the edge-16 LDS");
+  __shared__ B16 sm;
+  __shared__ int item;
+  const int xcd = blockIdx.x % kXcds;
+  const int n16 = pl.count[0], n8 = pl.count[1];
+  const int nq = (n8 + 3) / 4;
+  int qi = 0;  // queues drained so far (thread 0 only)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int wi = -1;
+      for (; qi < kXcds; ++qi) {
+        const int x = (xcd + qi) % kXcds;
+        const int lo16 = part_lo(n16, x), hi16 = part_lo(n16, x + 1);
+        const int loq = part_lo(nq, x), hiq = part_lo(nq, x + 1);
+        const int k = (int)atomicAdd(&pl.next[x], 1u);
+        if (k < hi16 - lo16) {
+          wi = lo16 + k;
+          break;
+        }
+        if (k < hi16 - lo16 + hiq - loq) {
+          wi = n16 + loq + k - (hi16 - lo16);
+          break;
+        }
+      }
+      item = wi;
+    }
+    __syncthreads();
+    const int wi = item;
+    __syncthreads();
+    if (wi < 0) break;  // uniform over the workgroup
+    // The thread index is passed through an empty asm statement (no
+    // instruction) so that the per-thread pencil indexing of every sweep is
+    // recomputed per item: hoisted out of the loop it stays live across all
+    // three sweeps and makes the register allocator spill.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (wi < n16) {
+      advance_block<T, 16, ORDER, 512, kFusedPad16, kFusedSplit16, GATHER>(kp, pl.list[wi], tid,
+                                                                          sm);
+    } else {
+      const int q = tid >> 7;
+      const int i = 4 * (wi - n16) + q;
+      const int b = i < n8 ? pl.list[n16 + i] : -1;
+      B8* quarter = reinterpret_cast<B8*>(&sm) + q;
+      advance_block<T, 8, ORDER, 128, kFusedPad8, kFusedSplit8, GATHER>(kp, b, tid & 127, *quarter);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -536,7 +719,7 @@ __global__ __launch_bounds__(kPlainNT) void k_plain_f64(KParams kp) {
     diag_cell<double>(dg, u, kp.diag, kp.gamma, kp.pfloor);
   }
   __syncthreads();
-  diag_publish<kPlainNT>(dg, b, dh, kp, S);
+  diag_publish<kPlainNT>(dg, b, dh, kp, S, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,10 +752,10 @@ __global__ __launch_bounds__(kRedNT) void k_block_diag(KParams kp, int layout) {
     diag_cell<T>(dg, u, kp.diag, kp.gamma, kp.pfloor);
   }
   if (kp.diag & kDiagSpeed) {
-    const double sm = block_max<kRedNT>(dg.smax, reinterpret_cast<double*>(red));
+    const double sm = block_max<kRedNT>(dg.smax, reinterpret_cast<double*>(red), threadIdx.x);
     if (threadIdx.x == 0) kp.ws_smax[b] = sm;
   } else {
-    block_csum<kRedNT>(dg.sum, red);
+    block_csum<kRedNT>(dg.sum, red, threadIdx.x);
     if (threadIdx.x == 0) {
       const double w = dh * dh * dh;
       for (int k = 0; k < kNV; ++k) {
@@ -593,7 +776,7 @@ __global__ __launch_bounds__(kFinNT) void k_finalize_max(const double* ws, int n
   __shared__ double red[kFinNT / 64];
   double m = 0.0;
   for (int i = threadIdx.x; i < n; i += kFinNT) m = fmax(m, ws[i]);
-  const double r = block_max<kFinNT>(m, red);
+  const double r = block_max<kFinNT>(m, red, threadIdx.x);
   if (threadIdx.x == 0) out[0] = r;
 }
 
@@ -608,7 +791,7 @@ __global__ __launch_bounds__(kFinNT) void k_finalize_sums(const double* ws, int 
   for (int b = lo; b < hi; ++b)
     for (int k = 0; k < kNV; ++k)
       a[k] = csum_merge(a[k], CSum{ws[(size_t)b * 2 * kNV + 2 * k], ws[(size_t)b * 2 * kNV + 2 * k + 1]});
-  block_csum<kFinNT>(a, red);
+  block_csum<kFinNT>(a, red, threadIdx.x);
   if (threadIdx.x == 0)
     for (int k = 0; k < kNV; ++k) out[k] = a[k].s + a[k].c;
 }
@@ -727,6 +910,24 @@ hipError_t launch_batched(int dtype, int order, const Variant& v, bool gather, c
   if (dtype == 1) return launch_typed<float>(order, v, gather, kp, s);
   if (v.edge == 16) return hipErrorInvalidValue;
   return launch_typed<double>(order, v, gather, kp, s);
+}
+
+hipError_t launch_fused(int dtype, int order, bool gather, const KParams& kp, const FusedPlan& pl,
+                        int workgroups, hipStream_t s) {
+  if (dtype != 1) return hipErrorInvalidValue;  // FP64 edge 16 does not fit in LDS
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanNT), 0, s, kp.d_edge, kp.edge, kp.nblocks, pl,
+                     kp.counters);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid(workgroups), block(512);
+  if (gather) {
+    if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, true>), grid, block, 0, s, kp, pl);
+    else hipLaunchKernelGGL((k_fused<float, 1, true>), grid, block, 0, s, kp, pl);
+  } else {
+    if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, false>), grid, block, 0, s, kp, pl);
+    else hipLaunchKernelGGL((k_fused<float, 1, false>), grid, block, 0, s, kp, pl);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_plain_f64(int order, const KParams& kp, hipStream_t s) {

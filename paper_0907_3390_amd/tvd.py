@@ -32,6 +32,7 @@ TVD_LAYOUT_INTERIOR = 1
 TVD_KERNEL_AUTO = 0
 TVD_KERNEL_BATCHED = 1
 TVD_KERNEL_PLAIN = 2
+TVD_KERNEL_PERSISTENT = 3
 
 EXPORTS = [
     "tvd_create", "tvd_destroy", "tvd_status_string", "tvd_last_error", "tvd_reserve",

@@ -75,3 +75,20 @@ def cone_blocks(grid, n, picks, steps, dt, dh, gamma=GAMMA, p_floor=0.0):
                                         p_floor)[0]
         out[b] = sub
     return out
+
+
+def oracle_boxes(grids, dhs, steps, cfl=0.5, gamma=GAMMA, p_floor=0.0):
+    """Independent periodic boxes advanced together by the oracle: before
+    every even step S is the Eq. (CFL) signal speed over all boxes and box i
+    takes dt_i = cfl * dh_i / S; each box is one ghosted block (periodic wrap
+    by three cells), so the region rule runs over the whole box."""
+    state = [np.asarray(g, dtype=np.float64) for g in grids]
+    dhs = np.asarray(dhs, dtype=np.float64)
+    dt = None
+    for s in range(steps):
+        if s % 2 == 0:
+            S = max(oracle.max_signal_speed(g, gamma, p_floor) for g in state)
+            dt = cfl * dhs / S
+        ghosted = [np.pad(g, ((0, 0), (3, 3), (3, 3), (3, 3)), mode="wrap") for g in state]
+        state = oracle.advance_ragged(ghosted, s % 2, dt, dhs, gamma, p_floor)
+    return state

@@ -17,7 +17,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import GAMMA, norms, note, oracle_periodic, worst
+from gpu_helpers import GAMMA, norms, note, oracle_boxes, oracle_periodic, worst
 from paper_0907_3390_amd import layout, tvd, workloads as wl
 from paper_0907_3390_amd.driver import DeviceBlocks
 
@@ -146,6 +146,74 @@ def test_gather_mixed_edges_fp32(ctx):
         torch.cuda.synchronize()
         outs.append(dev.interior.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("gather", [False, True])
+def test_persistent_equals_per_edge_launches(ctx, gather):
+    """Mixed edges in one persistent launch (workgroups drawing edge-16 blocks
+    and quads of edge-8 blocks from per-XCD queues, more blocks than
+    workgroups, a ragged last quad) give bit for bit the result of one launch
+    per edge, fused signal speed, dt and sums included."""
+    note(f"persistent vs per-edge launches gather={gather}")
+    boxes = wl.sound_wave_boxes(counts=(301, 40, 30), seed=9)
+    grids = [b.astype(np.float32).astype(np.float64) for b in boxes.grids]
+    edges = [g.shape[1] for g in grids]
+    efor = lambda L: 8 if L == 8 else 16
+    bs = layout.boxes_blockset(edges, efor, boxes.dh)
+    assert bs.n_blocks > 256 and (bs.edges == 8).sum() % 4 == 1
+    outs = []
+    for kernel in (tvd.TVD_KERNEL_BATCHED, tvd.TVD_KERNEL_PERSISTENT, tvd.TVD_KERNEL_AUTO):
+        dev = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=gather, kernel=kernel)
+        dev.upload(layout.boxes_to_blocks(grids, efor))
+        rec = dev.run(6, sums_each_step=True)
+        torch.cuda.synchronize()
+        outs.append((dev.interior.cpu().numpy(), dev.dt.cpu().numpy(), rec.cpu().numpy(),
+                     dev.smax.cpu().numpy()))
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_persistent_uniform_edge(ctx, n):
+    """The persistent kernel also takes a uniform-edge batch (no d_edge):
+    same bits as the one-workgroup-per-block launch."""
+    note(f"persistent uniform edge {n}")
+    g = wl.lognormal(64, seed=31, sigma_ln=0.6).astype(np.float32).astype(np.float64)
+    a, _ = run_gpu_periodic(ctx, g, 4, n, torch.float32, kernel=tvd.TVD_KERNEL_BATCHED)
+    b, _ = run_gpu_periodic(ctx, g, 4, n, torch.float32, kernel=tvd.TVD_KERNEL_PERSISTENT)
+    assert np.array_equal(a, b)
+
+
+def test_persistent_skips_unknown_edge(ctx):
+    """A block whose edge entry is neither 8 nor 16 is left out of the
+    persistent launch's plan: not advanced, counted once as non-physical; the
+    other blocks are advanced as usual."""
+    note("persistent launch with an unknown edge entry")
+    boxes = wl.sound_wave_boxes(counts=(6, 2, 1), seed=10)
+    grids = [b.astype(np.float32).astype(np.float64) for b in boxes.grids]
+    edges = [g.shape[1] for g in grids]
+    efor = lambda L: 8 if L == 8 else 16
+    bs = layout.boxes_blockset(edges, efor, boxes.dh)
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float32, kernel=tvd.TVD_KERNEL_PERSISTENT)
+    dev.upload(layout.boxes_to_blocks(grids, efor))
+    dev.fill_ghosts()
+    dev.dt.fill_(1e-3)
+    dev.advance(0)
+    ref = dev.interior.cpu().numpy()
+    victim = int(np.nonzero(bs.edges == 16)[0][1])
+    dev.edges[victim] = 12
+    dev.interior.fill_(7.0)
+    ctx.tvd_read_flags()
+    dev.advance(0)
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_ERR_NONPHYSICAL and bad == 1 and fl == 0
+    got = dev.interior.cpu().numpy()
+    lo, hi = int(bs.out_off[victim]), int(bs.out_off[victim]) + 5 * 16 ** 3
+    assert np.all(got[lo:hi] == 7.0)
+    keep = np.ones(got.size, dtype=bool)
+    keep[lo:hi] = False
+    assert np.array_equal(got[keep], ref[keep])
 
 
 def test_gather_missing_neighbour_is_flagged(ctx):
@@ -372,6 +440,39 @@ def test_graph_replay_matches_eager(ctx, gather):
     gr.close()
 
 
+def test_graph_replay_persistent_mixed_edges(ctx):
+    """A four-step sequence of persistent mixed-edge launches (each with its
+    planning kernel, which clears the work counters) recorded into a HIP graph
+    and replayed three times, with eager work in between, equals the eager
+    sequence bit for bit after every replay; then the block-edge tuner runs on
+    the same boxes."""
+    note("graph capture of persistent mixed-edge steps; block-edge tuner")
+    from paper_0907_3390_amd import tuning
+    boxes = wl.sound_wave_boxes(counts=(61, 10, 6), seed=12)
+    grids = [b.astype(np.float32).astype(np.float64) for b in boxes.grids]
+    efor = lambda L: 8 if L == 8 else 16
+    eager = tuning.boxes_device(ctx, grids, boxes.dh, efor)
+    graph = tuning.boxes_device(ctx, grids, boxes.dh, efor)
+    for d in (eager, graph):
+        d.run(2)
+    torch.cuda.synchronize()
+    gr = graph.capture(4)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        eager.run(4)
+        torch.cuda.synchronize()
+        x = eager.interior.sum()
+        graph.replay(gr)
+        torch.cuda.synchronize()
+        assert torch.equal(eager.interior, graph.interior), rep
+        assert torch.equal(eager.dt, graph.dt), rep
+        del x
+    gr.close()
+    best, times = tuning.tune_block_edge(
+        ctx, grids, boxes.dh, {"8": lambda L: 8, "8/16": efor}, pairs=2)
+    assert best in ("8", "8/16") and all(t > 0 for t in times.values())
+
+
 def test_torch_graph_capture_also_works(ctx):
     """The entry points are capture-safe under torch's graph wrapper too."""
     note("torch graph capture")
@@ -556,6 +657,36 @@ def test_full_size_512cube_sedov_fp32(ctx):
     centre = 15 + 32 * (15 + 32 * 15)  # the 16^3 group holding cell 255
     picks = sorted({centre, centre + 1, centre + 32 * 33, 0, 12345, 32767})
     _full_size_sampled(ctx, g, 16, torch.float32, 2, dt, picks, p_floor=1e-10, tol=1e-4)
+
+
+def test_full_size_uneven_boxes_fp32(ctx):
+    """The uneven batch at full size: 4000 periodic boxes, 2286 of 8^3, 1143 of
+    16^3 and 571 of 32^3, sound waves of amplitude 1e-3, FP32, the persistent
+    gathering launch (8^3 boxes as edge-8 blocks, the rest as 16^3 groups),
+    dt_b = C dh_b / S from the device; 10 steps against the oracle run over
+    every box: relative L1 <= 1e-5 per variable."""
+    note("full size uneven boxes fp32, persistent launch, 10 steps")
+    boxes = wl.sound_wave_boxes(seed=4)
+    grids = [b.astype(np.float32).astype(np.float64) for b in boxes.grids]
+    edges = [g.shape[1] for g in grids]
+    assert len(grids) == 4000 and sum(L ** 3 for L in edges) == 24_562_688
+    efor = lambda L: 8 if L == 8 else 16
+    bs = layout.boxes_blockset(edges, efor, boxes.dh)
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=True)
+    dev.upload(layout.boxes_to_blocks(grids, efor))
+    ctx.tvd_read_flags()
+    dev.run(10)
+    torch.cuda.synchronize()
+    st, fl, bad = ctx.tvd_read_flags()
+    assert st == tvd.TVD_OK and fl == 0 and bad == 0
+    got = layout.blocks_to_boxes(dev.download(), edges, efor)
+    note("oracle over 4000 boxes")
+    want = oracle_boxes(grids, boxes.dh, 10)
+    a = np.concatenate([x.reshape(5, -1) for x in got], axis=1)
+    b = np.concatenate([x.reshape(5, -1) for x in want], axis=1)
+    nrm = norms(a, b)
+    note(str({k: (v["relL1"], v["relL1_own"], v["relLinf"]) for k, v in nrm.items()}))
+    assert worst(nrm) <= 1e-5
 
 
 # ---------------------------------------------------------------------------
