@@ -285,6 +285,31 @@ struct GlobalOut {
     for (int k = 0; k < kNV; ++k) c[k * N3] = ug[k];
     diag_cell<T>(*dg, ug, diag, gamma, pfloor);
   }
+  // K consecutive cells i0 .. i0+K-1 of an x pencil (D == 0, stride 1) at
+  // once: each variable's run goes out in 16-byte stores, so that a wave
+  // writes whole row segments instead of one scattered element per lane.
+  // p + i0 must be 16-byte aligned.
+  template <int K>
+  __device__ inline void store_run(int i0, const T v[K][kNV]) const {
+    static_assert(D == 0 && (K * sizeof(T)) % 16 == 0, "runs along x of 16-byte multiples");
+    constexpr int N3 = N * N * N;
+    constexpr int W = 16 / sizeof(T);  // elements per 16-byte store
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      T* c = p + i0 + k * N3;
+#pragma unroll
+      for (int i = 0; i < K; i += W) {
+        if constexpr (W == 4) {
+          *reinterpret_cast<float4*>(c + i) =
+              make_float4(v[i][k], v[i + 1][k], v[i + 2][k], v[i + 3][k]);
+        } else {
+          *reinterpret_cast<double2*>(c + i) = make_double2(v[i][k], v[i + 1][k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) diag_cell<T>(*dg, v[i], diag, gamma, pfloor);
+  }
 };
 
 // Half of a pencil: the interior cells [off, off + N/2) of an LDS pencil,
@@ -463,8 +488,17 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
       const int p = tid / 2, off = (tid & 1) * (N / 2);
       const int c0 = p % N, c1 = p / N + kG;
       const Shifted<LdsPencil2<T, L, D2>> src{{S, c0, c1}, off};
-      const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
-      pencil_sweep<T, N / 2>(src, dst, cf);
+      if constexpr (ORDER == 1 && sizeof(T) == 4) {
+        // x pencils: the half pencil's cells wait in registers and leave as
+        // 16-byte runs along x (along z the lanes' stores already coalesce;
+        // FP64 keeps the direct stores, its registers are already full)
+        Held<T, N / 2> held;
+        pencil_sweep<T, N / 2>(src, held, cf);
+        out_pencil(c0, c1).template store_run<N / 2>(off, held.v);
+      } else {
+        const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
+        pencil_sweep<T, N / 2>(src, dst, cf);
+      }
     }
   } else {
     for (int p = tid; active && p < N * N; p += NT) {

@@ -5,7 +5,9 @@ a periodic domain, or a set of independent periodic boxes, is cut into cubic
 blocks of edge 8 or 16 (one 8^3 patch, or a 2^3 patch group as in the
 paper's Sec. 3.1); every block gets the 27-entry table of the blocks that
 cover its neighbourhood, which the device ghost fill reads.  Blocks are
-numbered x fastest, then y, then z, box after box.
+numbered x fastest, then y, then z, box after box, or, for a periodic grid,
+optionally along a Morton (Z-order) curve, so that blocks with nearby numbers
+are nearby in space.
 """
 from __future__ import annotations
 
@@ -30,21 +32,39 @@ def periodic_neighbors(nbx: int, nby: int, nbz: int, base: int = 0) -> np.ndarra
     return out
 
 
-def grid_to_blocks(grid: np.ndarray, n: int) -> np.ndarray:
-    """(5, Nz, Ny, Nx) -> (B, 5, n, n, n) interiors, blocks x fastest."""
+def morton_perm(nbx: int, nby: int, nbz: int) -> np.ndarray:
+    """perm[k] = x-fastest linear index of the k-th block along the Morton
+    curve (bits of bx, by, bz interleaved, x lowest) of an nbx x nby x nbz grid."""
+    lin = np.arange(nbx * nby * nbz, dtype=np.int64)
+    b = [lin % nbx, (lin // nbx) % nby, lin // (nbx * nby)]
+    key = np.zeros_like(lin)
+    for bit in range(21):
+        for a in range(3):
+            key |= ((b[a] >> bit) & 1) << (3 * bit + a)
+    return np.argsort(key, kind="stable")
+
+
+def grid_to_blocks(grid: np.ndarray, n: int, perm=None) -> np.ndarray:
+    """(5, Nz, Ny, Nx) -> (B, 5, n, n, n) interiors, blocks x fastest (or in
+    the order perm, block k being linear block perm[k])."""
     _, Nz, Ny, Nx = grid.shape
     nbz, nby, nbx = Nz // n, Ny // n, Nx // n
     if nbz * n != Nz or nby * n != Ny or nbx * n != Nx:
         raise ValueError("grid extents must be multiples of the block edge")
     g = grid.reshape(NVAR, nbz, n, nby, n, nbx, n)
-    return np.ascontiguousarray(g.transpose(1, 3, 5, 0, 2, 4, 6).reshape(nbz * nby * nbx, NVAR, n, n, n))
+    out = g.transpose(1, 3, 5, 0, 2, 4, 6).reshape(nbz * nby * nbx, NVAR, n, n, n)
+    return np.ascontiguousarray(out if perm is None else out[perm])
 
 
-def blocks_to_grid(blocks: np.ndarray, shape) -> np.ndarray:
+def blocks_to_grid(blocks: np.ndarray, shape, perm=None) -> np.ndarray:
     """(B, 5, n, n, n) -> (5, Nz, Ny, Nx), the inverse of grid_to_blocks."""
     _, Nz, Ny, Nx = shape
     n = blocks.shape[2]
     nbz, nby, nbx = Nz // n, Ny // n, Nx // n
+    if perm is not None:
+        lin = np.empty_like(blocks)
+        lin[perm] = blocks
+        blocks = lin
     g = blocks.reshape(nbz, nby, nbx, NVAR, n, n, n).transpose(3, 0, 4, 1, 5, 2, 6)
     return np.ascontiguousarray(g.reshape(NVAR, Nz, Ny, Nx))
 
@@ -58,6 +78,7 @@ class BlockSet:
     """
 
     def __init__(self, edges, dh, nbr):
+        self.perm = None  # block k is linear block perm[k] (periodic grids)
         self.edges = np.asarray(edges, dtype=np.int32)
         self.dh = np.asarray(dh, dtype=np.float64)
         self.nbr = np.ascontiguousarray(nbr, dtype=np.int32)
@@ -95,13 +116,26 @@ class BlockSet:
         return out
 
 
-def periodic_grid_blockset(N, n: int, dh: float | None = None) -> BlockSet:
-    """A periodic box of N^3 (or (Nz, Ny, Nx)) cells cut into n^3 blocks."""
+def periodic_grid_blockset(N, n: int, dh: float | None = None, curve: str = "linear") -> BlockSet:
+    """A periodic box of N^3 (or (Nz, Ny, Nx)) cells cut into n^3 blocks,
+    numbered x fastest (curve "linear") or along the Morton curve ("morton";
+    bs.perm then maps block k to linear block perm[k], for grid_to_blocks and
+    blocks_to_grid)."""
     Nz, Ny, Nx = (N, N, N) if np.isscalar(N) else N
     nbx, nby, nbz = Nx // n, Ny // n, Nz // n
     nbr = periodic_neighbors(nbx, nby, nbz)
     nb = nbx * nby * nbz
-    return BlockSet(np.full(nb, n), np.full(nb, 1.0 / Nx if dh is None else dh), nbr)
+    perm = None
+    if curve == "morton":
+        perm = morton_perm(nbx, nby, nbz)
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(nb)
+        nbr = inv[nbr[perm]].astype(np.int32)
+    elif curve != "linear":
+        raise ValueError(f"unknown curve {curve!r}")
+    bs = BlockSet(np.full(nb, n), np.full(nb, 1.0 / Nx if dh is None else dh), nbr)
+    bs.perm = perm
+    return bs
 
 
 def boxes_blockset(box_edges, block_edge_for, dhs) -> BlockSet:
