@@ -73,8 +73,11 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(variant):
     """HBM bytes per launch of the advance from the committed rocprofv3 counter
-    summary, only if it was taken on the current kernel sources and the same
-    launch variant."""
+    summary, only if it was taken on the current kernel sources and on a
+    launch variant with the same HBM access pattern: the block edge, the
+    workgroup size and whether the third sweep runs in half pencils (split
+    bit 1) fix which addresses are read and written; the LDS padding and the
+    second sweep's split only move work inside the workgroup."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     kv = {}
@@ -85,9 +88,10 @@ def measured_traffic(variant):
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
     if variant is not None:
-        want = ",".join(str(variant[k]) for k in ("edge", "threads", "lds_pad", "split"))
-        if kv.get("variant") != want:
-            return None, f"counters were taken on variant {kv.get('variant')}, not {want}"
+        got = [int(x) for x in kv.get("variant", "0,0,0,0").split(",")]
+        want = [variant[k] for k in ("edge", "threads", "lds_pad", "split")]
+        if got[:2] != want[:2] or (got[3] & 2) != (want[3] & 2):
+            return None, f"counters were taken on variant {got}, not {want}"
     return float(kv["hbm_bytes_per_launch_mean"]), ("rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
                                                     + os.path.relpath(TRAFFIC_FILE, ROOT))
 

@@ -153,7 +153,7 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
 }
 
 tvd::Variant default_variant(int dtype, int edge) {
-  if (edge == 16) return tvd::Variant{16, 512, 0, 1};
+  if (edge == 16) return tvd::Variant{16, 512, 16, 3};
   return dtype == TVD_F32 ? tvd::Variant{8, 128, 8, 0} : tvd::Variant{8, 256, 8, 0};
 }
 
