@@ -208,21 +208,28 @@ class MultiLevel:
 
 
 def _gaussian_field(centres, amps, radii):
-    def rho(x, y, z):
-        out = np.ones(np.broadcast(x, y, z).shape)
-        mx, my, mz = float(np.mean(x)), float(np.mean(y)), float(np.mean(z))
-        ext = max(float(np.ptp(x)), float(np.ptp(y)), float(np.ptp(z)))
-        for (cx, cy, cz), a, r in zip(centres, amps, radii):
-            # skip overdensities whose tail (exp(-32) relative) cannot reach
+    """rho on tensor-product point sets: rho(xs, ys, zs) with per-patch axis
+    coordinates of shape (P, k) returns (P, k, k, k) values (z, y, x order) of
+    1 + sum_k A_k exp(-d^2 / 2 r_k^2), d the periodic distance in the unit box.
+    Each Gaussian factorises into three 1-D factors.  A Gaussian whose tail
+    cannot reach a patch (centre farther than 8 r_k plus the patch's extent
+    from the patch's mean point, i.e. below exp(-32) relative) is skipped for
+    that patch."""
+    def rho(xs, ys, zs):
+        P, k = xs.shape
+        out = np.ones((P, k, k, k))
+        mean = [a.mean(axis=1) for a in (xs, ys, zs)]
+        ext = np.max([np.ptp(a, axis=1) for a in (xs, ys, zs)], axis=0)
+        for (cx, cy, cz), amp, r in zip(centres, amps, radii):
             d = np.sqrt(sum(((m_ - c_ + 0.5) % 1.0 - 0.5) ** 2
-                            for m_, c_ in ((mx, cx), (my, cy), (mz, cz))))
-            if d - ext > 8.0 * r:
+                            for m_, c_ in zip(mean, (cx, cy, cz))))
+            sel = np.nonzero(d - ext <= 8.0 * r)[0]
+            if sel.size == 0:
                 continue
-            # periodic distance to the centre
-            dx = (x - cx + 0.5) % 1.0 - 0.5
-            dy = (y - cy + 0.5) % 1.0 - 0.5
-            dz = (z - cz + 0.5) % 1.0 - 0.5
-            out = out + a * np.exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * r * r))
+            f = [np.exp(-(((a[sel] - c + 0.5) % 1.0 - 0.5) ** 2) / (2.0 * r * r))
+                 for a, c in ((xs, cx), (ys, cy), (zs, cz))]
+            out[sel] += amp * (f[2][:, :, None, None] * f[1][:, None, :, None] *
+                               f[0][:, None, None, :])
         return out
     return rho
 
@@ -249,68 +256,73 @@ def multilevel(base: int = 128, n_over: int = 32, seed: int = 3, max_level: int 
     rho_f = _gaussian_field(centres, amps, radii)
     n = 8
     ml = MultiLevel(base=base)
+
+    def axes_of(pc, h, offs):
+        # per-axis cell-centre coordinates of the patches pc [P, 3] (px, py,
+        # pz) at offsets offs (in cells) from each patch corner: 3 x [P, k]
+        return [(pc[:, a, None] * n + offs[None, :]) * h for a in range(3)]
+
     # level 0: every patch; refine level by level
     npb = base // n
-    cur = [(0, px, py, pz) for pz in range(npb) for py in range(npb) for px in range(npb)]
-    allp = list(cur)
+    cur = np.array([(px, py, pz) for pz in range(npb) for py in range(npb) for px in range(npb)],
+                   dtype=np.int64)
+    levels = [cur]
     for lev in range(max_level):
-        nxt = []
         h = 1.0 / (base * 2 ** lev)
-        c = (np.arange(n) + 0.5) * h
-        thr = 8.0 ** (lev + 1)
-        for (_, px, py, pz) in cur:
-            z, y, x = np.meshgrid(pz * n * h + c, py * n * h + c, px * n * h + c, indexing="ij")
-            if rho_f(x, y, z).max() >= thr:
-                for cz in range(2):
-                    for cy in range(2):
-                        for cx in range(2):
-                            nxt.append((lev + 1, 2 * px + cx, 2 * py + cy, 2 * pz + cz))
-        allp += nxt
-        cur = nxt
+        xs, ys, zs = axes_of(cur, h, np.arange(n) + 0.5)
+        hot = cur[rho_f(xs, ys, zs).reshape(len(cur), -1).max(axis=1) >= 8.0 ** (lev + 1)]
+        kids = np.array([(cx, cy, cz) for cz in range(2) for cy in range(2) for cx in range(2)],
+                        dtype=np.int64)
+        cur = (2 * hot[:, None, :] + kids[None, :, :]).reshape(-1, 3)
+        levels.append(cur)
+        if len(cur) == 0:
+            break
+    allp = [(lev, int(p[0]), int(p[1]), int(p[2])) for lev, pcs in enumerate(levels) for p in pcs]
     ml.patches = allp
     present = set(allp)
-
-    def prim_to_cons(rho):
-        return conserved(rho, 0.0, 0.0, 0.0, np.full(rho.shape, P0), gamma)
 
     m = n + 6
     g = np.empty((len(allp), 5, m, m, m))
     dh = np.empty(len(allp))
     off = np.arange(m) - 3 + 0.5  # ghosted cell centres in units of h, relative to the patch
-    for i, (lev, px, py, pz) in enumerate(allp):
+    reg = np.where(np.arange(m) < 3, 0, np.where(np.arange(m) >= n + 3, 2, 1))
+    base_i = 0
+    for lev, pcs in enumerate(levels):
+        if len(pcs) == 0:
+            continue
         h = 1.0 / (base * 2 ** lev)
-        dh[i] = h
-        z, y, x = np.meshgrid((pz * n + off) * h, (py * n + off) * h, (px * n + off) * h,
-                              indexing="ij")
-        fine = rho_f(x % 1.0, y % 1.0, z % 1.0)
+        xs, ys, zs = axes_of(pcs, h, off)
+        fine = rho_f(xs % 1.0, ys % 1.0, zs % 1.0)
         if lev > 0:
             # cells whose same-level patch does not exist: interpolate from the
             # coarser level's cell centres (trilinear, periodic)
             npl = base * 2 ** lev // n
-            reg = np.where(np.arange(m) < 3, 0, np.where(np.arange(m) >= n + 3, 2, 1))
-            have = np.zeros((3, 3, 3), dtype=bool)
-            for rz in range(3):
-                for ry in range(3):
-                    for rx in range(3):
-                        have[rz, ry, rx] = ((lev, (px + rx - 1) % npl, (py + ry - 1) % npl,
-                                             (pz + rz - 1) % npl) in present)
-            cover = have[reg[:, None, None], reg[None, :, None], reg[None, None, :]]
-            if not cover.all():
+            have = np.array([[((lev, (px + rx - 1) % npl, (py + ry - 1) % npl, (pz + rz - 1) % npl)
+                               in present) for rz in range(3) for ry in range(3) for rx in range(3)]
+                             for px, py, pz in pcs]).reshape(-1, 3, 3, 3)
+            cover = have[:, reg[:, None, None], reg[None, :, None], reg[None, None, :]]
+            need = np.nonzero(~cover.reshape(len(pcs), -1).all(axis=1))[0]
+            if need.size:
                 H = 2.0 * h
-                fx, fy, fz = x / H - 0.5, y / H - 0.5, z / H - 0.5
-                ix, iy, iz = np.floor(fx), np.floor(fy), np.floor(fz)
-                tx, ty, tz = fx - ix, fy - iy, fz - iz
-                interp = np.zeros((m, m, m))
+                # per axis: coarse cell below each fine centre and the weight
+                f_ = [a[need] / H - 0.5 for a in (xs, ys, zs)]
+                i_ = [np.floor(a) for a in f_]
+                t_ = [a - b for a, b in zip(f_, i_)]
+                interp = np.zeros((need.size, m, m, m))
                 for dz_ in (0, 1):
                     for dy_ in (0, 1):
                         for dx_ in (0, 1):
-                            wgt = ((tx if dx_ else 1 - tx) * (ty if dy_ else 1 - ty) *
-                                   (tz if dz_ else 1 - tz))
-                            interp += wgt * rho_f(((ix + dx_ + 0.5) * H) % 1.0,
-                                                  ((iy + dy_ + 0.5) * H) % 1.0,
-                                                  ((iz + dz_ + 0.5) * H) % 1.0)
-                fine = np.where(cover, fine, interp)
-        g[i] = prim_to_cons(fine)
+                            w = [t if d else 1 - t for t, d in zip(t_, (dx_, dy_, dz_))]
+                            wgt = w[2][:, :, None, None] * w[1][:, None, :, None] * w[0][:, None, None, :]
+                            interp += wgt * rho_f(((i_[0] + dx_ + 0.5) * H) % 1.0,
+                                                  ((i_[1] + dy_ + 0.5) * H) % 1.0,
+                                                  ((i_[2] + dz_ + 0.5) * H) % 1.0)
+                fine[need] = np.where(cover[need], fine[need], interp)
+        k = len(pcs)
+        g[base_i:base_i + k] = np.moveaxis(
+            conserved(fine, 0.0, 0.0, 0.0, np.full(fine.shape, P0), gamma), 0, 1)
+        dh[base_i:base_i + k] = h
+        base_i += k
     ml.ghosted = g
     ml.dh = dh
     return ml

@@ -711,41 +711,79 @@ def test_full_size_uneven_boxes_fp32(ctx):
     assert worst(nrm) <= 1e-5
 
 
+def test_sedov_128cube_100_steps_fp32(ctx):
+    """The point blast's 128^3 analog over all 100 steps (lognormal background
+    sigma_ln = 0.5 at rest, P = 1e-5, energy 1 in the central 2^3 cells,
+    p_floor 1e-10), FP32 gathering advance with the fused FP64 sums recorded
+    every step, against the FP64 oracle run over the same 100 steps (its own
+    dt): error per variable, conservation drift per step, health counters."""
+    note("sedov 128^3 analog, 100 steps fp32")
+    N, steps, pf = 128, 100, 1e-10
+    g = wl.sedov_lognormal(N, seed=5).astype(np.float32).astype(np.float64)
+    bs = layout.periodic_grid_blockset(N, 16, curve="morton")
+    dev = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=True, p_floor=pf)
+    dev.upload(layout.grid_to_blocks(g, 16, bs.perm))
+    ctx.tvd_read_flags()
+    rec = dev.run(steps, sums_each_step=True)
+    torch.cuda.synchronize()
+    st, fl, bad = ctx.tvd_read_flags()
+    note(f"health: floored {fl}, non-physical {bad}")
+    assert bad == 0
+    got = layout.blocks_to_grid(np.stack(dev.download()), g.shape, bs.perm)
+    note("oracle, 100 steps")
+    want, _ = oracle.run_periodic(g, steps, 0.5, 1.0 / N, GAMMA, n=32, p_floor=pf)
+    nrm = norms(got, want)
+    note(str({k: (f"{v['relL1']:.2e}", f"{v['relLinf']:.2e}") for k, v in nrm.items()}))
+    assert worst(nrm) <= 1e-4
+    # conservation drift of the fused FP64 sums, every step, against the exact
+    # sums of the initial state on each variable's own scale
+    w = (1.0 / N) ** 3
+    sums = rec.cpu().numpy()
+    rho = g[0]
+    kin = 0.5 * (g[1] ** 2 + g[2] ** 2 + g[3] ** 2) / rho
+    P = np.maximum((GAMMA - 1.0) * (g[4] - kin), pf)
+    mscale = np.sum(rho * np.sqrt(GAMMA * P / rho)) * w
+    drift = []
+    for k in range(5):
+        s0 = math.fsum((g[k].ravel() * w).tolist())
+        scale = np.abs(g[k]).sum() * w if k in (0, 4) else mscale
+        drift.append(np.max(np.abs(sums[:, k] - s0)) / scale)
+    note(f"max conservation drift over 100 steps (rho, m_x, m_y, m_z, e): {drift}")
+    assert max(drift) <= 1e-6
+
+
 # ---------------------------------------------------------------------------
 # multi-level batch: per-block dt and dh in one launch
 # ---------------------------------------------------------------------------
 
-def test_multilevel_batch_one_launch(ctx):
-    """Patches of levels 0-3 (dh halving per level) around Gaussian
-    overdensities, ghosts pre-filled by sibling copy or trilinear coarse-to-
-    fine interpolation; dt_b = C dh_b / S_global computed on the device.  One
-    batched launch (FP32 and FP64) and the plain FP64 kernel launched level by
-    level all match the oracle."""
-    note("multi-level batch")
-    ml = wl.multilevel(base=32, n_over=4, seed=3, radius=0.05)
+def _multilevel_check(ctx, ml, cases):
+    """One step of every patch of ml with dt_b = C dh_b / S_global computed on
+    the device, for each (dtype, kernel, tol) case, against the oracle's own
+    dt and step from the same (FP32-rounded for FP32) input.  The plain FP64
+    kernel is launched level by level on each level's contiguous range."""
     levels = ml.levels
-    assert set(np.unique(levels)) == {0, 1, 2, 3}
     nb = len(ml.patches)
-    S = oracle.max_signal_speed(np.ascontiguousarray(
-        ml.ghosted[:, :, 3:-3, 3:-3, 3:-3].transpose(1, 0, 2, 3, 4)).reshape(5, -1), GAMMA)
-    dt = 0.5 * ml.dh / S
-    ref = np.stack(oracle.advance_ragged(list(ml.ghosted), 0, dt, ml.dh, GAMMA))
-    for dtype, kernel, tol in [(torch.float64, tvd.TVD_KERNEL_BATCHED, 1e-12),
-                               (torch.float32, tvd.TVD_KERNEL_BATCHED, 1e-5),
-                               (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)]:
+    refs = {}
+    for dtype, kernel, tol in cases:
         code = tvd.dtype_code(dtype)
         gin = ml.ghosted.astype(np.float32).astype(np.float64) if dtype == torch.float32 else ml.ghosted
+        if dtype not in refs:
+            S = oracle.max_signal_speed(np.ascontiguousarray(
+                gin[:, :, 3:-3, 3:-3, 3:-3].transpose(1, 0, 2, 3, 4)).reshape(5, -1), GAMMA)
+            dt_ref = 0.5 * ml.dh / S
+            refs[dtype] = (dt_ref, np.stack(oracle.advance_ragged(list(gin), 0, dt_ref, ml.dh, GAMMA)))
+        dt_ref, want = refs[dtype]
         u_in = torch.from_numpy(np.ascontiguousarray(gin)).to(dtype).cuda().reshape(-1)
         u_out = torch.zeros(nb * 5 * 512, dtype=dtype, device="cuda")
         d_dh = torch.from_numpy(ml.dh).cuda()
         d_dt = torch.zeros(nb, dtype=torch.float64, device="cuda")
         smax = torch.zeros(1, dtype=torch.float64, device="cuda")
         b = tvd.Batch(code, nb, 8, d_dt=d_dt, d_dh=d_dh)
+        ctx.tvd_reserve(nb)
         ctx.tvd_max_signal_speed(b, u_in, tvd.TVD_LAYOUT_GHOSTED, GAMMA, smax)
         ctx.tvd_dt_from_speed(b, smax, 0.5, d_dt)
         if kernel == tvd.TVD_KERNEL_PLAIN:
-            # one launch per level on that level's contiguous range of patches
-            for lev in range(4):
+            for lev in np.unique(levels):
                 ids = np.nonzero(levels == lev)[0]
                 lo, hi = int(ids[0]), int(ids[-1]) + 1
                 assert hi - lo == ids.size
@@ -755,16 +793,39 @@ def test_multilevel_batch_one_launch(ctx):
         else:
             ctx.tvd_patch_advance(b, u_in, u_out, 0, GAMMA, flags=kernel)
         torch.cuda.synchronize()
-        want, dt_ref = ref, dt
-        if dtype == torch.float32:
-            # the oracle's own dt and step from the same FP32-rounded input
-            S32 = oracle.max_signal_speed(np.ascontiguousarray(
-                gin[:, :, 3:-3, 3:-3, 3:-3].transpose(1, 0, 2, 3, 4)).reshape(5, -1), GAMMA)
-            dt_ref = 0.5 * ml.dh / S32
-            want = np.stack(oracle.advance_ragged(list(gin), 0, dt_ref, ml.dh, GAMMA))
         np.testing.assert_allclose(d_dt.cpu().numpy(), dt_ref, rtol=1e-14)
         got = u_out.cpu().numpy().reshape(nb, 5, 8, 8, 8)
         nrm = norms(got.transpose(1, 0, 2, 3, 4).reshape(5, -1),
                     want.transpose(1, 0, 2, 3, 4).reshape(5, -1))
         note(f"{dtype} kernel {kernel}: " + str({k: f"{v['relL1']:.2e}" for k, v in nrm.items()}))
         assert worst(nrm) <= tol
+        del u_in, u_out
+
+
+def test_multilevel_batch_one_launch(ctx):
+    """Patches of levels 0-3 (dh halving per level) around Gaussian
+    overdensities, ghosts pre-filled by sibling copy or trilinear coarse-to-
+    fine interpolation; dt_b = C dh_b / S_global computed on the device.  One
+    batched launch (FP32 and FP64), one persistent FP32 launch and the plain
+    FP64 kernel launched level by level all match the oracle."""
+    note("multi-level batch")
+    ml = wl.multilevel(base=32, n_over=4, seed=3, radius=0.05)
+    assert set(np.unique(ml.levels)) == {0, 1, 2, 3}
+    _multilevel_check(ctx, ml, [(torch.float64, tvd.TVD_KERNEL_BATCHED, 1e-12),
+                                (torch.float32, tvd.TVD_KERNEL_BATCHED, 1e-5),
+                                (torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5),
+                                (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)])
+
+
+def test_multilevel_full_size_fp32(ctx):
+    """The multi-level batch at full size: a 128^3 base (4096 patches) and
+    levels 1-3 around 32 overdensities (19 592 patches in all), one
+    persistent FP32 launch and the plain FP64 kernel per level, against the
+    oracle."""
+    note("multi-level batch, full size")
+    ml = wl.multilevel()
+    counts = np.bincount(ml.levels)
+    note(f"patches per level {counts.tolist()}")
+    assert len(counts) == 4 and counts[0] == 4096 and len(ml.patches) > 15000
+    _multilevel_check(ctx, ml, [(torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5),
+                                (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)])
