@@ -14,6 +14,9 @@ Reported (one JSON line on stdout):
   (4096 blocks of 16^3 interior cells), inputs resident in HBM;
 * fp64_plain: the same steps with the plain FP64 per-patch kernel
   (32768 blocks of 8^3) on the same FP32-rounded initial state;
+* fp64_batched, fp32_batched_edge8: the batched kernel in FP64 on 8^3
+  patches (with its largest difference from fp64_plain) and in FP32 on
+  single 8^3 patches instead of 2^3 patch groups;
 * l1_vs_fp64: relative L1 error per variable of the FP32 result against
   the FP64 result after the same steps;
 * roofline: the advance kernel's algorithmic HBM bytes per launch over its
@@ -359,7 +362,7 @@ def main():
         s64 = np.stack(dev64.download())
         g32 = layout.blocks_to_grid(s32, (5, N_GRID, N_GRID, N_GRID), dev32_perm)
         g64 = layout.blocks_to_grid(s64, (5, N_GRID, N_GRID, N_GRID), dev64.bs.perm)
-        del dev64
+        del dev64, s64
         nrm = {}
         for k, nm in enumerate(["rho", "m_x", "m_y", "m_z", "e"]):
             d = np.abs(g32[k] - g64[k]).sum()
@@ -376,6 +379,28 @@ def main():
         out["l1_vs_fp64"] = {k: float(v) for k, v in nrm.items()}
         out["l1_vs_fp64"]["after_steps"] = max(args.warmup, 2) + 2 * args.steps
         log(f"bench: FP64 plain {v64 / 1e9:.3f} G cell-updates/s; relL1 {nrm}")
+        # the other two points of the comparison: the batched kernel in FP64
+        # (8^3 patches, gathering) and in FP32 on single 8^3 patches
+        torch.cuda.empty_cache()
+        others = {}
+        for name, dtype, n in (("fp64_batched", torch.float64, 8), ("fp32_batched_edge8", torch.float32, 8)):
+            log(f"bench: {name}, edge {n}, {args.warmup}+{args.steps} steps")
+            dv, rr = run_gpu(ctx, grid32, n, dtype, tvd.TVD_KERNEL_AUTO, args.steps, args.warmup,
+                             gather=True, tune=not args.no_tune)
+            vv = cells * args.steps / (rr["total_ms"] * 1e-3)
+            others[name] = {"value": vv, "unit": "cell-updates/s",
+                            "ms_per_step": rr["total_ms"] / args.steps,
+                            "avg_launch_ms": float(np.mean(rr["adv_ms"])), "blocks": rr["blocks"],
+                            "block_edge": n, "variant": rr.get("variant")}
+            if dtype == torch.float64:
+                gb = layout.blocks_to_grid(np.stack(dv.download()), (5, N_GRID, N_GRID, N_GRID),
+                                           dv.bs.perm)
+                others[name]["max_rel_diff_vs_fp64_plain"] = float(
+                    max(np.abs(gb[k] - g64[k]).max() / np.abs(g64[k]).max() for k in range(5)))
+            del dv
+            torch.cuda.empty_cache()
+            log(f"bench: {name} {vv / 1e9:.3f} G cell-updates/s")
+        out.update(others)
     if not args.no_uneven:
         log("bench: uneven batch of 4000 boxes")
         torch.cuda.empty_cache()
