@@ -42,10 +42,9 @@ template <> struct Num<double> {
 
 // Per-block coefficients of one sweep.
 template <typename T> struct Coef {
-  T gamma;    // ratio of specific heats
-  T qgamma;   // gamma / 4
-  T gm1;      // gamma - 1
-  T pfloor;   // pressure floor
+  T hgamma;   // gamma / 2
+  T hgm1;     // (gamma - 1) / 2
+  T hpfloor;  // pressure floor / 2
   T lam;      // dt / dh
   T hlam;     // dt / (2 dh)
 };
@@ -67,20 +66,21 @@ __device__ __forceinline__ void split_flux(const T u[kNV], const Coef<T>& cf, T 
                                            T FL[kNV]) {
   using F = Num<T>;
   const T inv = F::rcp(u[0]);
-  const T vn = u[1] * inv;
   const T mt2 = u[2] * u[2] + u[3] * u[3];
   const T m2 = F::fma(u[1], u[1], mt2);
-  const T P = F::max(cf.gm1 * F::fma(T(-0.5) * m2, inv, u[4]), cf.pfloor);
-  // c/2 = |v_n|/2 + sqrt(gamma P / (4 rho)); the halving is exact
-  const T hcs = F::sqrt((cf.qgamma * P) * inv);
-  const T hc = F::fma(T(0.5), F::abs(vn), hcs);
-  const T hv = T(0.5) * vn;
+  // Everything is carried at half scale, which is exact (scaling by 2^-1
+  // commutes with rounding): hP = P*/2 = max((gamma-1)/2 (e - m^2/2rho),
+  // p_floor/2), v_n/2 = (m_n/2)/rho, c/2 = |v_n/2| + sqrt((gamma/2)(P*/2)/rho).
+  const T hP = F::max(cf.hgm1 * F::fma(T(-0.5) * m2, inv, u[4]), cf.hpfloor);
+  const T hcs = F::sqrt((cf.hgamma * hP) * inv);
   T hF[kNV];
   hF[0] = T(0.5) * u[1];
-  hF[1] = F::fma(u[1], hv, T(0.5) * P);
+  const T hv = hF[0] * inv;
+  const T hc = F::abs(hv) + hcs;
+  hF[1] = F::fma(u[1], hv, hP);
   hF[2] = u[2] * hv;
   hF[3] = u[3] * hv;
-  hF[4] = (u[4] + P) * hv;
+  hF[4] = F::fma(T(2), hP, u[4]) * hv;  // (e + P*) v_n / 2
 #pragma unroll
   for (int k = 0; k < kNV; ++k) {
     FR[k] = F::fma(hc, u[k], hF[k]);

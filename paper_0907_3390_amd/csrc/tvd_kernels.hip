@@ -156,10 +156,11 @@ __device__ __forceinline__ Coef<T> make_coef(const KParams& kp, int b, double& d
   dh_out = dh;
   const double lam = dt / dh;  // FP64, rounded once to T
   Coef<T> cf;
-  cf.gamma = T(kp.gamma);
-  cf.qgamma = T(0.25 * kp.gamma);
-  cf.gm1 = T(kp.gamma - 1.0);
-  cf.pfloor = T(kp.pfloor);
+  // halves of the rounded gamma - 1 and floor: exact, so P*/2 is exactly half
+  // of max((gamma - 1)(e - K), p_floor) evaluated in T
+  cf.hgamma = T(0.5 * kp.gamma);
+  cf.hgm1 = T(0.5) * T(kp.gamma - 1.0);
+  cf.hpfloor = T(0.5) * T(kp.pfloor);
   cf.lam = T(lam);
   cf.hlam = T(0.5 * lam);
   return cf;
