@@ -23,7 +23,10 @@ Reported (one JSON line on stdout):
   average duration (HIP events on the launch stream) against 8 TB/s;
 * cpu_baseline: the FP64 oracle on the host cores over a bounded sample;
 * uneven_batch: cell-updates/s of 4000 periodic boxes of mixed sizes in one
-  persistent launch per step, 50-step HIP graphs, block edge tuned.
+  persistent launch per step, 50-step HIP graphs, block edge tuned;
+* multilevel_batch: one step of a 4-level patch hierarchy (19 592 patches,
+  per-block dt and dh) as one persistent FP32 launch on patches and on 2^3
+  patch groups, and as plain FP64 launches level by level.
 """
 from __future__ import annotations
 
@@ -216,6 +219,76 @@ def run_uneven(ctx, graph_steps=50):
     return res
 
 
+def run_multilevel(ctx, reps=10):
+    """The multi-level batch: a 128^3 base of 8^3 patches and levels 1-3
+    around 32 seeded overdensities (19 592 patches, ghost zones pre-filled by
+    sibling copy or trilinear coarse-to-fine interpolation), per-block dt_b =
+    C dh_b / S computed on the device.  Timed: one step of every patch as one
+    persistent FP32 launch on the patches and on their 2^3 patch groups (16^3
+    blocks), against the plain FP64 kernel launched level by level."""
+    import torch
+    from paper_0907_3390_amd import tvd, workloads as wl
+    ml = wl.multilevel()
+    groups, G, gdh = ml.group_blocks()
+    cells = len(ml.patches) * 512
+    res = {"workload": "multi-level batch: 128^3 base + levels 1-3 around 32 Gaussian "
+                       "overdensities (seed 3), ghosts pre-filled, gas at rest, P = 1",
+           "patches": len(ml.patches), "patches_per_level": np.bincount(ml.levels).tolist(),
+           "patch_groups": len(groups), "cells": cells}
+    stream = torch.cuda.current_stream()
+    for name, ghosted, dhs, levels, edge, dtype, kernel in (
+            ("fp32_persistent_patches", ml.ghosted, ml.dh, ml.levels, 8, torch.float32,
+             tvd.TVD_KERNEL_PERSISTENT),
+            ("fp32_persistent_groups", G, gdh, np.array([g[0] for g in groups]), 16, torch.float32,
+             tvd.TVD_KERNEL_PERSISTENT),
+            ("fp64_plain_per_level", ml.ghosted, ml.dh, ml.levels, 8, torch.float64,
+             tvd.TVD_KERNEL_PLAIN)):
+        nb, m = len(dhs), edge + 6
+        code = tvd.dtype_code(dtype)
+        u_in = torch.from_numpy(np.ascontiguousarray(ghosted)).to(dtype).cuda().reshape(-1)
+        u_out = torch.zeros(nb * 5 * edge ** 3, dtype=dtype, device="cuda")
+        d_dh = torch.from_numpy(np.ascontiguousarray(dhs)).cuda()
+        d_dt = torch.zeros(nb, dtype=torch.float64, device="cuda")
+        smax = torch.zeros(1, dtype=torch.float64, device="cuda")
+        b = tvd.Batch(code, nb, edge, d_dt=d_dt, d_dh=d_dh)
+        ctx.tvd_reserve(nb)
+        ctx.tvd_max_signal_speed(b, u_in, tvd.TVD_LAYOUT_GHOSTED, GAMMA, smax)
+        ctx.tvd_dt_from_speed(b, smax, CFL, d_dt)
+        if kernel == tvd.TVD_KERNEL_PLAIN:
+            ranges = []
+            for lev in np.unique(levels):
+                ids = np.nonzero(levels == lev)[0]
+                lo, hi = int(ids[0]), int(ids[-1]) + 1
+                ranges.append((tvd.Batch(code, hi - lo, edge, d_dt=d_dt[lo:hi], d_dh=d_dh[lo:hi]),
+                               u_in[lo * 5 * m ** 3:], u_out[lo * 5 * edge ** 3:]))
+
+            def step(o):
+                for bl, ui, uo in ranges:
+                    ctx.tvd_patch_advance(bl, ui, uo, o, GAMMA, flags=kernel)
+        else:
+            def step(o):
+                ctx.tvd_patch_advance(b, u_in, u_out, o, GAMMA, flags=kernel)
+        for o in (0, 1):
+            step(o)
+        a = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for r in range(reps):
+            step(r % 2)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e) / reps
+        res[name] = {"value": cells / (ms * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms,
+                     "blocks": nb, "block_edge": edge,
+                     "launches_per_step": len(np.unique(levels)) if kernel == tvd.TVD_KERNEL_PLAIN else 1}
+        log(f"bench: multi-level {name}: {res[name]['value'] / 1e9:.2f} G cell-updates/s")
+        del u_in, u_out
+        torch.cuda.empty_cache()
+    res["speedup_fp32_groups_vs_fp64_plain"] = (res["fp32_persistent_groups"]["value"] /
+                                                res["fp64_plain_per_level"]["value"])
+    return res
+
+
 def cpu_baseline(grid32, budget_s=15.0):
     """The FP64 oracle (as it stands) on the host cores over a bounded sample
     of the same workload: whole steps of the 256^3 grid as 32768 patches of
@@ -273,6 +346,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-variant tuner")
+    ap.add_argument("--no-multilevel", action="store_true",
+                    help="skip the multi-level (19 592 patches) throughput")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch (4000 mixed boxes) throughput")
     ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
@@ -401,6 +476,10 @@ def main():
             torch.cuda.empty_cache()
             log(f"bench: {name} {vv / 1e9:.3f} G cell-updates/s")
         out.update(others)
+    if not args.no_multilevel:
+        log("bench: multi-level batch")
+        torch.cuda.empty_cache()
+        out["multilevel_batch"] = run_multilevel(ctx)
     if not args.no_uneven:
         log("bench: uneven batch of 4000 boxes")
         torch.cuda.empty_cache()

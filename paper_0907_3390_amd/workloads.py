@@ -196,38 +196,119 @@ class MultiLevel:
 
     ``patches`` lists (level, px, py, pz) patch coordinates; ``ghosted`` holds
     the (5, 14, 14, 14) FP64 ghosted block of every patch; ``dh`` the zone
-    size of each patch (1 / (base * 2^level))."""
+    size of each patch (1 / (base * 2^level)).  ``group_blocks()`` gives the
+    same hierarchy as 2^3 patch groups (16^3 blocks, 22^3 ghosted)."""
     base: int
     patches: list = field(default_factory=list)
     ghosted: np.ndarray | None = None
     dh: np.ndarray | None = None
+    rho_f: object = None
+    P0: float = 1.0
+    gamma: float = GAMMA
 
     @property
     def levels(self):
         return np.array([p[0] for p in self.patches])
 
+    def group_blocks(self):
+        """The patches as 2^3 patch groups (Sec. 3.1): every family of eight
+        siblings (level >= 1), and every aligned 2^3 set of root patches,
+        becomes one 16^3 block with three ghost zones, filled by the same
+        rule as the patches' (sibling copy where a same-level patch exists,
+        else trilinear from the next coarser level).  Returns (groups
+        [(level, gx, gy, gz)], ghosted (G, 5, 22, 22, 22), dh (G,)), groups
+        ordered by level; the cells of group (l, g) are those of patches
+        (l, 2g + c), c in {0, 1}^3."""
+        by_lev = {}
+        for lev, px, py, pz in self.patches:
+            by_lev.setdefault(lev, set()).add((px // 2, py // 2, pz // 2))
+        groups = [(lev, *g) for lev in sorted(by_lev) for g in sorted(by_lev[lev], key=lambda t: (t[2], t[1], t[0]))]
+        for lev, gx, gy, gz in groups:
+            for c in range(8):
+                if (lev, 2 * gx + (c & 1), 2 * gy + (c >> 1 & 1), 2 * gz + (c >> 2)) not in self._present:
+                    raise ValueError("a patch group is incomplete")
+        levels = [np.array([g[1:] for g in groups if g[0] == lev], dtype=np.int64).reshape(-1, 3)
+                  for lev in range(max(by_lev) + 1)]
+        g, dh = _ghosted_blocks(self, levels, 16)
+        return groups, g, dh
+
+
+def _ghosted_blocks(ml, levels, e):
+    """Ghosted blocks of edge e (8: patches, 16: 2^3 patch groups) at the block
+    coordinates levels[l] (array [P, 3]) of each level: cells take the field
+    at their centres where a same-level patch covers them, else the trilinear
+    interpolant of the next coarser level's cell centres (conserved
+    variables; gas at rest, P = P0)."""
+    n = 8
+    m = e + 6
+    total = sum(len(b) for b in levels)
+    g = np.empty((total, 5, m, m, m))
+    dh = np.empty(total)
+    off = np.arange(m) - 3 + 0.5  # ghosted cell centres in units of h, relative to the block
+    # patch index (relative to the block's first patch, +1) of each ghosted cell
+    reg = (np.arange(m) - 3) // n + 1
+    nr = e // n + 2
+    base_i = 0
+    for lev, bcs in enumerate(levels):
+        if len(bcs) == 0:
+            continue
+        h = 1.0 / (ml.base * 2 ** lev)
+        xs, ys, zs = [(bcs[:, a, None] * e + off[None, :]) * h for a in range(3)]
+        fine = ml.rho_f(xs % 1.0, ys % 1.0, zs % 1.0)
+        if lev > 0:
+            # cells whose same-level patch does not exist: interpolate from the
+            # coarser level's cell centres (trilinear, periodic)
+            npl = ml.base * 2 ** lev // n
+            q = e // n
+            have = np.array([[((lev, (q * bx + rx - 1) % npl, (q * by + ry - 1) % npl,
+                                (q * bz + rz - 1) % npl) in ml._present)
+                              for rz in range(nr) for ry in range(nr) for rx in range(nr)]
+                             for bx, by, bz in bcs]).reshape(-1, nr, nr, nr)
+            cover = have[:, reg[:, None, None], reg[None, :, None], reg[None, None, :]]
+            need = np.nonzero(~cover.reshape(len(bcs), -1).all(axis=1))[0]
+            if need.size:
+                H = 2.0 * h
+                # per axis: coarse cell below each fine centre and the weight
+                f_ = [a[need] / H - 0.5 for a in (xs, ys, zs)]
+                i_ = [np.floor(a) for a in f_]
+                t_ = [a - b for a, b in zip(f_, i_)]
+                interp = np.zeros((need.size, m, m, m))
+                for dz_ in (0, 1):
+                    for dy_ in (0, 1):
+                        for dx_ in (0, 1):
+                            w = [t if d else 1 - t for t, d in zip(t_, (dx_, dy_, dz_))]
+                            wgt = w[2][:, :, None, None] * w[1][:, None, :, None] * w[0][:, None, None, :]
+                            interp += wgt * ml.rho_f(((i_[0] + dx_ + 0.5) * H) % 1.0,
+                                                     ((i_[1] + dy_ + 0.5) * H) % 1.0,
+                                                     ((i_[2] + dz_ + 0.5) * H) % 1.0)
+                fine[need] = np.where(cover[need], fine[need], interp)
+        k = len(bcs)
+        g[base_i:base_i + k] = np.moveaxis(
+            conserved(fine, 0.0, 0.0, 0.0, np.full(fine.shape, ml.P0), ml.gamma), 0, 1)
+        dh[base_i:base_i + k] = h
+        base_i += k
+    return g, dh
+
 
 def _gaussian_field(centres, amps, radii):
-    """rho on tensor-product point sets: rho(xs, ys, zs) with per-patch axis
+    """rho on tensor-product point sets: rho(xs, ys, zs) with per-block axis
     coordinates of shape (P, k) returns (P, k, k, k) values (z, y, x order) of
     1 + sum_k A_k exp(-d^2 / 2 r_k^2), d the periodic distance in the unit box.
-    Each Gaussian factorises into three 1-D factors.  A Gaussian whose tail
-    cannot reach a patch (centre farther than 8 r_k plus the patch's extent
-    from the patch's mean point, i.e. below exp(-32) relative) is skipped for
-    that patch."""
+    Each Gaussian factorises into three 1-D factors, and a factor is cut to 0
+    where that axis' distance exceeds 8 r_k (below exp(-32) relative): a
+    rule per cell, so the value of a cell does not depend on which block it
+    is evaluated in.  Blocks with no cell inside the cut skip the Gaussian."""
     def rho(xs, ys, zs):
         P, k = xs.shape
         out = np.ones((P, k, k, k))
-        mean = [a.mean(axis=1) for a in (xs, ys, zs)]
-        ext = np.max([np.ptp(a, axis=1) for a in (xs, ys, zs)], axis=0)
         for (cx, cy, cz), amp, r in zip(centres, amps, radii):
-            d = np.sqrt(sum(((m_ - c_ + 0.5) % 1.0 - 0.5) ** 2
-                            for m_, c_ in zip(mean, (cx, cy, cz))))
-            sel = np.nonzero(d - ext <= 8.0 * r)[0]
+            d = [(a - c + 0.5) % 1.0 - 0.5 for a, c in ((xs, cx), (ys, cy), (zs, cz))]
+            inside = [np.abs(x) <= 8.0 * r for x in d]
+            sel = np.nonzero(inside[0].any(axis=1) & inside[1].any(axis=1) & inside[2].any(axis=1))[0]
             if sel.size == 0:
                 continue
-            f = [np.exp(-(((a[sel] - c + 0.5) % 1.0 - 0.5) ** 2) / (2.0 * r * r))
-                 for a, c in ((xs, cx), (ys, cy), (zs, cz))]
+            f = [np.where(ins[sel], np.exp(-(x[sel] ** 2) / (2.0 * r * r)), 0.0)
+                 for x, ins in zip(d, inside)]
             out[sel] += amp * (f[2][:, :, None, None] * f[1][:, None, :, None] *
                                f[0][:, None, None, :])
         return out
@@ -279,50 +360,9 @@ def multilevel(base: int = 128, n_over: int = 32, seed: int = 3, max_level: int 
             break
     allp = [(lev, int(p[0]), int(p[1]), int(p[2])) for lev, pcs in enumerate(levels) for p in pcs]
     ml.patches = allp
-    present = set(allp)
-
-    m = n + 6
-    g = np.empty((len(allp), 5, m, m, m))
-    dh = np.empty(len(allp))
-    off = np.arange(m) - 3 + 0.5  # ghosted cell centres in units of h, relative to the patch
-    reg = np.where(np.arange(m) < 3, 0, np.where(np.arange(m) >= n + 3, 2, 1))
-    base_i = 0
-    for lev, pcs in enumerate(levels):
-        if len(pcs) == 0:
-            continue
-        h = 1.0 / (base * 2 ** lev)
-        xs, ys, zs = axes_of(pcs, h, off)
-        fine = rho_f(xs % 1.0, ys % 1.0, zs % 1.0)
-        if lev > 0:
-            # cells whose same-level patch does not exist: interpolate from the
-            # coarser level's cell centres (trilinear, periodic)
-            npl = base * 2 ** lev // n
-            have = np.array([[((lev, (px + rx - 1) % npl, (py + ry - 1) % npl, (pz + rz - 1) % npl)
-                               in present) for rz in range(3) for ry in range(3) for rx in range(3)]
-                             for px, py, pz in pcs]).reshape(-1, 3, 3, 3)
-            cover = have[:, reg[:, None, None], reg[None, :, None], reg[None, None, :]]
-            need = np.nonzero(~cover.reshape(len(pcs), -1).all(axis=1))[0]
-            if need.size:
-                H = 2.0 * h
-                # per axis: coarse cell below each fine centre and the weight
-                f_ = [a[need] / H - 0.5 for a in (xs, ys, zs)]
-                i_ = [np.floor(a) for a in f_]
-                t_ = [a - b for a, b in zip(f_, i_)]
-                interp = np.zeros((need.size, m, m, m))
-                for dz_ in (0, 1):
-                    for dy_ in (0, 1):
-                        for dx_ in (0, 1):
-                            w = [t if d else 1 - t for t, d in zip(t_, (dx_, dy_, dz_))]
-                            wgt = w[2][:, :, None, None] * w[1][:, None, :, None] * w[0][:, None, None, :]
-                            interp += wgt * rho_f(((i_[0] + dx_ + 0.5) * H) % 1.0,
-                                                  ((i_[1] + dy_ + 0.5) * H) % 1.0,
-                                                  ((i_[2] + dz_ + 0.5) * H) % 1.0)
-                fine[need] = np.where(cover[need], fine[need], interp)
-        k = len(pcs)
-        g[base_i:base_i + k] = np.moveaxis(
-            conserved(fine, 0.0, 0.0, 0.0, np.full(fine.shape, P0), gamma), 0, 1)
-        dh[base_i:base_i + k] = h
-        base_i += k
+    ml._present = set(allp)
+    ml.rho_f, ml.P0, ml.gamma = rho_f, P0, gamma
+    g, dh = _ghosted_blocks(ml, levels, n)
     ml.ghosted = g
     ml.dh = dh
     return ml

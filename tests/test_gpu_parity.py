@@ -756,29 +756,30 @@ def test_sedov_128cube_100_steps_fp32(ctx):
 # multi-level batch: per-block dt and dh in one launch
 # ---------------------------------------------------------------------------
 
-def _multilevel_check(ctx, ml, cases):
-    """One step of every patch of ml with dt_b = C dh_b / S_global computed on
-    the device, for each (dtype, kernel, tol) case, against the oracle's own
-    dt and step from the same (FP32-rounded for FP32) input.  The plain FP64
-    kernel is launched level by level on each level's contiguous range."""
-    levels = ml.levels
-    nb = len(ml.patches)
+def _multilevel_check(ctx, ghosted, dhs, levels, edge, cases):
+    """One step of every block (8^3 patches or 16^3 patch groups, ghosted)
+    with dt_b = C dh_b / S_global computed on the device, for each (dtype,
+    kernel, tol) case, against the oracle's own dt and step from the same
+    (FP32-rounded for FP32) input.  The plain FP64 kernel is launched level by
+    level on each level's contiguous range."""
+    nb = len(dhs)
+    m, n = edge + 6, edge
     refs = {}
     for dtype, kernel, tol in cases:
         code = tvd.dtype_code(dtype)
-        gin = ml.ghosted.astype(np.float32).astype(np.float64) if dtype == torch.float32 else ml.ghosted
+        gin = ghosted.astype(np.float32).astype(np.float64) if dtype == torch.float32 else ghosted
         if dtype not in refs:
             S = oracle.max_signal_speed(np.ascontiguousarray(
                 gin[:, :, 3:-3, 3:-3, 3:-3].transpose(1, 0, 2, 3, 4)).reshape(5, -1), GAMMA)
-            dt_ref = 0.5 * ml.dh / S
-            refs[dtype] = (dt_ref, np.stack(oracle.advance_ragged(list(gin), 0, dt_ref, ml.dh, GAMMA)))
+            dt_ref = 0.5 * dhs / S
+            refs[dtype] = (dt_ref, np.stack(oracle.advance_ragged(list(gin), 0, dt_ref, dhs, GAMMA)))
         dt_ref, want = refs[dtype]
         u_in = torch.from_numpy(np.ascontiguousarray(gin)).to(dtype).cuda().reshape(-1)
-        u_out = torch.zeros(nb * 5 * 512, dtype=dtype, device="cuda")
-        d_dh = torch.from_numpy(ml.dh).cuda()
+        u_out = torch.zeros(nb * 5 * n ** 3, dtype=dtype, device="cuda")
+        d_dh = torch.from_numpy(np.ascontiguousarray(dhs)).cuda()
         d_dt = torch.zeros(nb, dtype=torch.float64, device="cuda")
         smax = torch.zeros(1, dtype=torch.float64, device="cuda")
-        b = tvd.Batch(code, nb, 8, d_dt=d_dt, d_dh=d_dh)
+        b = tvd.Batch(code, nb, edge, d_dt=d_dt, d_dh=d_dh)
         ctx.tvd_reserve(nb)
         ctx.tvd_max_signal_speed(b, u_in, tvd.TVD_LAYOUT_GHOSTED, GAMMA, smax)
         ctx.tvd_dt_from_speed(b, smax, 0.5, d_dt)
@@ -787,17 +788,17 @@ def _multilevel_check(ctx, ml, cases):
                 ids = np.nonzero(levels == lev)[0]
                 lo, hi = int(ids[0]), int(ids[-1]) + 1
                 assert hi - lo == ids.size
-                bl = tvd.Batch(code, hi - lo, 8, d_dt=d_dt[lo:hi], d_dh=d_dh[lo:hi])
-                ctx.tvd_patch_advance(bl, u_in[lo * 5 * 14 ** 3:], u_out[lo * 5 * 512:], 0, GAMMA,
+                bl = tvd.Batch(code, hi - lo, edge, d_dt=d_dt[lo:hi], d_dh=d_dh[lo:hi])
+                ctx.tvd_patch_advance(bl, u_in[lo * 5 * m ** 3:], u_out[lo * 5 * n ** 3:], 0, GAMMA,
                                       flags=kernel)
         else:
             ctx.tvd_patch_advance(b, u_in, u_out, 0, GAMMA, flags=kernel)
         torch.cuda.synchronize()
         np.testing.assert_allclose(d_dt.cpu().numpy(), dt_ref, rtol=1e-14)
-        got = u_out.cpu().numpy().reshape(nb, 5, 8, 8, 8)
+        got = u_out.cpu().numpy().reshape(nb, 5, n, n, n)
         nrm = norms(got.transpose(1, 0, 2, 3, 4).reshape(5, -1),
                     want.transpose(1, 0, 2, 3, 4).reshape(5, -1))
-        note(f"{dtype} kernel {kernel}: " + str({k: f"{v['relL1']:.2e}" for k, v in nrm.items()}))
+        note(f"edge {edge} {dtype} kernel {kernel}: " + str({k: f"{v['relL1']:.2e}" for k, v in nrm.items()}))
         assert worst(nrm) <= tol
         del u_in, u_out
 
@@ -807,25 +808,36 @@ def test_multilevel_batch_one_launch(ctx):
     overdensities, ghosts pre-filled by sibling copy or trilinear coarse-to-
     fine interpolation; dt_b = C dh_b / S_global computed on the device.  One
     batched launch (FP32 and FP64), one persistent FP32 launch and the plain
-    FP64 kernel launched level by level all match the oracle."""
+    FP64 kernel launched level by level all match the oracle; so does the
+    same hierarchy as 2^3 patch groups of 16^3 in one FP32 launch."""
     note("multi-level batch")
     ml = wl.multilevel(base=32, n_over=4, seed=3, radius=0.05)
     assert set(np.unique(ml.levels)) == {0, 1, 2, 3}
-    _multilevel_check(ctx, ml, [(torch.float64, tvd.TVD_KERNEL_BATCHED, 1e-12),
-                                (torch.float32, tvd.TVD_KERNEL_BATCHED, 1e-5),
-                                (torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5),
-                                (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)])
+    _multilevel_check(ctx, ml.ghosted, ml.dh, ml.levels, 8,
+                      [(torch.float64, tvd.TVD_KERNEL_BATCHED, 1e-12),
+                       (torch.float32, tvd.TVD_KERNEL_BATCHED, 1e-5),
+                       (torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5),
+                       (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)])
+    groups, G, gdh = ml.group_blocks()
+    glev = np.array([g[0] for g in groups])
+    _multilevel_check(ctx, G, gdh, glev, 16,
+                      [(torch.float32, tvd.TVD_KERNEL_BATCHED, 1e-5),
+                       (torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5)])
 
 
 def test_multilevel_full_size_fp32(ctx):
     """The multi-level batch at full size: a 128^3 base (4096 patches) and
-    levels 1-3 around 32 overdensities (19 592 patches in all), one
-    persistent FP32 launch and the plain FP64 kernel per level, against the
-    oracle."""
+    levels 1-3 around 32 overdensities (19 592 patches in all): one persistent
+    FP32 launch on the patches and on their 2^3 patch groups (2449 blocks of
+    16^3), and the plain FP64 kernel per level, against the oracle."""
     note("multi-level batch, full size")
     ml = wl.multilevel()
     counts = np.bincount(ml.levels)
     note(f"patches per level {counts.tolist()}")
     assert len(counts) == 4 and counts[0] == 4096 and len(ml.patches) > 15000
-    _multilevel_check(ctx, ml, [(torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5),
-                                (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)])
+    _multilevel_check(ctx, ml.ghosted, ml.dh, ml.levels, 8,
+                      [(torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5),
+                       (torch.float64, tvd.TVD_KERNEL_PLAIN, 1e-12)])
+    groups, G, gdh = ml.group_blocks()
+    _multilevel_check(ctx, G, gdh, np.array([g[0] for g in groups]), 16,
+                      [(torch.float32, tvd.TVD_KERNEL_PERSISTENT, 1e-5)])
