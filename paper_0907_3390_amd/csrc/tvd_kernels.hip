@@ -546,7 +546,7 @@ constexpr int kXcds = 8;
 // the variants the persistent kernel runs (edge 16 on the whole workgroup,
 // edge 8 on each quarter)
 constexpr int kFusedPad16 = 16, kFusedSplit16 = 3;
-constexpr int kFusedPad8 = 8, kFusedSplit8 = 0;
+constexpr int kFusedPad8 = 8, kFusedSplit8 = 2;
 
 __global__ __launch_bounds__(kPlanNT) void k_plan(const int32_t* __restrict__ edge, int uniform,
                                                   int n, FusedPlan pl,
