@@ -363,9 +363,15 @@ struct BlockLds {
 // remaining pencils are split in halves over the other threads, so that all
 // four SIMDs carry about the same number of wave-pencils.
 // Sweep 2 (SPLIT bit 1): every pencil is split in halves over all threads.
+//
+// lookahead (persistent launch, one thread of the workgroup): a work counter
+// to draw the next ticket from once the second sweep is done, so that the
+// atomic's latency hides behind the third sweep; the ticket goes to *ticket.
 template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER>
 __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
-                                              BlockLds<T, N, PAD>& sm) {
+                                              BlockLds<T, N, PAD>& sm,
+                                              unsigned* lookahead = nullptr,
+                                              int* ticket = nullptr) {
   using L = LdsLayout<N, PAD>;
   constexpr int M = N + 2 * kG;
   constexpr int M3 = M * M * M;
@@ -473,6 +479,7 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
     }
   }
   __syncthreads();
+  if (lookahead) *ticket = (int)atomicAdd(lookahead, 1u);
   // sweep 2: interior along c0 and c1, results straight to HBM with the
   // per-cell diagnostics (a pencil at (c0, c1) is the column x = c0,
   // y = c1 - 3 along z for xyz, or z = c0, y = c1 - 3 along x for zyx)
@@ -629,7 +636,10 @@ __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
   const int xcd = blockIdx.x % kXcds;
   const int n16 = pl.count[0], n8 = pl.count[1];
   const int nq = (n8 + 3) / 4;
-  int qi = 0;  // queues drained so far (thread 0 only)
+  // thread 0 only: queues drained so far, and the ticket drawn during the
+  // previous item from queue (xcd + qi) % kXcds (-1: none)
+  int qi = 0;
+  int ticket = -1;
   for (;;) {
     if (threadIdx.x == 0) {
       int wi = -1;
@@ -637,7 +647,8 @@ __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
         const int x = (xcd + qi) % kXcds;
         const int lo16 = part_lo(n16, x), hi16 = part_lo(n16, x + 1);
         const int loq = part_lo(nq, x), hiq = part_lo(nq, x + 1);
-        const int k = (int)atomicAdd(&pl.next[x], 1u);
+        const int k = ticket >= 0 ? ticket : (int)atomicAdd(&pl.next[x], 1u);
+        ticket = -1;
         if (k < hi16 - lo16) {
           wi = lo16 + k;
           break;
@@ -653,6 +664,8 @@ __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
     const int wi = item;
     __syncthreads();
     if (wi < 0) break;  // uniform over the workgroup
+    // thread 0 draws the next ticket from its current queue late in this item
+    unsigned* const ahead = threadIdx.x == 0 ? &pl.next[(xcd + qi) % kXcds] : nullptr;
     // The thread index is passed through an empty asm statement (no
     // instruction) so that the per-thread pencil indexing of every sweep is
     // recomputed per item: hoisted out of the loop it stays live across all
@@ -661,13 +674,14 @@ __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
     asm volatile("" : "+v"(tid));
     if (wi < n16) {
       advance_block<T, 16, ORDER, 512, kFusedPad16, kFusedSplit16, GATHER>(kp, pl.list[wi], tid,
-                                                                          sm);
+                                                                          sm, ahead, &ticket);
     } else {
       const int q = tid >> 7;
       const int i = 4 * (wi - n16) + q;
       const int b = i < n8 ? pl.list[n16 + i] : -1;
       B8* quarter = reinterpret_cast<B8*>(&sm) + q;
-      advance_block<T, 8, ORDER, 128, kFusedPad8, kFusedSplit8, GATHER>(kp, b, tid & 127, *quarter);
+      advance_block<T, 8, ORDER, 128, kFusedPad8, kFusedSplit8, GATHER>(kp, b, tid & 127, *quarter,
+                                                                        ahead, &ticket);
     }
   }
 }
