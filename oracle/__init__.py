@@ -94,6 +94,15 @@ def use_library(path: str | None):
     _lib = None if path is None else _bind(path)
 
 
+def set_threads(n: int):
+    """Number of OpenMP threads the batch advance uses from now on (the
+    OpenMP runtime the library links; a timing knob, no arithmetic)."""
+    fn = _load().omp_set_num_threads
+    fn.restype = None
+    fn.argtypes = [ctypes.c_int]
+    fn(int(n))
+
+
 def _dptr(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
