@@ -17,6 +17,9 @@ Chiueh (GAMER, 2010) it follows:
 * ``max_signal_speed`` Eq. (CFL)
 * ``periodic_ghosted_blocks`` / ``run_periodic``: the step driver on a
                        uniform periodic grid cut into cubic blocks.
+* ``oracle.ghosts``    Sec. 2.2 coarse-fine ghost zones: sibling copy, else
+                       linear interpolation with the Min-Mod limiter from one
+                       level coarser (numpy).
 """
 from __future__ import annotations
 
