@@ -256,6 +256,37 @@ int tvd_read_flags(tvd_ctx *ctx, int64_t *n_floored, int64_t *n_nonphysical,
 int tvd_fill_ghosts(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
                     const void *d_interior, void *d_ghosted, void *stream);
 
+/*
+ * Ghost zones on a coarse-fine boundary (Sec. 2.2: a ghost cell is copied
+ * from the sibling patch when it exists, otherwise filled by linear
+ * interpolation with the Min-Mod limiter from the patches one level
+ * coarser).  For every fine block b and every cell of its ghosted copy in
+ * d_fine_ghosted (the fine batch's in offsets):
+ *   - if d_nbr[27*b + r] >= 0 for the cell's region r (as for
+ *     tvd_fill_ghosts, r = 13 being b itself), the cell is copied from that
+ *     block's interior in d_fine_interior (the fine batch's out offsets);
+ *   - otherwise, per variable, with f the cell's fine index relative to the
+ *     corner of b's parent (f = 2 * d_corigin[3*b + axis] + cell - 3 along
+ *     each axis), c = floor(f / 2) the coarse cell and d = -1/4 (f even) or
+ *     +1/4 (f odd): u_c + dx s_x + dy s_y + dz s_z, summed in that order,
+ *     s_axis = minmod(u_{c+1} - u_c, u_c - u_{c-1}) along the axis, minmod
+ *     being 0 unless both differences are positive or both negative, else
+ *     the one of smaller magnitude (the second on a tie).
+ * The coarse level is a batch of 8^3 patches (uniform edge 8, interiors in
+ * d_coarse_interior at its out offsets, same dtype).  d_cnbr[27*b + r] names
+ * the coarse patch at offset r around b's parent (r = 13: the parent), and
+ * d_corigin[3*b + 0..2] (x, y, z) is b's lower corner, in coarse cells,
+ * relative to the parent's: 0 or 4 for 8^3 fine patches, 0 for 16^3 groups.
+ * A cell whose coarse stencil leaves those 27 patches, or names a coarse
+ * index outside [0, coarse n_blocks), is left untouched and counted as
+ * non-physical.  Proper nesting (every parent has its 26 neighbours) makes
+ * every entry valid.  Asynchronous on stream.
+ */
+int tvd_fill_ghosts_amr(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nbr,
+                        const void *d_fine_interior, void *d_fine_ghosted,
+                        const tvd_batch *coarse, const void *d_coarse_interior,
+                        const int32_t *d_cnbr, const int32_t *d_corigin, void *stream);
+
 /* ---- step sequences as HIP graphs --------------------------------------------- */
 
 typedef struct tvd_graph tvd_graph;

@@ -583,4 +583,33 @@ int tvd_fill_ghosts(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   return TVD_OK;
 }
 
+int tvd_fill_ghosts_amr(tvd_ctx* ctx, const tvd_batch* fine, const int32_t* d_nbr,
+                        const void* d_fine_interior, void* d_fine_ghosted,
+                        const tvd_batch* coarse, const void* d_coarse_interior,
+                        const int32_t* d_cnbr, const int32_t* d_corigin, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, fine);
+  if (st) return st;
+  if ((st = check_batch(ctx, coarse))) return st;
+  if (coarse->dtype != fine->dtype)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "coarse and fine batches differ in dtype");
+  if (coarse->d_edge || coarse->edge != 8)
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "coarse blocks must be 8^3 patches (uniform edge 8)");
+  if (fine->n_blocks == 0) return TVD_OK;
+  if (!d_nbr || !d_fine_interior || !d_fine_ghosted || !d_coarse_interior || !d_cnbr ||
+      !d_corigin)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if (d_fine_interior == d_fine_ghosted || d_coarse_interior == d_fine_ghosted)
+    return fail(ctx, TVD_ERR_ALIAS, "an input is the ghosted output");
+  DeviceGuard g(ctx->device);
+  const tvd::KParams kp = make_params(ctx, fine, d_fine_ghosted,
+                                      const_cast<void*>(d_fine_interior), 1.0, 0.0);
+  const int max_edge = fine->d_edge ? 16 : fine->edge;
+  hipError_t e = tvd::launch_fill_ghosts_amr(fine->dtype, kp, d_nbr, max_edge, d_coarse_interior,
+                                             coarse->d_out_off, coarse->n_blocks, d_cnbr,
+                                             d_corigin, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "coarse-fine ghost fill launch");
+  return TVD_OK;
+}
+
 }  // extern "C"

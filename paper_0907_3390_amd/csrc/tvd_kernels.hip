@@ -895,6 +895,106 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32
 }
 
 // ---------------------------------------------------------------------------
+// coarse-fine ghost fill: sibling copy, else Min-Mod limited linear
+// interpolation from the level one coarser (Sec. 2.2)
+// ---------------------------------------------------------------------------
+
+// Min-Mod limiter: 0 unless a and b are both positive or both negative, then
+// the one of smaller magnitude (b on a tie).
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  const bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
+  return same ? (Num<T>::abs(a) < Num<T>::abs(b) ? a : b) : T(0);
+}
+
+// Coarse blocks are 8^3 patches; cin points at the coarse interiors, cnbr at
+// the 27 coarse patches around the fine block's parent.  Coarse index i
+// (per axis, relative to the parent's corner) lies in region i >> 3.
+template <typename T>
+struct CoarseNbhd {
+  const T* cin;
+  const int64_t* coff;  // coarse out offsets (or null: dense)
+  const int32_t* cnbr;  // 27 entries of this fine block
+  int ncoarse;
+  __device__ inline bool get(int ix, int iy, int iz, T u[kNV]) const {
+    const int qx = ix >> 3, qy = iy >> 3, qz = iz >> 3;
+    if (qx < -1 || qx > 1 || qy < -1 || qy > 1 || qz < -1 || qz > 1) return false;
+    const int cb = cnbr[(qx + 1) + 3 * (qy + 1) + 9 * (qz + 1)];
+    if (cb < 0 || cb >= ncoarse) return false;
+    const T* c = cin + (coff ? coff[cb] : (int64_t)cb * kNV * 512) + (ix & 7) + 8 * (iy & 7) +
+                 64 * (iz & 7);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = c[k * 512];
+    return true;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const int32_t* nbr,
+                                                            int chunks, const T* cin,
+                                                            const int64_t* coff, int ncoarse,
+                                                            const int32_t* cnbr,
+                                                            const int32_t* corigin) {
+  const int b = blockIdx.x / chunks;
+  const int chunk = blockIdx.x % chunks;
+  const int n = block_edge(kp, b);
+  const int m = n + 2 * kG;
+  const int m3 = m * m * m;
+  const int n3 = n * n * n;
+  const int cell = chunk * kFillNT + threadIdx.x;
+  if (cell >= m3) return;
+  const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+  const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
+  const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
+  const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
+  T* d = reinterpret_cast<T*>(const_cast<void*>(kp.uin)) +
+         (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
+  const int src = nbr[27 * b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
+  if (src >= 0) {
+    // sibling copy
+    if (src >= kp.nblocks || block_edge(kp, src) != n) {
+      atomicAdd(&kp.counters[1], 1ull);
+      return;
+    }
+    const int sx = x - kG - rx * n, sy = y - kG - ry * n, sz = z - kG - rz * n;
+    const int so = sx + n * (sy + n * sz);
+    const T* s = reinterpret_cast<const T*>(kp.uout) +
+                 (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n3);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = s[(int64_t)k * n3 + so];
+    return;
+  }
+  // interpolation: fine index relative to the parent's corner, in fine cells
+  const int fx = 2 * corigin[3 * b + 0] + x - kG;
+  const int fy = 2 * corigin[3 * b + 1] + y - kG;
+  const int fz = 2 * corigin[3 * b + 2] + z - kG;
+  const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;  // floor
+  const T q = T(0.25);
+  const T dx = (fx & 1) ? q : -q, dy = (fy & 1) ? q : -q, dz = (fz & 1) ? q : -q;
+  const CoarseNbhd<T> cn{cin, coff, cnbr + 27 * (int64_t)b, ncoarse};
+  T u[kNV], p[kNV], mm[kNV], out[kNV];
+  bool ok = cn.get(cx, cy, cz, u);
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) out[k] = u[k];
+  // x, then y, then z (the order of the sum)
+  ok = ok && cn.get(cx + 1, cy, cz, p) && cn.get(cx - 1, cy, cz, mm);
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) out[k] = out[k] + dx * minmod(p[k] - u[k], u[k] - mm[k]);
+  ok = ok && cn.get(cx, cy + 1, cz, p) && cn.get(cx, cy - 1, cz, mm);
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) out[k] = out[k] + dy * minmod(p[k] - u[k], u[k] - mm[k]);
+  ok = ok && cn.get(cx, cy, cz + 1, p) && cn.get(cx, cy, cz - 1, mm);
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) out[k] = out[k] + dz * minmod(p[k] - u[k], u[k] - mm[k]);
+  if (!ok) {
+    atomicAdd(&kp.counters[1], 1ull);
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = out[k];
+}
+
+// ---------------------------------------------------------------------------
 // launchers and the variant table
 // ---------------------------------------------------------------------------
 
@@ -1025,6 +1125,21 @@ hipError_t launch_fill_ghosts(int dtype, const KParams& kp, const int32_t* nbr, 
   const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
   if (dtype == 1) hipLaunchKernelGGL((k_fill_ghosts<float>), grid, block, 0, s, kp, nbr, chunks);
   else hipLaunchKernelGGL((k_fill_ghosts<double>), grid, block, 0, s, kp, nbr, chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
+                                  const void* cin, const int64_t* coff, int ncoarse,
+                                  const int32_t* cnbr, const int32_t* corigin, hipStream_t s) {
+  const int m = max_edge + 2 * kG;
+  const int chunks = (m * m * m + kFillNT - 1) / kFillNT;
+  const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
+  if (dtype == 1)
+    hipLaunchKernelGGL((k_fill_ghosts_amr<float>), grid, block, 0, s, kp, nbr, chunks,
+                       static_cast<const float*>(cin), coff, ncoarse, cnbr, corigin);
+  else
+    hipLaunchKernelGGL((k_fill_ghosts_amr<double>), grid, block, 0, s, kp, nbr, chunks,
+                       static_cast<const double*>(cin), coff, ncoarse, cnbr, corigin);
   return hipGetLastError();
 }
 

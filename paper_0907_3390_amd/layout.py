@@ -172,3 +172,47 @@ def blocks_to_boxes(blocks, box_edges, block_edge_for) -> list:
         out.append(blocks_to_grid(np.stack(blocks[i:i + k ** 3]), (NVAR, L, L, L)))
         i += k ** 3
     return out
+
+
+def two_level(Nc: int, origin, shape, n: int):
+    """A coarse-fine configuration: the periodic coarse level of Nc^3 cells as
+    8^3 patches (x fastest), and a box of fine cells (the level one finer, 2 Nc
+    cells per axis) of shape (Lz, Ly, Lx) at fine-cell origin (oz, oy, ox), cut
+    into n^3 blocks (x fastest).  The origin and shape must be multiples of n,
+    so that blocks are aligned like octree patches (n = 8) or patch groups
+    (n = 16), and the box must not wrap around the domain.
+
+    Returns (coarse BlockSet, fine BlockSet whose sibling table is -1 outside
+    the box, cnbr [B, 27] coarse patches around each fine block's parent,
+    corigin [B, 3] the fine block's corner in coarse cells relative to its
+    parent's corner, x first)."""
+    Lz, Ly, Lx = shape
+    oz, oy, ox = origin
+    if any(v % n for v in (Lz, Ly, Lx, oz, oy, ox)) or Nc % 8:
+        raise ValueError("box origin and shape must be multiples of the block edge")
+    if any(o < 0 or o + L > 2 * Nc for o, L in ((oz, Lz), (oy, Ly), (ox, Lx))):
+        raise ValueError("the box must lie inside the domain")
+    coarse = periodic_grid_blockset(Nc, 8, dh=1.0 / Nc)
+    npc = Nc // 8
+    nbx, nby, nbz = Lx // n, Ly // n, Lz // n
+    nb = nbx * nby * nbz
+    nbr = np.full((nb, 27), -1, dtype=np.int32)
+    cnbr = np.empty((nb, 27), dtype=np.int32)
+    corigin = np.empty((nb, 3), dtype=np.int32)
+    for b in range(nb):
+        bx, by, bz = b % nbx, (b // nbx) % nby, b // (nbx * nby)
+        corner = [(ox + bx * n) // 2, (oy + by * n) // 2, (oz + bz * n) // 2]  # coarse cells
+        parent = [c // 8 for c in corner]
+        corigin[b] = [c - 8 * p for c, p in zip(corner, parent)]
+        for rz in (-1, 0, 1):
+            for ry in (-1, 0, 1):
+                for rx in (-1, 0, 1):
+                    r = (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)
+                    sx, sy, sz = bx + rx, by + ry, bz + rz
+                    if 0 <= sx < nbx and 0 <= sy < nby and 0 <= sz < nbz:
+                        nbr[b, r] = sx + nbx * (sy + nby * sz)
+                    px, py, pz = ((parent[0] + rx) % npc, (parent[1] + ry) % npc,
+                                  (parent[2] + rz) % npc)
+                    cnbr[b, r] = px + npc * (py + npc * pz)
+    fine = BlockSet(np.full(nb, n), np.full(nb, 0.5 / Nc), nbr)
+    return coarse, fine, cnbr, corigin

@@ -40,6 +40,7 @@ EXPORTS = [
     "tvd_conservation_sums", "tvd_read_flags", "tvd_fill_ghosts",
     "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
+    "tvd_fill_ghosts_amr",
 ]
 
 
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
         "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
         "tvd_read_flags": (ctypes.c_int, [vp, i64p, i64p, vp]),
         "tvd_fill_ghosts": (ctypes.c_int, [vp, bp, vp, vp, vp, vp]),
+        "tvd_fill_ghosts_amr": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp, vp]),
         "tvd_variant_count": (ctypes.c_int, []),
         "tvd_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 4),
         "tvd_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
@@ -236,6 +238,12 @@ class Context:
     def tvd_fill_ghosts(self, batch: Batch, nbr, interior, ghosted, stream=None):
         return self._check(self.lib.tvd_fill_ghosts(
             self.h, batch.ref, _ptr(nbr), _ptr(interior), _ptr(ghosted), _stream(stream)))
+
+    def tvd_fill_ghosts_amr(self, fine: Batch, nbr, fine_interior, fine_ghosted, coarse: Batch,
+                            coarse_interior, cnbr, corigin, stream=None):
+        return self._check(self.lib.tvd_fill_ghosts_amr(
+            self.h, fine.ref, _ptr(nbr), _ptr(fine_interior), _ptr(fine_ghosted), coarse.ref,
+            _ptr(coarse_interior), _ptr(cnbr), _ptr(corigin), _stream(stream)))
 
 
 class Graph:

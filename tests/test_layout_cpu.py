@@ -56,3 +56,16 @@ def test_grid_blocks_round_trip_with_perm():
     k = 5
     bx, by, bz = _coords(bs.perm[k], 3, 4)
     assert np.array_equal(blocks[k], g[:, 8 * bz:8 * bz + 8, 8 * by:8 * by + 8, 8 * bx:8 * bx + 8])
+
+
+def test_two_level_tables():
+    coarse, fine, cnbr, corigin = layout.two_level(16, (8, 0, 16), (8, 16, 8), 8)
+    assert coarse.n_blocks == 8 and fine.n_blocks == 2
+    # block 1 sits above block 0 in y; outside the box there are no siblings
+    assert fine.nbr[0, 13] == 0 and fine.nbr[0, 1 + 3 * 2 + 9] == 1 and fine.nbr[0, 1 + 9] == -1
+    assert (fine.nbr[0] >= 0).sum() == 2
+    # fine block 0 corner at fine (x, y, z) = (16, 0, 8) -> coarse (8, 0, 4): parent patch (1, 0, 0)
+    assert corigin[0].tolist() == [0, 0, 4] and corigin[1].tolist() == [0, 4, 4]
+    assert cnbr[0, 13] == 1 and cnbr[0, 12] == 0 and cnbr[0, 14] == 0   # periodic, 2 patches per axis
+    with pytest.raises(ValueError):
+        layout.two_level(16, (4, 0, 0), (8, 8, 8), 8)
