@@ -24,6 +24,9 @@ Reported (one JSON line on stdout):
 * cpu_baseline: the FP64 oracle on the host cores over a bounded sample;
 * uneven_batch: cell-updates/s of 4000 periodic boxes of mixed sizes in one
   persistent launch per step, 50-step HIP graphs, block edge tuned;
+* amr_ghost_fill: the coarse-fine ghost fill (sibling copy, else Min-Mod
+  limited interpolation from the coarser level) of 8^3 patches and 16^3
+  groups covering a refined 256^3-cell box;
 * multilevel_batch: one step of a 4-level patch hierarchy (19 592 patches,
   per-block dt and dh) as one persistent FP32 launch on patches and on 2^3
   patch groups, and as plain FP64 launches level by level.
@@ -289,6 +292,59 @@ def run_multilevel(ctx, reps=10):
     return res
 
 
+def run_amr_fill(ctx, reps=20):
+    """Coarse-fine ghost fill (sibling copy, else Min-Mod limited linear
+    interpolation from the coarser level): a periodic 256^3 coarse level
+    (32768 patches of 8^3) under a fine box of 256^3 fine cells (a 128^3
+    coarse region refined), cut into 8^3 patches and 16^3 patch groups.
+    Reported per fill: ghosted cells written per second and the algorithmic
+    bytes (ghosted blocks written, fine interiors and the coarse cells read
+    once) over the fill time, against 8 TB/s."""
+    import torch
+    from paper_0907_3390_amd import layout, tvd, workloads as wl
+    Nc = 256
+    coarse_grid = wl.lognormal(Nc, seed=SEED, sigma_ln=1.0).astype(np.float32)
+    origin, shape = (128, 128, 128), (256, 256, 256)
+    fine = wl.smooth_random(256, seed=SEED + 1, amplitude=0.3).astype(np.float32)
+    res = {"workload": "coarse 256^3 lognormal (32768 patches) under a 256^3-cell fine box "
+                       "(fine origin 128 along each axis), FP32"}
+    c_in = torch.from_numpy(layout.grid_to_blocks(coarse_grid, 8)).cuda().reshape(-1)
+    for n in (8, 16):
+        coarse_bs, fine_bs, cnbr, corigin = layout.two_level(Nc, origin, shape, n)
+        m = n + 6
+        nb = fine_bs.n_blocks
+        f_in = torch.from_numpy(layout.grid_to_blocks(fine, n)).cuda().reshape(-1)
+        f_gh = torch.empty(nb * 5 * m ** 3, dtype=torch.float32, device="cuda")
+        nbr = torch.from_numpy(fine_bs.nbr).cuda()
+        cn = torch.from_numpy(cnbr).cuda()
+        co = torch.from_numpy(corigin).cuda()
+        fb = tvd.Batch(tvd.TVD_F32, nb, n, dt=1e-3, dh=0.5 / Nc)
+        cb = tvd.Batch(tvd.TVD_F32, coarse_bs.n_blocks, 8, dt=1e-3, dh=1.0 / Nc)
+        ctx.tvd_fill_ghosts_amr(fb, nbr, f_in, f_gh, cb, c_in, cn, co)
+        a = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            ctx.tvd_fill_ghosts_amr(fb, nbr, f_in, f_gh, cb, c_in, cn, co)
+        e.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e) / reps
+        # cells interpolated: ghost cells of blocks on the box surface
+        ghost_cells = nb * (m ** 3 - n ** 3)
+        bytes_alg = nb * m ** 3 * 20 + nb * n ** 3 * 20 + (128 + 4) ** 3 * 20
+        res[f"edge{n}"] = {"blocks": nb, "ms": ms, "ghosted_cells_per_s": nb * m ** 3 / (ms * 1e-3),
+                           "ghost_cells": ghost_cells,
+                           "algorithmic_GBs": bytes_alg / (ms * 1e-3) / 1e9,
+                           "hbm_frac": bytes_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"bench: coarse-fine ghost fill, edge {n}: {ms:.3f} ms, "
+            f"{res[f'edge{n}']['algorithmic_GBs']:.0f} GB/s algorithmic")
+        del f_in, f_gh
+        torch.cuda.empty_cache()
+    st, fl, bad = ctx.tvd_read_flags()
+    res["health"] = {"nonphysical": bad}
+    return res
+
+
 def cpu_baseline(grid32, budget_s=15.0):
     """The FP64 oracle (as it stands) on the host cores over a bounded sample
     of the same workload: whole steps of the 256^3 grid as 32768 patches of
@@ -357,6 +413,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-variant tuner")
+    ap.add_argument("--no-amr-fill", action="store_true",
+                    help="skip the coarse-fine ghost-fill throughput")
     ap.add_argument("--no-multilevel", action="store_true",
                     help="skip the multi-level (19 592 patches) throughput")
     ap.add_argument("--no-uneven", action="store_true",
@@ -487,6 +545,10 @@ def main():
             torch.cuda.empty_cache()
             log(f"bench: {name} {vv / 1e9:.3f} G cell-updates/s")
         out.update(others)
+    if not args.no_amr_fill:
+        log("bench: coarse-fine ghost fill")
+        torch.cuda.empty_cache()
+        out["amr_ghost_fill"] = run_amr_fill(ctx)
     if not args.no_multilevel:
         log("bench: multi-level batch")
         torch.cuda.empty_cache()
