@@ -66,10 +66,14 @@ def _bind(path: str):
     lib.oracle_pencil.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   dp, ctypes.c_void_p]
+    lib.oracle_pencil_flux.restype = None
+    lib.oracle_pencil_flux.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       dp, dp, ctypes.c_void_p]
     lib.oracle_advance_batch.restype = ctypes.c_int
     lib.oracle_advance_batch.argtypes = [dp, dp, ctypes.c_int, ip, llp, llp, dp, dp,
                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                         llp, llp]
+                                         dp, llp, llp, llp]
     lib.oracle_max_signal_speed.restype = ctypes.c_double
     lib.oracle_max_signal_speed.argtypes = [dp, ctypes.c_longlong, ctypes.c_longlong,
                                             ctypes.c_double, ctypes.c_double]
@@ -140,6 +144,18 @@ def pencil(q, d: int, dt: float, dh: float, gamma: float, p_floor: float = 0.0):
     return out
 
 
+def pencil_flux(q, d: int, dt: float, dh: float, gamma: float, p_floor: float = 0.0):
+    """As ``pencil``, also returning the (n+1, 5) interface fluxes of the full
+    step: row i is the flux through interface i-1/2 of interior cell i."""
+    lib = _load()
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    n = q.shape[0] - 2 * GHOST
+    out = np.zeros((n, NVAR))
+    hf = np.zeros((n + 1, NVAR))
+    lib.oracle_pencil_flux(_dptr(q), n, d, dt, dh, gamma, p_floor, _dptr(out), _dptr(hf), None)
+    return out, hf
+
+
 # ---------------------------------------------------------------------------
 # block level
 # ---------------------------------------------------------------------------
@@ -151,18 +167,34 @@ class Counts:
     threads: int = 1
 
 
+PATCH = 8
+
+
+def flux_record_shape(n: int):
+    """Shape of one block's patch-boundary flux record (see ``advance_ragged``)."""
+    return (3, n // PATCH + 1, NVAR, n, n)
+
+
 def advance_ragged(blocks_in, order: int, dt, dh, gamma: float, p_floor: float = 0.0,
-                   counts: Counts | None = None):
+                   counts: Counts | None = None, fluxes: bool = False):
     """One step on a list of ghosted blocks of shape (5, n+6, n+6, n+6).
 
     ``dt`` and ``dh`` are scalars or per-block sequences.  ``order`` 0 is the
     forward xyz triple, 1 the backward zyx triple.  Returns the list of
     (5, n, n, n) interiors.
+
+    With ``fluxes`` (n a multiple of 8) it returns (interiors, records): the
+    record of a block, shape (3, n/8 + 1, 5, n, n), holds for each axis d and
+    face plane f = 0, 8, .., n the flux through interface f-1/2 of every
+    d-pencil, taken in the sweep along d, indexed [d, f/8, k, a, b] with
+    (a, b) the other two axes, higher-numbered first (x: (z, y); y: (z, x);
+    z: (y, x)).  These are the patch-boundary fluxes that the closing step
+    (Sec. 3.1) hands to the coarse-fine flux correction (Sec. 2.1).
     """
     lib = _load()
     nb = len(blocks_in)
     if nb == 0:
-        return []
+        return ([], []) if fluxes else []
     edges = np.array([b.shape[1] - 2 * GHOST for b in blocks_in], dtype=np.int32)
     for b, n in zip(blocks_in, edges):
         if b.shape != (NVAR, n + 6, n + 6, n + 6):
@@ -178,13 +210,22 @@ def advance_ragged(blocks_in, order: int, dt, dh, gamma: float, p_floor: float =
     dh_a = np.broadcast_to(np.asarray(dh, dtype=np.float64), (nb,)).copy()
     fl = ctypes.c_longlong(0)
     npy = ctypes.c_longlong(0)
+    flux_p = flux_off_p = None
+    if fluxes:
+        if np.any(edges % PATCH):
+            raise ValueError("flux records need block edges that are multiples of 8")
+        f_sizes = np.array([int(np.prod(flux_record_shape(int(n)))) for n in edges], dtype=np.int64)
+        flux_off = np.concatenate([[0], np.cumsum(f_sizes)[:-1]]).astype(np.int64)
+        flat_flux = np.full(int(f_sizes.sum()), np.nan)
+        flux_p = _dptr(flat_flux)
+        flux_off_p = flux_off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
     th = lib.oracle_advance_batch(
         _dptr(flat_in), _dptr(flat_out), nb,
         edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
         in_off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
         out_off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
         _dptr(dt_a), _dptr(dh_a), int(order), float(gamma), float(p_floor),
-        ctypes.byref(fl), ctypes.byref(npy))
+        flux_p, flux_off_p, ctypes.byref(fl), ctypes.byref(npy))
     if counts is not None:
         counts.floored += fl.value
         counts.nonphysical += npy.value
@@ -193,7 +234,11 @@ def advance_ragged(blocks_in, order: int, dt, dh, gamma: float, p_floor: float =
     for b in range(nb):
         n = int(edges[b])
         outs.append(flat_out[out_off[b]:out_off[b] + out_sizes[b]].reshape(NVAR, n, n, n))
-    return outs
+    if not fluxes:
+        return outs
+    recs = [flat_flux[flux_off[b]:flux_off[b] + f_sizes[b]].reshape(flux_record_shape(int(edges[b])))
+            for b in range(nb)]
+    return outs, recs
 
 
 def advance_blocks(blocks_in, order: int, dt, dh, gamma: float, p_floor: float = 0.0,

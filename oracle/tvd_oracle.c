@@ -53,6 +53,7 @@
 
 #define NVAR 5
 #define GHOST 3
+#define PATCH 8   /* patch edge: boundary fluxes are kept at multiples of it */
 
 /* ---------------------------------------------------------------------- */
 /* Cell level: Eqs. (ThermalEnergy), (EOS), (LRFlux)                        */
@@ -129,10 +130,13 @@ double oracle_vanleer(double dF1, double dF2)
  * Advance one pencil of n+6 cells (cells -3 .. n+2, stored at array index
  * i+3) along axis d by dt with zone size dh.  q holds (n+6) x 5 values in the
  * global component order; out receives the n updated interior cells.
+ * hface, if not NULL, receives the (n+1) x 5 second-order interface fluxes
+ * that the full step uses: row i is the flux through interface i-1/2 of
+ * interior cell i (i = 0 .. n), so that out_i = q_i - dt/dh (row i+1 - row i).
  */
-void oracle_pencil(const double *q, int n, int d, double dt, double dh,
-                   double gamma, double p_floor, double *out,
-                   oracle_counts *cnt)
+void oracle_pencil_flux(const double *q, int n, int d, double dt, double dh,
+                        double gamma, double p_floor, double *out, double *hface,
+                        oracle_counts *cnt)
 {
     const int L = n + 2 * GHOST;
 
@@ -190,7 +194,21 @@ void oracle_pencil(const double *q, int n, int d, double dt, double dh,
                                 (H[j * NVAR + k] - H[(j - 1) * NVAR + k]) / dh * dt;
     }
 
+    /* the fluxes through interfaces -1/2 .. n-1/2 (H[j] is interface j+1/2
+     * in array index j, so interface i-1/2 is H[i + GHOST - 1]) */
+    if (hface)
+        for (int i = 0; i <= n; ++i)
+            for (int k = 0; k < NVAR; ++k)
+                hface[i * NVAR + k] = H[(i + GHOST - 1) * NVAR + k];
+
     free(FR); free(FL); free(G); free(h); free(FRh); free(FLh); free(H);
+}
+
+void oracle_pencil(const double *q, int n, int d, double dt, double dh,
+                   double gamma, double p_floor, double *out,
+                   oracle_counts *cnt)
+{
+    oracle_pencil_flux(q, n, d, dt, dh, gamma, p_floor, out, NULL, cnt);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -206,10 +224,20 @@ static inline long long cell_index(int m, int x, int y, int z)
  * One step (one directional triple) on one block.  order = 0 sweeps x, y, z
  * (forward); order = 1 sweeps z, y, x (backward).  in: 5 cubes of (n+6)^3;
  * out: 5 cubes of n^3.
+ *
+ * flux, if not NULL, receives the block's patch-boundary fluxes (the fluxes
+ * across the boundaries of every 8^3 patch of the block, which the closing
+ * step of Sec. 3.1 needs for the coarse-fine correction of Sec. 2.1; n must
+ * then be a multiple of PATCH).  For each axis d and each face plane f = 0,
+ * 8, .., n along d (plane index q = f / 8), the flux through interface f-1/2
+ * of the d-pencils with interior transverse coordinates, taken in the sweep
+ * along d: flux[((d * NQ + q) * NVAR + k) * n * n + a * n + b], NQ = n/8 + 1,
+ * where (a, b) are the two other axes, the higher-numbered one first
+ * (x: (z, y); y: (z, x); z: (y, x)) and k the global component.
  */
 void oracle_advance_block(const double *in, double *out, int n, int order,
                           double dt, double dh, double gamma, double p_floor,
-                          oracle_counts *cnt)
+                          double *flux, oracle_counts *cnt)
 {
     const int m = n + 2 * GHOST;
     const long long m3 = (long long)m * m * m;
@@ -221,6 +249,8 @@ void oracle_advance_block(const double *in, double *out, int n, int order,
 
     double *q = (double *)malloc(sizeof(double) * m * NVAR);
     double *res = (double *)malloc(sizeof(double) * n * NVAR);
+    double *hf = (double *)malloc(sizeof(double) * (n + 1) * NVAR);
+    const int nq = n / PATCH + 1;
 
     for (int s = 0; s < 3; ++s) {
         const int d = seq[s];
@@ -244,11 +274,22 @@ void oracle_advance_block(const double *in, double *out, int n, int order,
                     const long long idx = cell_index(m, c[0], c[1], c[2]);
                     for (int k = 0; k < NVAR; ++k) q[j * NVAR + k] = u[k * m3 + idx];
                 }
-                oracle_pencil(q, n, d, dt, dh, gamma, p_floor, res, cnt);
+                const int interior = p1 >= 0 && p1 < n && p2 >= 0 && p2 < n;
+                double *hp = flux && interior ? hf : NULL;
+                oracle_pencil_flux(q, n, d, dt, dh, gamma, p_floor, res, hp, cnt);
                 for (int i = 0; i < n; ++i) {
                     c[d] = i + GHOST;
                     const long long idx = cell_index(m, c[0], c[1], c[2]);
                     for (int k = 0; k < NVAR; ++k) u[k * m3 + idx] = res[i * NVAR + k];
+                }
+                if (hp) {
+                    /* face coordinates: the higher-numbered transverse axis first */
+                    const int a = a1 > a2 ? p1 : p2;
+                    const int b = a1 > a2 ? p2 : p1;
+                    for (int qq = 0; qq < nq; ++qq)
+                        for (int k = 0; k < NVAR; ++k)
+                            flux[((long long)(d * nq + qq) * NVAR + k) * n * n + a * n + b] =
+                                hf[qq * PATCH * NVAR + k];
                 }
             }
         }
@@ -262,21 +303,22 @@ void oracle_advance_block(const double *in, double *out, int n, int order,
                     out[k * n3 + x + (long long)n * (y + (long long)n * z)] =
                         u[k * m3 + cell_index(m, x + GHOST, y + GHOST, z + GHOST)];
 
-    free(q); free(res); free(u);
+    free(q); free(res); free(hf); free(u);
 }
 
 /*
  * One step on a batch of blocks, possibly of different edges, time steps and
  * zone sizes.  Block b reads 5 (edge[b]+6)^3 cubes at in + in_off[b] and
- * writes 5 edge[b]^3 cubes at out + out_off[b].  Blocks are independent and
+ * writes 5 edge[b]^3 cubes at out + out_off[b] (and, with flux != NULL, its
+ * patch-boundary fluxes at flux + flux_off[b]).  Blocks are independent and
  * are spread over OpenMP threads.  Returns the number of threads used.
  */
 int oracle_advance_batch(const double *in, double *out, int nblocks,
                          const int *edge, const long long *in_off,
                          const long long *out_off, const double *dt,
                          const double *dh, int order, double gamma,
-                         double p_floor, long long *n_floored,
-                         long long *n_nonphysical)
+                         double p_floor, double *flux, const long long *flux_off,
+                         long long *n_floored, long long *n_nonphysical)
 {
     long long fl = 0, np = 0;
     int nthreads = 1;
@@ -290,7 +332,8 @@ int oracle_advance_batch(const double *in, double *out, int nblocks,
 #pragma omp for schedule(dynamic, 1)
         for (int b = 0; b < nblocks; ++b)
             oracle_advance_block(in + in_off[b], out + out_off[b], edge[b], order,
-                                 dt[b], dh[b], gamma, p_floor, &cnt);
+                                 dt[b], dh[b], gamma, p_floor,
+                                 flux ? flux + flux_off[b] : NULL, &cnt);
         fl += cnt.floored;
         np += cnt.nonphysical;
     }

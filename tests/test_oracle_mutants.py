@@ -2,7 +2,7 @@
 
 Each case below plants one mistake in a copy of ``oracle/tvd_oracle.c`` (a
 dropped term, a wrong sign, a shifted index, a transposed operand, the wrong
-state in the full step, a wrong region rule), builds it with gcc into a
+state in the full step, a wrong region rule, a misplaced boundary flux), builds it with gcc into a
 temporary directory and runs the pins of ``test_oracle_pins.py`` against it
 in a child process.  At least one pin must fail for every mistake.  The
 planted copies live only in the temporary directory; the real oracle is
@@ -59,6 +59,15 @@ MUTANTS = {
         ("bwd[3] = {2, 1, 0};", "bwd[3] = {0, 1, 2};"),
     "signal speed uses the sum of the velocities":
         ("const double s = cs + vmax;", "const double s = cs + fabs(vx) + fabs(vy) + fabs(vz);"),
+    "boundary flux taken one interface off":
+        ("hface[i * NVAR + k] = H[(i + GHOST - 1) * NVAR + k];",
+         "hface[i * NVAR + k] = H[(i + GHOST) * NVAR + k];"),
+    "boundary flux face coordinates transposed":
+        ("const int a = a1 > a2 ? p1 : p2;\n                    const int b = a1 > a2 ? p2 : p1;",
+         "const int a = a1 > a2 ? p2 : p1;\n                    const int b = a1 > a2 ? p1 : p2;"),
+    "boundary flux taken from the first-order flux":
+        ("hface[i * NVAR + k] = H[(i + GHOST - 1) * NVAR + k];",
+         "hface[i * NVAR + k] = G[(i + GHOST - 1) * NVAR + k];"),
 }
 
 PINS = [
@@ -71,6 +80,10 @@ PINS = [
     "test_transpose_reverses_sweep_order",
     "test_decomposition_invariance_bitwise",
     "test_conservation_periodic",
+    "test_flux_uniform_closed_form",
+    "test_flux_one_d_closed_form",
+    "test_flux_patch_conservation",
+    "test_flux_shared_faces_bitwise",
     "test_pressureless_advection",
     "test_acoustic_wave_second_order",
     "test_sod_against_exact_riemann",

@@ -223,6 +223,162 @@ def test_conservation_periodic():
 
 
 # ---------------------------------------------------------------------------
+# patch-boundary flux records (the fluxes the closing step of Sec. 3.1 hands
+# to the coarse-fine flux correction of Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def _euler_flux(u, d, gamma):
+    """Euler flux along axis d of conserved states u (5, ...), Eqs. (1)-(3)."""
+    rho = u[0]
+    v = [u[1] / rho, u[2] / rho, u[3] / rho]
+    P = (gamma - 1) * (u[4] - 0.5 * (u[1] * v[0] + u[2] * v[1] + u[3] * v[2]))
+    F = np.stack([u[0] * v[d], u[1] * v[d], u[2] * v[d], u[3] * v[d], (u[4] + P) * v[d]])
+    F[1 + d] += P
+    return F
+
+
+def _face_axes(d):
+    """The two face axes of a record along d, higher-numbered first."""
+    return {0: (2, 1), 1: (2, 0), 2: (1, 0)}[d]
+
+
+@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("order", [0, 1])
+def test_flux_uniform_closed_form(n, order):
+    """On a uniform state every limiter term vanishes and the interface flux
+    is F^R - F^L = the Euler flux of the state (Eq. LRFlux), on every face."""
+    gamma = G53
+    g = wl.uniform(n, rho=1.3, v=(0.4, -0.25, 0.15), P=0.8, gamma=gamma)
+    blocks = oracle.periodic_ghosted_blocks(g, n)
+    _, recs = oracle.advance_ragged(list(blocks), order, 0.01, 1.0 / n, gamma, fluxes=True)
+    rec = recs[0]
+    assert rec.shape == (3, n // 8 + 1, 5, n, n)
+    for d in range(3):
+        want = _euler_flux(g[:, 0, 0, 0], d, gamma)
+        np.testing.assert_allclose(rec[d], np.broadcast_to(want[None, :, None, None], rec[d].shape),
+                                   rtol=1e-13, atol=1e-15)
+
+
+def _one_d_state(N, e, gamma):
+    """A state varying only along axis e, moving only along e."""
+    c = (np.arange(N) + 0.5) / N
+    prof = [1.0 + 0.4 * np.sin(2 * np.pi * c), 0.5 + 0.2 * np.cos(2 * np.pi * c),
+            0.3 * np.sin(4 * np.pi * c)]
+    shape = [1, 1, 1]
+    shape[2 - e] = N
+    rho, P, ve = (np.broadcast_to(p.reshape(shape), (N, N, N)) for p in prof)
+    v = [0.0, 0.0, 0.0]
+    v[e] = ve
+    return wl.conserved(rho, *v, P, gamma)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_flux_one_d_closed_form(order):
+    """A state that varies along e only, with velocity along e, is inert in the
+    sweeps along d != e: there the interface flux is the Euler flux of the
+    state at that sweep, which for v_d = 0 is P in the d-momentum and zero
+    elsewhere.  The state is the initial one if d is swept before e and the
+    final one if after.  Checks the face coordinates of the record (P varies
+    along e only)."""
+    gamma, N, n = G53, 16, 8
+    seq = [0, 1, 2] if order == 0 else [2, 1, 0]
+    for e in range(3):
+        g = _one_d_state(N, e, gamma)
+        blocks = oracle.periodic_ghosted_blocks(g, n)
+        outs, recs = oracle.advance_ragged(list(blocks), order, 0.3 / N, 1.0 / N, gamma,
+                                           fluxes=True)
+        out = oracle.assemble_blocks(np.stack(outs), g.shape)
+        nb = N // n
+        for d in range(3):
+            if d == e:
+                continue
+            state = g if seq.index(d) < seq.index(e) else out
+            for b, rec in enumerate(recs):
+                bx, by, bz = b % nb, (b // nb) % nb, b // (nb * nb)
+                cell = state[:, bz * n:bz * n + n, by * n:by * n + n, bx * n:bx * n + n]
+                # the state is uniform along d: any cell of the pencil gives its flux
+                arr = {0: 3, 1: 2, 2: 1}
+                sl = [slice(None)] * 4
+                sl[arr[d]] = 0
+                face = cell[tuple(sl)]          # (5, a, b): the remaining axes, z..x order
+                want = _euler_flux(face, d, gamma)
+                for q in range(n // 8 + 1):
+                    np.testing.assert_allclose(rec[d, q], want, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("order", [0, 1])
+def test_flux_patch_conservation(n, order):
+    """Every 8^3 patch of every block changes by exactly what its recorded
+    boundary fluxes carry: sum(u_new - u) = -dt/dh sum_d sum_face (H_hi - H_lo)
+    (the telescoping sum of Eq. FullstepValue in each sweep), to round-off.
+    With n = 16 this includes the planes between the patches of a group."""
+    N = 16
+    g = wl.lognormal(N, seed=21, sigma_ln=0.6)
+    dt, dh = 0.2 / N, 1.0 / N
+    blocks = oracle.periodic_ghosted_blocks(g, n)
+    outs, recs = oracle.advance_ragged(list(blocks), order, dt, dh, G53, fluxes=True)
+    for blk, out, rec in zip(blocks, outs, recs):
+        inner = blk[:, 3:3 + n, 3:3 + n, 3:3 + n]
+        for pz in range(n // 8):
+            for py in range(n // 8):
+                for px in range(n // 8):
+                    sl = (slice(None), slice(8 * pz, 8 * pz + 8), slice(8 * py, 8 * py + 8),
+                          slice(8 * px, 8 * px + 8))
+                    p = {0: px, 1: py, 2: pz}
+                    for k in range(5):
+                        change = math.fsum((out[sl][k] - inner[sl][k]).ravel())
+                        terms = []
+                        for d in range(3):
+                            hi, lo = _face_axes(d)
+                            fa = slice(8 * p[hi], 8 * p[hi] + 8)
+                            fb = slice(8 * p[lo], 8 * p[lo] + 8)
+                            terms += (rec[d, p[d] + 1, k, fa, fb]).ravel().tolist()
+                            terms += (-rec[d, p[d], k, fa, fb]).ravel().tolist()
+                        want = -dt / dh * math.fsum(terms)
+                        scale = math.fsum(np.abs(inner[sl][k]).ravel()) + 1e-300
+                        assert abs(change - want) <= 1e-13 * scale, (k, change, want)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_flux_shared_faces_bitwise(order):
+    """Two blocks that share a face compute its flux from the same cells with
+    the same operations, so the + plane of a block equals the - plane of its
+    neighbour bit for bit; the plane inside a 16^3 block equals the planes of
+    its 8^3 patches advanced as separate blocks."""
+    N = 32
+    g = wl.lognormal(N, seed=22, sigma_ln=0.6)
+    dt, dh = 0.2 / N, 1.0 / N
+    res = {}
+    for n in (8, 16):
+        blocks = oracle.periodic_ghosted_blocks(g, n)
+        _, recs = oracle.advance_ragged(list(blocks), order, dt, dh, G53, fluxes=True)
+        res[n] = recs
+        nb = N // n
+        for b, rec in enumerate(recs):
+            c = [b % nb, (b // nb) % nb, b // (nb * nb)]
+            for d in range(3):
+                cn = list(c)
+                cn[d] = (c[d] + 1) % nb
+                other = recs[cn[0] + nb * (cn[1] + nb * cn[2])]
+                assert np.array_equal(rec[d, -1], other[d, 0])
+    # 16^3 block 0's planes against its eight 8^3 patches (blocks of the 8-cut)
+    big = res[16][0]
+    for d in range(3):
+        hi, lo = _face_axes(d)
+        for q in range(3):
+            for ph in range(2):
+                for pl in range(2):
+                    # plane q (face 8q) is the - plane of the patch at min(q, 1)
+                    # along d, or its + plane for q = 2
+                    c = {d: min(q, 1), hi: ph, lo: pl}
+                    small = res[8][c[0] + 4 * (c[1] + 4 * c[2])]
+                    sq = q - c[d]
+                    assert np.array_equal(big[d, q, :, 8 * ph:8 * ph + 8, 8 * pl:8 * pl + 8],
+                                          small[d, sq])
+
+
+# ---------------------------------------------------------------------------
 # physics with known answers
 # ---------------------------------------------------------------------------
 
