@@ -287,6 +287,80 @@ int tvd_fill_ghosts_amr(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nb
                         const tvd_batch *coarse, const void *d_coarse_interior,
                         const int32_t *d_cnbr, const int32_t *d_corigin, void *stream);
 
+/* ---- closing step of a level pair (Sec. 2.1 step 3, Sec. 3.1) --------------- */
+
+/*
+ * Patch-boundary flux record of a block of edge e (a multiple of 8): the
+ * fluxes across the boundaries of each 8^3 patch in it, which the closing
+ * step of Sec. 3.1 routes to the coarse-fine flux correction of Sec. 2.1.
+ * 3 * (e/8 + 1) * 5 * e^2 values of the batch's dtype:
+ *   record[((d * (e/8 + 1) + q) * 5 + k) * e * e + a * e + b]
+ * is the flux of variable k (rho, m_x, m_y, m_z, e) through the face plane
+ * f = 8 q along axis d (0 = x), i.e. through interface f - 1/2, at face cell
+ * (a, b) = the two other axes, the higher-numbered first (x: (z, y);
+ * y: (z, x); z: (y, x)).  It is the flux H of Eq. (FullstepValue) in the
+ * sweep along d (u_i -= dt/dh (H at i+1 - H at i)), so a patch changes by
+ * exactly what its six faces carry.  Records are packed densely in block
+ * order (offset b * record size) unless an int64 offset array is given.
+ */
+
+/*
+ * tvd_patch_advance that also writes every block's flux record to d_flux
+ * (at d_flux_off[b], or densely when NULL; required with mixed edges).
+ * Ghosted input as for tvd_patch_advance; flags AUTO, BATCHED or PERSISTENT
+ * (TVD_KERNEL_PLAIN is TVD_ERR_UNSUPPORTED).  The batched kernel runs its
+ * default launch variant here whatever the tuner chose.  d_flux must not
+ * overlap the state buffers.
+ */
+int tvd_patch_advance_flux(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u_in,
+                           void *d_u_out, void *d_flux, const int64_t *d_flux_off,
+                           int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                           double *d_smax, double *d_sums, void *stream);
+
+/*
+ * Restriction (Sec. 2.1: a coarse patch overlaid by its children takes the
+ * spatial average of the fine-grid values).  d_rows[5*r .. 5*r+4] =
+ * (f, c, ox, oy, oz): the (e_f/2)^3 coarse cells of coarse block c (interior
+ * layout, d_coarse at the coarse batch's out offsets) starting at cell
+ * (ox, oy, oz) become the means of their eight children in fine block f
+ * (interior layout, d_fine at the fine batch's out offsets), summed in the
+ * order (dz, dy, dx) = 000, 001, .., 111 and multiplied by 1/8.  Rows must
+ * not write one cell twice, and no row may read a block another row writes.
+ * A row naming a block out of range, an edge other than 8 or 16, or cells
+ * outside its blocks is skipped and its cells counted as non-physical.
+ * d_coarse and d_fine may be the same buffer (one batch holding both
+ * levels).  Asynchronous on stream.
+ */
+int tvd_restrict(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse, const tvd_batch *fine,
+                 const void *d_fine, const int32_t *d_rows, int32_t n_rows, void *stream);
+
+/*
+ * Coarse-fine flux correction (Sec. 2.1: the coarse cells next to a
+ * coarse-fine interface are corrected with the difference between the
+ * coarse-grid and fine-grid fluxes, so that what leaves the coarse side
+ * enters the fine side).  Both levels were advanced with the same dt, and
+ * their flux records (tvd_patch_advance_flux) are read, never written.
+ * d_rows[8*r .. 8*r+7] = (c, d, s, qc, oa, ob, f, qf): on plane qc along
+ * axis d of coarse block c, the face cells (oa + a, ob + b), a, b in
+ * [0, e_f/2), are covered by the 2 x 2 face cells (2a + i, 2b + j) of plane
+ * qf of fine block f.  The coarse cell on side s of the plane (s = 1: the
+ * cell below it, whose + face the plane is; s = 0: the cell above it) gets
+ *   u + lam (H_c - H_f)   (s = 1)   or   u - lam (H_c - H_f)   (s = 0),
+ * lam = dt_c / dh_c of block c, H_f = (((f00 + f01) + f10) + f11) / 4.
+ * Rows are grouped by pass p = 2 d + s (x-, x+, y-, y+, z-, z+) with
+ * pass_count[p] rows each (a host array); the passes run in that order, one
+ * launch each, and rows of one pass must not share a cell.  d_coarse is
+ * read and written (interior layout, the coarse batch's out offsets); flux
+ * offsets as for tvd_patch_advance_flux.  A row naming a block out of range
+ * or cells outside its blocks is skipped and its cells counted as
+ * non-physical.  Asynchronous on stream.
+ */
+int tvd_flux_correct(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse,
+                     const void *d_coarse_flux, const int64_t *d_coarse_flux_off,
+                     const tvd_batch *fine, const void *d_fine_flux,
+                     const int64_t *d_fine_flux_off, const int32_t *d_rows,
+                     const int32_t pass_count[6], void *stream);
+
 /* ---- step sequences as HIP graphs --------------------------------------------- */
 
 typedef struct tvd_graph tvd_graph;

@@ -149,6 +149,8 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
   kp.ws_smax = ctx->ws_smax;
   kp.ws_sums = ctx->ws_sums;
   kp.counters = ctx->counters;
+  kp.flux = nullptr;
+  kp.flux_off = nullptr;
   return kp;
 }
 
@@ -277,7 +279,8 @@ namespace {
 // tvd_patch_advance_gather (nbr != NULL: interior input, ghosts gathered).
 int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
                  int32_t sweep_order, double gamma, double p_floor, int32_t flags,
-                 double* d_smax, double* d_sums, void* stream, const int32_t* d_nbr) {
+                 double* d_smax, double* d_sums, void* stream, const int32_t* d_nbr,
+                 void* d_flux = nullptr, const int64_t* d_flux_off = nullptr) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   int st = check_batch(ctx, batch);
   if (st) return st;
@@ -289,6 +292,14 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
     return fail(ctx, TVD_ERR_INVALID_ARG, "flags %d", flags);
   if (batch->n_blocks == 0) return TVD_OK;
   if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
+  if (d_flux) {
+    if (flags == TVD_KERNEL_PLAIN)
+      return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel records no fluxes");
+    if (batch->d_edge && !d_flux_off)
+      return fail(ctx, TVD_ERR_INVALID_ARG, "mixed edges need flux record offsets");
+    if (d_flux == d_u_in || d_flux == d_u_out)
+      return fail(ctx, TVD_ERR_ALIAS, "the flux records overlap a state buffer");
+  }
   if (flags == TVD_KERNEL_PLAIN) {
     if (d_nbr) return fail(ctx, TVD_ERR_UNSUPPORTED, "the plain kernel takes ghosted input only");
     if (batch->dtype != TVD_F64 || batch->d_edge || batch->edge != 8)
@@ -319,7 +330,13 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
   kp.nbr = d_nbr;
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
+  kp.flux = d_flux;
+  kp.flux_off = d_flux_off;
   const bool gather = d_nbr != nullptr;
+  // the flux-recording advance has one variant per (type, edge): the default
+  auto variant = [&](int edge) {
+    return d_flux ? default_variant(batch->dtype, edge) : chosen_variant(ctx, batch->dtype, edge);
+  };
   hipError_t e;
   if (flags == TVD_KERNEL_PLAIN) {
     e = tvd::launch_plain_f64(sweep_order, kp, s);
@@ -337,13 +354,11 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   } else if (batch->d_edge) {
     // one launch per edge; a workgroup whose block has the other edge exits
     for (int edge : {16, 8}) {
-      e = tvd::launch_batched(batch->dtype, sweep_order, chosen_variant(ctx, batch->dtype, edge),
-                              gather, kp, s);
+      e = tvd::launch_batched(batch->dtype, sweep_order, variant(edge), gather, kp, s);
       if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
     }
   } else {
-    e = tvd::launch_batched(batch->dtype, sweep_order,
-                            chosen_variant(ctx, batch->dtype, batch->edge), gather, kp, s);
+    e = tvd::launch_batched(batch->dtype, sweep_order, variant(batch->edge), gather, kp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
   }
   if (d_smax) {
@@ -376,6 +391,79 @@ int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
   if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
   return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
                       d_sums, stream, d_nbr);
+}
+
+int tvd_patch_advance_flux(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in,
+                           void* d_u_out, void* d_flux, const int64_t* d_flux_off,
+                           int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                           double* d_smax, double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!d_flux) return fail(ctx, TVD_ERR_INVALID_ARG, "d_flux is NULL");
+  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
+                      d_sums, stream, nullptr, d_flux, d_flux_off);
+}
+
+int tvd_restrict(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse, const tvd_batch* fine,
+                 const void* d_fine, const int32_t* d_rows, int32_t n_rows, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, coarse);
+  if (st) return st;
+  if ((st = check_batch(ctx, fine))) return st;
+  if (coarse->dtype != fine->dtype)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "coarse and fine batches differ in dtype");
+  if (n_rows < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_rows %d", n_rows);
+  if (n_rows == 0) return TVD_OK;
+  if (!d_coarse || !d_fine || !d_rows) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  DeviceGuard g(ctx->device);
+  const tvd::KParams ck = make_params(ctx, coarse, nullptr, d_coarse, 1.0, 0.0);
+  const tvd::KParams fk = make_params(ctx, fine, d_fine, nullptr, 1.0, 0.0);
+  hipError_t e = tvd::launch_restrict(coarse->dtype, ck, fk, d_rows, n_rows, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "restriction launch");
+  return TVD_OK;
+}
+
+int tvd_flux_correct(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse,
+                     const void* d_coarse_flux, const int64_t* d_coarse_flux_off,
+                     const tvd_batch* fine, const void* d_fine_flux,
+                     const int64_t* d_fine_flux_off, const int32_t* d_rows,
+                     const int32_t pass_count[6], void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, coarse);
+  if (st) return st;
+  if ((st = check_batch(ctx, fine))) return st;
+  if (coarse->dtype != fine->dtype)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "coarse and fine batches differ in dtype");
+  if (!pass_count) return fail(ctx, TVD_ERR_INVALID_ARG, "pass_count is NULL");
+  int64_t total = 0;
+  for (int p = 0; p < 6; ++p) {
+    if (pass_count[p] < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "pass_count[%d] < 0", p);
+    total += pass_count[p];
+  }
+  if (total > INT32_MAX) return fail(ctx, TVD_ERR_INVALID_ARG, "too many rows");
+  if (total == 0) return TVD_OK;
+  if (!d_coarse || !d_coarse_flux || !d_fine_flux || !d_rows)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if ((coarse->d_edge && !d_coarse_flux_off) || (fine->d_edge && !d_fine_flux_off))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "mixed edges need flux record offsets");
+  if (d_coarse == d_coarse_flux || d_coarse == d_fine_flux)
+    return fail(ctx, TVD_ERR_ALIAS, "the state overlaps a flux record buffer");
+  DeviceGuard g(ctx->device);
+  tvd::KParams ck = make_params(ctx, coarse, nullptr, d_coarse, 1.0, 0.0);
+  ck.flux = const_cast<void*>(d_coarse_flux);
+  ck.flux_off = d_coarse_flux_off;
+  tvd::KParams fk = make_params(ctx, fine, nullptr, nullptr, 1.0, 0.0);
+  fk.flux = const_cast<void*>(d_fine_flux);
+  fk.flux_off = d_fine_flux_off;
+  // one launch per pass, in the order x-, x+, y-, y+, z-, z+: a coarse cell
+  // on several interfaces takes its corrections in that order
+  int64_t first = 0;
+  for (int p = 0; p < 6; ++p) {
+    hipError_t e = tvd::launch_flux_correct(coarse->dtype, ck, fk, d_rows + 8 * first,
+                                            pass_count[p], (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "flux correction launch");
+    first += pass_count[p];
+  }
+  return TVD_OK;
 }
 
 int tvd_autotune(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr, const void* d_u_in,

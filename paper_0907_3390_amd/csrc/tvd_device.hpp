@@ -105,10 +105,23 @@ __device__ __forceinline__ float vanleer<float>(float a, float b) {
   return Num<float>::max(a * b, 0.0f) * r;
 }
 
+// Whether a sweep destination also takes the interface fluxes of the full
+// step (a static member kFlux = true and a member flux(f, H)).
+template <class D, class = void>
+struct TakesFlux {
+  static constexpr bool value = false;
+};
+template <class D>
+struct TakesFlux<D, decltype((void)D::kFlux)> {
+  static constexpr bool value = D::kFlux;
+};
+
 // One sweep over a pencil of M = N+6 cells.  Src::load(j, u) fetches cell j
 // (0 .. M-1, ghosts included) in pencil component order; Dst::store(i, u)
 // writes interior cell i (0 .. N-1).  The loop is fully unrolled, so the
-// rolling windows (indexed modulo 4) live in registers.
+// rolling windows (indexed modulo 4) live in registers.  A destination that
+// takes fluxes gets dst.flux(f, H) for every interface f - 1/2, f = 0 .. N:
+// the flux of Eq. (FullstepValue), u_i -= lam (H at i+1 - H at i).
 template <typename T, int N, class Src, class Dst>
 __device__ __forceinline__ void pencil_sweep(const Src& src, const Dst& dst, const Coef<T>& cf) {
   constexpr int M = N + 2 * kG;
@@ -153,6 +166,7 @@ __device__ __forceinline__ void pencil_sweep(const Src& src, const Dst& dst, con
         const T L = FLh[c][k] + vanleer(FLh[c][k] - FLh[d][k], FLh[b][k] - FLh[c][k]);
         H[k] = R - L;
       }
+      if constexpr (TakesFlux<Dst>::value) dst.flux(j - 5, H);
       if (j >= 6) {
         // Eq. (FullstepValue) for cell j-3 (interior cell j-6), from u^t
         T out[kNV];

@@ -28,7 +28,17 @@ struct KParams {
   double* ws_smax;               // [nblocks] per-block max signal speed
   double* ws_sums;               // [nblocks][10] per-block (sum, comp) x 5
   unsigned long long* counters;  // [0] floored, [1] non-physical
+  void* flux;                    // patch-boundary flux records (null: none)
+  const int64_t* flux_off;       // [nblocks] record offsets, or null for dense
 };
+
+// Patch edge: boundary fluxes are recorded on the planes at its multiples.
+constexpr int kPatch = 8;
+// Values in one block's flux record: 3 axes x (edge/8 + 1) planes x 5
+// variables x edge^2 face cells.
+constexpr int64_t flux_record_size(int edge) {
+  return 3 * (int64_t)(edge / kPatch + 1) * 5 * edge * edge;
+}
 
 // Variant of the batched kernel (chosen by the tuner or by default).
 struct Variant {
@@ -71,6 +81,15 @@ hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* n
                                   const void* cin, const int64_t* coff, int ncoarse,
                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// Closing step of a level pair: ck is the coarse level (interior blocks read
+// and written at uout / out_off, flux records at flux / flux_off), fk the
+// fine level (interior blocks read at uin with the interior offsets out_off,
+// flux records at flux / flux_off).  rows: [nrows][5] restriction rows, or
+// [nrows][8] face rows of one pass.
+hipError_t launch_restrict(int dtype, const KParams& ck, const KParams& fk, const int32_t* rows,
+                           int nrows, hipStream_t s);
+hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, const int32_t* rows,
+                               int nrows, hipStream_t s);
 
 // Variants compiled into the library.
 int variant_count();

@@ -344,6 +344,49 @@ struct Held {
   }
 };
 
+// A sweep destination that also records the patch-boundary fluxes of its
+// pencil: the flux through every interface on a multiple of the patch edge
+// goes to the block's flux record (the closing step's input, Sec. 3.1).  fp
+// is the record entry of this pencil's face cell on plane 0, variable 0 (null
+// for a pencil outside the interior, which records nothing); planes are
+// 5 N^2 apart, variables N^2, in global component order.  off is the first
+// cell of a half pencil: the interface the two halves share is recorded by
+// the first half only.
+template <typename T, int N, int D, class Dst>
+struct FluxTap {
+  const Dst& dst;
+  T* fp;
+  int off;
+  static constexpr bool kFlux = true;
+  __device__ inline void store(int i, const T u[kNV]) const { dst.store(i, u); }
+  __device__ inline void flux(int f, const T H[kNV]) const {
+    const int g = f + off;
+    if (fp != nullptr && g % kPatch == 0 && (f > 0 || off == 0)) {
+      T* p = fp + (g / kPatch) * (kNV * N * N);
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) p[gcomp<D>(k) * (N * N)] = H[k];
+    }
+  }
+};
+
+// dst itself, or dst recording fluxes when FLUX is set.
+template <bool FLUX, typename T, int N, int D, class Dst>
+__device__ __forceinline__ decltype(auto) tap(const Dst& dst, T* fp, int off) {
+  if constexpr (FLUX) {
+    return FluxTap<T, N, D, Dst>{dst, fp, off};
+  } else {
+    (void)fp;
+    (void)off;
+    return (dst);
+  }
+}
+
+// Record entry of face cell (a, b) on plane 0 of axis d (null if no record).
+template <typename T, int N>
+__device__ __forceinline__ T* flux_entry(T* rec, int d, int a, int b) {
+  return rec ? rec + d * ((N / kPatch + 1) * kNV * N * N) + a * N + b : nullptr;
+}
+
 // LDS a thread group needs for one block: the block after sweep 0, the 27
 // neighbour offsets of gather mode and a flag word.
 template <typename T, int N, int PAD>
@@ -367,7 +410,8 @@ struct BlockLds {
 // lookahead (persistent launch, one thread of the workgroup): a work counter
 // to draw the next ticket from once the second sweep is done, so that the
 // atomic's latency hides behind the third sweep; the ticket goes to *ticket.
-template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER>
+template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER,
+          bool FLUX = false>
 __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
                                               BlockLds<T, N, PAD>& sm,
                                               unsigned* lookahead = nullptr,
@@ -385,9 +429,15 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
   T* __restrict__ bout = nullptr;
   double dh = 1.0;
   Coef<T> cf{};
+  // FLUX: this block's patch-boundary flux record; face cells (a, b) of an
+  // axis are its two other axes, the higher-numbered first
+  T* frec = nullptr;
   if (active) {
     bout = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3);
     cf = make_coef<T>(kp, b, dh);
+    if constexpr (FLUX)
+      frec = reinterpret_cast<T*>(kp.flux) +
+             (kp.flux_off ? kp.flux_off[b] : (int64_t)b * flux_record_size(N));
   }
 
   if constexpr (GATHER) {
@@ -451,11 +501,25 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
       }
       const GlobalPencil<T, M, D0> src{bin + start};
       const LdsSink0<T, L, D0> dst{S, c1, c2};
-      pencil_sweep<T, N>(src, dst, cf);
+      T* fp = nullptr;
+      if constexpr (FLUX) {
+        // x pencils: face (z, y) = (c2, c1); z pencils: face (y, x) = (c1, c2)
+        const bool in = c1 >= kG && c1 < N + kG && c2 >= kG && c2 < N + kG;
+        fp = in ? flux_entry<T, N>(frec, D0, (ORDER == 0 ? c2 : c1) - kG,
+                                   (ORDER == 0 ? c1 : c2) - kG)
+                : nullptr;
+      }
+      pencil_sweep<T, N>(src, tap<FLUX, T, N, D0>(dst, fp, 0), cf);
     }
   }
   __syncthreads();
-  // sweep 1: interior along c0, all of c2
+  // sweep 1: interior along c0, all of c2 (y pencils; face (z, x) is
+  // (c2, c0) for xyz and (c0, c2) for zyx)
+  auto sweep1_flux = [&](int c0, int c2) -> T* {
+    if (c2 < kG || c2 >= N + kG) return nullptr;
+    return ORDER == 0 ? flux_entry<T, N>(frec, 1, c2 - kG, c0)
+                      : flux_entry<T, N>(frec, 1, c0, c2 - kG);
+  };
   if constexpr ((SPLIT & 1) != 0) {
     constexpr int F = NT / 2;          // whole pencils
     constexpr int R = N * M - F;       // pencils done in halves
@@ -465,17 +529,21 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
     const int p = t < F ? t : F + (t - F) / 2;
     const Shifted<LdsPencil1<T, L, D1>> acc{{S, p % N, p / N}, ((t - F) & 1) * (N / 2)};
     Held<T, N / 2> held;
+    T* fp = nullptr;
+    if constexpr (FLUX) fp = sweep1_flux(acc.a.c0, acc.a.c2);
     if (active && t < F) {
-      pencil_sweep<T, N>(acc.a, acc.a, cf);
+      pencil_sweep<T, N>(acc.a, tap<FLUX, T, N, D1>(acc.a, fp, 0), cf);
     } else if (half) {
-      pencil_sweep<T, N / 2>(acc, held, cf);
+      pencil_sweep<T, N / 2>(acc, tap<FLUX, T, N, D1>(held, fp, acc.off), cf);
     }
     __syncthreads();
     if (half) held.flush(acc);
   } else {
     for (int p = tid; active && p < N * M; p += NT) {
       const LdsPencil1<T, L, D1> acc{S, p % N, p / N};
-      pencil_sweep<T, N>(acc, acc, cf);
+      T* fp = nullptr;
+      if constexpr (FLUX) fp = sweep1_flux(acc.c0, acc.c2);
+      pencil_sweep<T, N>(acc, tap<FLUX, T, N, D1>(acc, fp, 0), cf);
     }
   }
   __syncthreads();
@@ -490,29 +558,40 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
     T* base = ORDER == 0 ? bout + c0 + N * y : bout + N * y + N * N * c0;
     return GlobalOut<T, N, D2>{base, &dg, kp.diag, kp.gamma, kp.pfloor};
   };
+  // face of a sweep-2 pencil: (y, x) = (c1, c0) for z pencils, (z, y) =
+  // (c0, c1) for x pencils
+  auto sweep2_flux = [&](int c0, int c1) -> T* {
+    return ORDER == 0 ? flux_entry<T, N>(frec, 2, c1 - kG, c0)
+                      : flux_entry<T, N>(frec, 0, c0, c1 - kG);
+  };
   if constexpr ((SPLIT & 2) != 0) {
     static_assert(2 * N * N == NT, "sweep-2 halves need one thread each");
     if (active) {
       const int p = tid / 2, off = (tid & 1) * (N / 2);
       const int c0 = p % N, c1 = p / N + kG;
       const Shifted<LdsPencil2<T, L, D2>> src{{S, c0, c1}, off};
+      T* fp = nullptr;
+      if constexpr (FLUX) fp = sweep2_flux(c0, c1);
       if constexpr (ORDER == 1 && sizeof(T) == 4) {
         // x pencils: the half pencil's cells wait in registers and leave as
         // 16-byte runs along x (along z the lanes' stores already coalesce;
         // FP64 keeps the direct stores, its registers are already full)
         Held<T, N / 2> held;
-        pencil_sweep<T, N / 2>(src, held, cf);
+        pencil_sweep<T, N / 2>(src, tap<FLUX, T, N, D2>(held, fp, off), cf);
         out_pencil(c0, c1).template store_run<N / 2>(off, held.v);
       } else {
         const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
-        pencil_sweep<T, N / 2>(src, dst, cf);
+        pencil_sweep<T, N / 2>(src, tap<FLUX, T, N, D2>(dst, fp, off), cf);
       }
     }
   } else {
     for (int p = tid; active && p < N * N; p += NT) {
       const int c0 = p % N, c1 = p / N + kG;
       const LdsPencil2<T, L, D2> src{S, c0, c1};
-      pencil_sweep<T, N>(src, out_pencil(c0, c1), cf);
+      T* fp = nullptr;
+      if constexpr (FLUX) fp = sweep2_flux(c0, c1);
+      const auto dst = out_pencil(c0, c1);
+      pencil_sweep<T, N>(src, tap<FLUX, T, N, D2>(dst, fp, 0), cf);
     }
   }
   __syncthreads();
@@ -522,12 +601,13 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
 // One workgroup per block, blocks spread over the XCDs in contiguous ranges.
 // With mixed edges each edge has its own launch and a workgroup whose block
 // has the other edge exits at once.
-template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER>
+template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER,
+          bool FLUX = false>
 __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   __shared__ BlockLds<T, N, PAD> sm;
   const int b = xcd_block(blockIdx.x, gridDim.x);
   if (block_edge(kp, b) != N) return;  // uniform over the workgroup
-  advance_block<T, N, ORDER, NT, PAD, SPLIT, GATHER>(kp, b, threadIdx.x, sm);
+  advance_block<T, N, ORDER, NT, PAD, SPLIT, GATHER, FLUX>(kp, b, threadIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -626,7 +706,7 @@ __device__ __forceinline__ int part_lo(int n, int k) {
   return k * q + (k < r ? k : r);
 }
 
-template <typename T, int ORDER, bool GATHER>
+template <typename T, int ORDER, bool GATHER, bool FLUX = false>
 __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
   using B16 = BlockLds<T, 16, kFusedPad16>;
   using B8 = BlockLds<T, 8, kFusedPad8>;
@@ -673,15 +753,15 @@ __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     if (wi < n16) {
-      advance_block<T, 16, ORDER, 512, kFusedPad16, kFusedSplit16, GATHER>(kp, pl.list[wi], tid,
-                                                                          sm, ahead, &ticket);
+      advance_block<T, 16, ORDER, 512, kFusedPad16, kFusedSplit16, GATHER, FLUX>(
+          kp, pl.list[wi], tid, sm, ahead, &ticket);
     } else {
       const int q = tid >> 7;
       const int i = 4 * (wi - n16) + q;
       const int b = i < n8 ? pl.list[n16 + i] : -1;
       B8* quarter = reinterpret_cast<B8*>(&sm) + q;
-      advance_block<T, 8, ORDER, 128, kFusedPad8, kFusedSplit8, GATHER>(kp, b, tid & 127, *quarter,
-                                                                        ahead, &ticket);
+      advance_block<T, 8, ORDER, 128, kFusedPad8, kFusedSplit8, GATHER, FLUX>(
+          kp, b, tid & 127, *quarter, ahead, &ticket);
     }
   }
 }
@@ -995,6 +1075,114 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
 }
 
 // ---------------------------------------------------------------------------
+// closing step of a level pair (Sec. 2.1, step 3; Sec. 3.1)
+// ---------------------------------------------------------------------------
+//
+// Both kernels take the coarse level as ck (its interior blocks, read and
+// written, at ck.uout / ck.out_off; its flux records at ck.flux /
+// ck.flux_off) and the fine level as fk (interior blocks read at fk.uin with
+// the interior offsets fk.out_off; flux records at fk.flux / fk.flux_off).
+// A row that names a block out of range, an edge other than 8 or 16, or a
+// region outside its blocks is skipped and its cells are counted as
+// non-physical.
+
+constexpr int kCloseNT = 128;
+
+template <typename T>
+__device__ __forceinline__ const T* interior_of(const KParams& k, const void* base, int b, int e) {
+  return static_cast<const T*>(base) + (k.out_off ? k.out_off[b] : (int64_t)b * kNV * e * e * e);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* record_of(const KParams& k, int b, int e) {
+  return static_cast<const T*>(k.flux) + (k.flux_off ? k.flux_off[b] : (int64_t)b * flux_record_size(e));
+}
+
+__device__ __forceinline__ bool edge_ok(int e) { return e == 8 || e == 16; }
+
+// Restriction: row r = (f, c, ox, oy, oz); the (e_f/2)^3 coarse cells of
+// block c at offset (ox, oy, oz) become the mean of their eight children in
+// fine block f, summed in the order (dz, dy, dx) = 000, 001, .., 111, then
+// times 1/8.  One workgroup per row.
+template <typename T>
+__global__ __launch_bounds__(kCloseNT) void k_restrict(KParams ck, KParams fk, const int32_t* rows) {
+  const int32_t* r = rows + 5 * (int64_t)blockIdx.x;
+  const int f = r[0], c = r[1], ox = r[2], oy = r[3], oz = r[4];
+  const bool fin = f >= 0 && f < fk.nblocks, cin = c >= 0 && c < ck.nblocks;
+  const int ef = fin ? block_edge(fk, f) : 0, ec = cin ? block_edge(ck, c) : 0;
+  const int h = ef / 2;
+  const bool ok = fin && cin && edge_ok(ef) && edge_ok(ec) && ox >= 0 && oy >= 0 && oz >= 0 &&
+                  ox + h <= ec && oy + h <= ec && oz + h <= ec;
+  if (!ok) {
+    if (threadIdx.x == 0) atomicAdd(&ck.counters[1], edge_ok(ef) ? (unsigned long long)h * h * h : 1ull);
+    return;
+  }
+  const T* u = interior_of<T>(fk, fk.uin, f, ef);
+  T* v = const_cast<T*>(interior_of<T>(ck, ck.uout, c, ec));
+  const int h3 = h * h * h;
+  const int64_t ef3 = (int64_t)ef * ef * ef, ec3 = (int64_t)ec * ec * ec;
+  const T eighth = T(0.125);
+  for (int i = threadIdx.x; i < kNV * h3; i += kCloseNT) {
+    const int k = i / h3, cell = i % h3;
+    const int x = cell % h, y = (cell / h) % h, z = cell / (h * h);
+    const T* p = u + k * ef3 + 2 * x + ef * (2 * y + ef * (2 * z));
+    const int sy = ef, sz = ef * ef;
+    T sum = p[0];
+    sum = sum + p[1];
+    sum = sum + p[sy];
+    sum = sum + p[sy + 1];
+    sum = sum + p[sz];
+    sum = sum + p[sz + 1];
+    sum = sum + p[sz + sy];
+    sum = sum + p[sz + sy + 1];
+    v[k * ec3 + (ox + x) + ec * ((oy + y) + (int64_t)ec * (oz + z))] = sum * eighth;
+  }
+}
+
+// Flux correction: row r = (c, d, s, qc, oa, ob, f, qf).  Face cells
+// (oa + a, ob + b), a, b < e_f/2, of plane qc along axis d of coarse block c
+// are covered by the 2 x 2 fine face cells (2a.., 2b..) of plane qf of fine
+// block f; the coarse cell on the s side of the plane (s = 1: below it, the
+// interface is its + face) takes u + lam (H_c - H_f), or u - lam (H_c - H_f)
+// for s = 0, with lam = dt_c / dh_c and H_f the mean of the four fine fluxes
+// summed ((f00 + f01) + f10) + f11.  One workgroup per row; rows of one pass
+// (one d and s) never share a cell.
+template <typename T>
+__global__ __launch_bounds__(kCloseNT) void k_flux_correct(KParams ck, KParams fk, const int32_t* rows) {
+  const int32_t* r = rows + 8 * (int64_t)blockIdx.x;
+  const int c = r[0], d = r[1], s = r[2], qc = r[3], oa = r[4], ob = r[5], f = r[6], qf = r[7];
+  const bool fin = f >= 0 && f < fk.nblocks, cin = c >= 0 && c < ck.nblocks;
+  const int ef = fin ? block_edge(fk, f) : 0, ec = cin ? block_edge(ck, c) : 0;
+  const int h = ef / 2;
+  const bool ok = fin && cin && edge_ok(ef) && edge_ok(ec) && d >= 0 && d < 3 && (s == 0 || s == 1) &&
+                  (s ? qc >= 1 && qc <= ec / kPatch : qc >= 0 && qc < ec / kPatch) && qf >= 0 &&
+                  qf <= ef / kPatch && oa >= 0 && ob >= 0 && oa + h <= ec && ob + h <= ec;
+  if (!ok) {
+    if (threadIdx.x == 0) atomicAdd(&ck.counters[1], edge_ok(ef) ? (unsigned long long)h * h : 1ull);
+    return;
+  }
+  T* u = const_cast<T*>(interior_of<T>(ck, ck.uout, c, ec));
+  const T* Hc = record_of<T>(ck, c, ec) + (int64_t)(d * (ec / kPatch + 1) + qc) * kNV * ec * ec;
+  const T* Hf = record_of<T>(fk, f, ef) + (int64_t)(d * (ef / kPatch + 1) + qf) * kNV * ef * ef;
+  double dt = ck.d_dt ? ck.d_dt[c] : ck.dt, dh = ck.d_dh ? ck.d_dh[c] : ck.dh;
+  const T lam = (T)(dt / dh);
+  const T quarter = T(0.25);
+  // cell strides along d and along the face axes (the higher-numbered first)
+  const int st[3] = {1, ec, ec * ec};
+  const int dhi = d == 0 ? 2 : d == 1 ? 2 : 1, dlo = d == 0 ? 1 : 0;
+  const int i_d = s ? kPatch * qc - 1 : kPatch * qc;
+  const int64_t ec3 = (int64_t)ec * ec * ec;
+  for (int i = threadIdx.x; i < kNV * h * h; i += kCloseNT) {
+    const int k = i / (h * h), a = (i / h) % h, b = i % h;
+    const T* F = Hf + k * ef * ef + (2 * a) * ef + 2 * b;
+    const T hf = (((F[0] + F[1]) + F[ef]) + F[ef + 1]) * quarter;
+    const T t = Hc[k * ec * ec + (oa + a) * ec + (ob + b)] - hf;
+    T* p = u + k * ec3 + i_d * st[d] + (oa + a) * st[dhi] + (ob + b) * st[dlo];
+    *p = s ? *p + lam * t : *p - lam * t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers and the variant table
 // ---------------------------------------------------------------------------
 
@@ -1019,9 +1207,27 @@ bool variant_supported(int dtype, const Variant& v) {
   return !(dtype == 2 && v.edge == 16);
 }
 
+// The flux-recording advance exists for one variant per (type, edge): the
+// default ones (edge 16: 512 threads, pad 16, split 3; edge 8: 128 threads
+// FP32 or 256 threads FP64, pad 8, split 0).
+template <typename T, int N, int NT, int PAD, int SPLIT>
+constexpr bool kFluxVariant =
+    N == 16 ? (NT == 512 && PAD == 16 && SPLIT == 3)
+            : (NT == (sizeof(T) == 4 ? 128 : 256) && PAD == 8 && SPLIT == 0);
+
 template <typename T, int N, int NT, int PAD, int SPLIT>
 static hipError_t launch_b(int order, bool gather, const KParams& kp, hipStream_t s) {
   const dim3 grid(kp.nblocks), block(NT);
+  if (kp.flux) {
+    if constexpr (kFluxVariant<T, N, NT, PAD, SPLIT>) {
+      if (gather) return hipErrorInvalidValue;
+      if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, false, true>), grid, block, 0, s, kp);
+      else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, false, true>), grid, block, 0, s, kp);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (gather) {
     if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, true>), grid, block, 0, s, kp);
     else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, true>), grid, block, 0, s, kp);
@@ -1069,7 +1275,11 @@ hipError_t launch_fused(int dtype, int order, bool gather, const KParams& kp, co
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid(workgroups), block(512);
-  if (gather) {
+  if (kp.flux) {
+    if (gather) return hipErrorInvalidValue;
+    if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, false, true>), grid, block, 0, s, kp, pl);
+    else hipLaunchKernelGGL((k_fused<float, 1, false, true>), grid, block, 0, s, kp, pl);
+  } else if (gather) {
     if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, true>), grid, block, 0, s, kp, pl);
     else hipLaunchKernelGGL((k_fused<float, 1, true>), grid, block, 0, s, kp, pl);
   } else {
@@ -1145,6 +1355,24 @@ hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* n
 
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(int dtype, const KParams& ck, const KParams& fk, const int32_t* rows,
+                           int nrows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  if (dtype == 1) hipLaunchKernelGGL((k_restrict<float>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
+  else hipLaunchKernelGGL((k_restrict<double>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, const int32_t* rows,
+                               int nrows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  if (dtype == 1)
+    hipLaunchKernelGGL((k_flux_correct<float>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
+  else
+    hipLaunchKernelGGL((k_flux_correct<double>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
   return hipGetLastError();
 }
 

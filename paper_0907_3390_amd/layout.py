@@ -216,3 +216,183 @@ def two_level(Nc: int, origin, shape, n: int):
                     cnbr[b, r] = px + npc * (py + npc * pz)
     fine = BlockSet(np.full(nb, n), np.full(nb, 0.5 / Nc), nbr)
     return coarse, fine, cnbr, corigin
+
+
+# ---------------------------------------------------------------------------
+# closing step of a level pair (Sec. 2.1 step 3, Sec. 3.1): patch-boundary
+# flux records, restriction rows and coarse-fine face rows
+# ---------------------------------------------------------------------------
+
+PATCH = 8
+# columns of a face row (see closing_tables)
+FACE_COLS = ("c", "d", "s", "qc", "oa", "ob", "f", "qf")
+
+
+def flux_record_size(edge: int) -> int:
+    """Values in one block's patch-boundary flux record: 3 axes x (edge/8 + 1)
+    planes x 5 variables x edge^2 face cells."""
+    return 3 * (edge // PATCH + 1) * NVAR * edge * edge
+
+
+def flux_offsets(edges) -> np.ndarray:
+    """Element offsets of the blocks' flux records packed in block order."""
+    sizes = np.array([flux_record_size(int(e)) for e in edges], dtype=np.int64)
+    return np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+
+
+def _face_axes(d: int):
+    """The two axes of a face normal to d, higher-numbered first."""
+    return {0: (2, 1), 1: (2, 0), 2: (1, 0)}[d]
+
+
+def closing_tables(patches, base: int, locate):
+    """Restriction and flux-correction rows of every level pair of a static
+    octree of 8^3 patches over a periodic box of ``base`` root patches per
+    axis.
+
+    patches: iterable of (level, px, py, pz); a patch of level l > 0 is a
+    child of (l-1, px//2, py//2, pz//2), and children come in complete
+    families of eight.  locate(level, px, py, pz) -> (block, (ox, oy, oz))
+    names the block holding the patch and the patch's cell offset in it (a
+    patch is its own block, offset 0; or one octant of a 16^3 patch group).
+
+    Returns {level l: (restrict_rows, face_rows, pass_count)} for every l
+    with a finer level:
+      restrict_rows int32 [R, 5] (f, c, ox, oy, oz): fine block f (level
+        l+1) averages into coarse block c (level l) at coarse-cell offset
+        (ox, oy, oz); one row per fine block.
+      face_rows int32 [F, 8] (c, d, s, qc, oa, ob, f, qf): coarse block c
+        holds an unrefined patch whose face along axis d (s = 1: its + face,
+        s = 0: its - face) is a coarse-fine interface at plane qc of c's flux
+        record; the face cells [oa, oa + e_f/2) x [ob, ob + e_f/2) of that
+        plane (face axes higher-numbered first) are covered by plane qf of
+        fine block f (edge e_f).  Rows are sorted by pass 2d + s, then c, f.
+      pass_count int32 [6]: rows of each pass.
+    """
+    present = set(tuple(int(v) for v in p) for p in patches)
+    levels = sorted(set(p[0] for p in present))
+    out = {}
+    for lev in levels:
+        if lev + 1 not in levels:
+            continue
+        n_l = base << lev
+
+        def refined(px, py, pz):
+            return (lev + 1, 2 * px, 2 * py, 2 * pz) in present
+
+        rrows, seen = [], set()
+        for (l1, cx, cy, cz) in sorted(p for p in present if p[0] == lev + 1):
+            fb, fo = locate(l1, cx, cy, cz)
+            if any(fo) or fb in seen:
+                continue  # one row per fine block, from its corner child
+            seen.add(fb)
+            cb, co = locate(lev, cx // 2, cy // 2, cz // 2)
+            bits = (cx & 1, cy & 1, cz & 1)
+            rrows.append((fb, cb) + tuple(co[a] + 4 * bits[a] for a in range(3)))
+        frows = []
+        for (l0, px, py, pz) in sorted(p for p in present if p[0] == lev):
+            if refined(px, py, pz):
+                continue
+            P = (px, py, pz)
+            cb, co = locate(lev, px, py, pz)
+            for d in range(3):
+                hi, lo = _face_axes(d)
+                for s in (0, 1):
+                    Q = list(P)
+                    Q[d] = (P[d] + (1 if s else -1)) % n_l
+                    if (lev, *Q) not in present or not refined(*Q):
+                        continue
+                    done = set()
+                    for c in range(8):
+                        bit = (c & 1, (c >> 1) & 1, c >> 2)
+                        if bit[d] != (0 if s else 1):
+                            continue  # children of Q that touch P
+                        C = tuple(2 * Q[a] + bit[a] for a in range(3))
+                        fb, fo = locate(lev + 1, *C)
+                        if fb in done:
+                            continue
+                        done.add(fb)
+                        qc = (co[d] + (PATCH if s else 0)) // PATCH
+                        qf = (fo[d] + (0 if s else PATCH)) // PATCH
+                        # the fine block's face corner, in coarse cells of P's face
+                        oa = co[hi] + (PATCH * bit[hi] - fo[hi]) // 2
+                        ob = co[lo] + (PATCH * bit[lo] - fo[lo]) // 2
+                        frows.append((cb, d, s, qc, oa, ob, fb, qf))
+        frows.sort(key=lambda r: (2 * r[1] + r[2], r[0], r[6]))
+        count = np.zeros(6, dtype=np.int32)
+        for r in frows:
+            count[2 * r[1] + r[2]] += 1
+        out[lev] = (np.array(rrows, dtype=np.int32).reshape(-1, 5),
+                    np.array(frows, dtype=np.int32).reshape(-1, 8), count)
+    return out
+
+
+class RefinedLevels:
+    """A two-level periodic hierarchy: the coarse level of Nc^3 cells as 8^3
+    patches numbered x fastest, and the refined patches ``refined[pz, py, px]``
+    (a boolean array of Nc/8 per axis) replaced on the next level by fine
+    blocks of edge n (8: the eight child patches, 16: one 2^3 patch group),
+    numbered refined patch by refined patch (pz slowest, px fastest), then
+    block by block inside the patch (z slowest, x fastest).
+
+    Attributes: coarse, fine (BlockSets; the fine sibling table is -1 where
+    the neighbouring region is not refined), cnbr [B, 27] and corigin [B, 3]
+    (for the coarse-fine ghost fill: the coarse patches around each fine
+    block's parent and the block's corner in coarse cells inside its parent,
+    x first), origins [B, 3] fine-cell corners (z, y, x), patches (the
+    octree, for closing_tables), locate."""
+
+    def __init__(self, Nc: int, refined, n: int):
+        refined = np.asarray(refined, dtype=bool)
+        npc = Nc // PATCH
+        if Nc % PATCH or refined.shape != (npc, npc, npc) or n not in (8, 16):
+            raise ValueError("refined must be (Nc/8,)*3 and the fine edge 8 or 16")
+        self.Nc, self.n, self.refined = Nc, n, refined
+        self.coarse = periodic_grid_blockset(Nc, PATCH, dh=1.0 / Nc)
+        k = 2 * PATCH // n              # fine blocks per refined patch and axis
+        nfb = 2 * Nc // n               # fine block grid per axis (periodic)
+        ref = [tuple(int(v) for v in p) for p in np.argwhere(refined)]   # (pz, py, px)
+        index, origins = {}, []
+        for pz, py, px in ref:
+            for bz in range(k):
+                for by in range(k):
+                    for bx in range(k):
+                        g = (k * px + bx, k * py + by, k * pz + bz)
+                        index[g] = len(origins)
+                        origins.append((n * g[2], n * g[1], n * g[0]))
+        nb = len(origins)
+        nbr = np.full((nb, 27), -1, dtype=np.int32)
+        cnbr = np.empty((nb, 27), dtype=np.int32)
+        corigin = np.empty((nb, 3), dtype=np.int32)
+        for g, b in index.items():
+            corner = [n * g[a] // 2 for a in range(3)]       # coarse cells, x first
+            parent = [c // PATCH for c in corner]
+            corigin[b] = [c - PATCH * p for c, p in zip(corner, parent)]
+            for rz in (-1, 0, 1):
+                for ry in (-1, 0, 1):
+                    for rx in (-1, 0, 1):
+                        r = (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)
+                        s = ((g[0] + rx) % nfb, (g[1] + ry) % nfb, (g[2] + rz) % nfb)
+                        nbr[b, r] = index.get(s, -1)
+                        q = ((parent[0] + rx) % npc, (parent[1] + ry) % npc, (parent[2] + rz) % npc)
+                        cnbr[b, r] = q[0] + npc * (q[1] + npc * q[2])
+        self.fine = BlockSet(np.full(nb, n), np.full(nb, 0.5 / Nc), nbr)
+        self.cnbr, self.corigin = cnbr, corigin
+        self.origins = np.array(origins, dtype=np.int64).reshape(-1, 3)
+        self._index = index
+        self.patches = [(0, px, py, pz) for pz in range(npc) for py in range(npc) for px in range(npc)]
+        self.patches += [(1, 2 * px + (c & 1), 2 * py + (c >> 1 & 1), 2 * pz + (c >> 2))
+                         for pz, py, px in ref for c in range(8)]
+
+    def locate(self, level, px, py, pz):
+        npc = self.Nc // PATCH
+        if level == 0:
+            return px + npc * (py + npc * pz), (0, 0, 0)
+        k = 2 * PATCH // self.n
+        per = self.n // PATCH           # patches per fine block and axis
+        g = (px // per, py // per, pz // per)
+        return self._index[g], tuple(PATCH * (v % per) for v in (px, py, pz))
+
+    def tables(self):
+        """(restrict_rows, face_rows, pass_count) of the level pair."""
+        return closing_tables(self.patches, self.Nc // PATCH, self.locate)[0]

@@ -40,7 +40,7 @@ EXPORTS = [
     "tvd_conservation_sums", "tvd_read_flags", "tvd_fill_ghosts",
     "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
-    "tvd_fill_ghosts_amr",
+    "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
 ]
 
 
@@ -89,6 +89,11 @@ def load(path: str = LIB_PATH):
         "tvd_read_flags": (ctypes.c_int, [vp, i64p, i64p, vp]),
         "tvd_fill_ghosts": (ctypes.c_int, [vp, bp, vp, vp, vp, vp]),
         "tvd_fill_ghosts_amr": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp, vp]),
+        "tvd_patch_advance_flux": (ctypes.c_int, [vp, bp, vp, vp, vp, vp, i32, dbl, dbl, i32, vp,
+                                                  vp, vp]),
+        "tvd_restrict": (ctypes.c_int, [vp, bp, vp, bp, vp, vp, i32, vp]),
+        "tvd_flux_correct": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp,
+                                            ctypes.POINTER(ctypes.c_int32), vp]),
         "tvd_variant_count": (ctypes.c_int, []),
         "tvd_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 4),
         "tvd_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
@@ -191,6 +196,31 @@ class Context:
         st = self.lib.tvd_patch_advance_gather(self.h, batch.ref, _ptr(nbr), _ptr(u_in),
                                                _ptr(u_out), sweep_order, gamma, p_floor, flags,
                                                _ptr(smax), _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_patch_advance_flux(self, batch: Batch, u_in, u_out, flux, flux_off, sweep_order: int,
+                               gamma: float, p_floor: float = 0.0, flags: int = TVD_KERNEL_AUTO,
+                               smax=None, sums=None, stream=None, check: bool = True):
+        st = self.lib.tvd_patch_advance_flux(self.h, batch.ref, _ptr(u_in), _ptr(u_out),
+                                             _ptr(flux), _ptr(flux_off), sweep_order, gamma,
+                                             p_floor, flags, _ptr(smax), _ptr(sums),
+                                             _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_restrict(self, coarse: Batch, u_coarse, fine: Batch, u_fine, rows, stream=None,
+                     check: bool = True):
+        n = 0 if rows is None else int(rows.shape[0])
+        st = self.lib.tvd_restrict(self.h, coarse.ref, _ptr(u_coarse), fine.ref, _ptr(u_fine),
+                                   _ptr(rows), n, _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_flux_correct(self, coarse: Batch, u_coarse, coarse_flux, coarse_flux_off, fine: Batch,
+                         fine_flux, fine_flux_off, rows, pass_count, stream=None,
+                         check: bool = True):
+        pc = (ctypes.c_int32 * 6)(*[int(v) for v in pass_count])
+        st = self.lib.tvd_flux_correct(self.h, coarse.ref, _ptr(u_coarse), _ptr(coarse_flux),
+                                       _ptr(coarse_flux_off), fine.ref, _ptr(fine_flux),
+                                       _ptr(fine_flux_off), _ptr(rows), pc, _stream(stream))
         return self._check(st) if check else st
 
     def tvd_max_signal_speed(self, batch: Batch, u, layout: int, gamma: float, smax,

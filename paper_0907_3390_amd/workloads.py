@@ -210,6 +210,28 @@ class MultiLevel:
     def levels(self):
         return np.array([p[0] for p in self.patches])
 
+    def closing(self, edge: int = 8):
+        """Closing-step rows of every level pair (layout.closing_tables) for
+        the hierarchy as 8^3 patches (edge 8, blocks in ``patches`` order) or
+        as 2^3 patch groups (edge 16, blocks in ``group_blocks`` order)."""
+        from . import layout
+        if edge == 8:
+            idx = {p: i for i, p in enumerate(self.patches)}
+            locate = lambda l, x, y, z: (idx[(l, x, y, z)], (0, 0, 0))
+        else:
+            groups = self._group_list()
+            gidx = {g: i for i, g in enumerate(groups)}
+            locate = lambda l, x, y, z: (gidx[(l, x // 2, y // 2, z // 2)],
+                                         (8 * (x & 1), 8 * (y & 1), 8 * (z & 1)))
+        return layout.closing_tables(self.patches, self.base // 8, locate)
+
+    def _group_list(self):
+        by_lev = {}
+        for lev, px, py, pz in self.patches:
+            by_lev.setdefault(lev, set()).add((px // 2, py // 2, pz // 2))
+        return [(lev, *g) for lev in sorted(by_lev)
+                for g in sorted(by_lev[lev], key=lambda t: (t[2], t[1], t[0]))]
+
     def group_blocks(self):
         """The patches as 2^3 patch groups (Sec. 3.1): every family of eight
         siblings (level >= 1), and every aligned 2^3 set of root patches,
@@ -219,10 +241,10 @@ class MultiLevel:
         [(level, gx, gy, gz)], ghosted (G, 5, 22, 22, 22), dh (G,)), groups
         ordered by level; the cells of group (l, g) are those of patches
         (l, 2g + c), c in {0, 1}^3."""
+        groups = self._group_list()
         by_lev = {}
-        for lev, px, py, pz in self.patches:
-            by_lev.setdefault(lev, set()).add((px // 2, py // 2, pz // 2))
-        groups = [(lev, *g) for lev in sorted(by_lev) for g in sorted(by_lev[lev], key=lambda t: (t[2], t[1], t[0]))]
+        for g in groups:
+            by_lev.setdefault(g[0], []).append(g)
         for lev, gx, gy, gz in groups:
             for c in range(8):
                 if (lev, 2 * gx + (c & 1), 2 * gy + (c >> 1 & 1), 2 * gz + (c >> 2)) not in self._present:
@@ -322,7 +344,8 @@ def multilevel(base: int = 128, n_over: int = 32, seed: int = 3, max_level: int 
     exp(-r^2 / 2 r_k^2): centres uniform, A_k log-uniform in [10, 1e3], r_k =
     radius * U(0.5, 1.5).  A patch of level l is refined into its 2^3
     children when its densest cell reaches 8^(l+1) (the paper's cosmological
-    criterion rho_l >= 8^(l+1) rho_b, Sec. 5).  Gas at rest, P = P0.
+    criterion rho_l >= 8^(l+1) rho_b, Sec. 5) and its 26 neighbours exist on
+    level l (proper nesting, Sec. 2.1).  Gas at rest, P = P0.
 
     Cells take the density at their centres on every level.  Ghost cells
     covered by a patch of the same level are copied from it (sibling copy);
@@ -352,6 +375,15 @@ def multilevel(base: int = 128, n_over: int = 32, seed: int = 3, max_level: int 
         h = 1.0 / (base * 2 ** lev)
         xs, ys, zs = axes_of(cur, h, np.arange(n) + 0.5)
         hot = cur[rho_f(xs, ys, zs).reshape(len(cur), -1).max(axis=1) >= 8.0 ** (lev + 1)]
+        # proper nesting (Sec. 2.1): a patch is refined only if its 26
+        # neighbours exist on its level, so that refinement never jumps more
+        # than one level across adjacent patches
+        have = set(map(tuple, cur.tolist()))
+        npl = npb << lev
+        nest = [all(((p[0] + rx) % npl, (p[1] + ry) % npl, (p[2] + rz) % npl) in have
+                    for rz in (-1, 0, 1) for ry in (-1, 0, 1) for rx in (-1, 0, 1))
+                for p in hot.tolist()]
+        hot = hot[np.array(nest, dtype=bool)] if len(hot) else hot
         kids = np.array([(cx, cy, cz) for cz in range(2) for cy in range(2) for cx in range(2)],
                         dtype=np.int64)
         cur = (2 * hot[:, None, :] + kids[None, :, :]).reshape(-1, 3)

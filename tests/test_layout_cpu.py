@@ -69,3 +69,68 @@ def test_two_level_tables():
     assert cnbr[0, 13] == 1 and cnbr[0, 12] == 0 and cnbr[0, 14] == 0   # periodic, 2 patches per axis
     with pytest.raises(ValueError):
         layout.two_level(16, (4, 0, 0), (8, 8, 8), 8)
+
+
+def _L_refined():
+    r = np.zeros((4, 4, 4), dtype=bool)
+    r[1, 1, 1] = r[1, 1, 2] = r[1, 2, 1] = True
+    r[3, 0, 3] = True          # a refined patch at the periodic corner
+    return r
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_refined_levels_tables_match_geometry(n):
+    """Every restriction row and face row names cells that coincide in space,
+    and the face rows cover each coarse-fine interface cell face exactly once
+    (checked against a brute-force scan of the refinement mask)."""
+    Nc = 32
+    ref = _L_refined()
+    L = layout.RefinedLevels(Nc, ref, n)
+    rr, fr, count = L.tables()
+    corner = lambda c: np.array([8 * (c % 4), 8 * ((c // 4) % 4), 8 * (c // 16)])  # x, y, z
+    fo = L.origins[:, ::-1]                                                       # x, y, z
+    # restriction: fine block f is the coarse region at (c, offset)
+    assert sorted(rr[:, 0].tolist()) == list(range(L.fine.n_blocks))
+    for f, c, ox, oy, oz in rr:
+        assert np.array_equal(fo[f] // 2, corner(c) + [ox, oy, oz])
+        assert ref[(fo[f][2] // 16), (fo[f][1] // 16), (fo[f][0] // 16)]
+    # faces
+    assert count.sum() == len(fr) and np.all(np.diff(2 * fr[:, 1] + fr[:, 2]) >= 0)
+    covered = set()
+    for c, d, s, qc, oa, ob, f, qf in fr:
+        hi, lo = {0: (2, 1), 1: (2, 0), 2: (1, 0)}[d]
+        plane_c = corner(c)[d] + 8 * qc
+        plane_f = fo[f][d] + 8 * qf
+        assert (2 * plane_c - plane_f) % (2 * Nc) == 0
+        assert (2 * (corner(c)[hi] + oa) - fo[f][hi]) % (2 * Nc) == 0
+        assert (2 * (corner(c)[lo] + ob) - fo[f][lo]) % (2 * Nc) == 0
+        for a in range(n // 2):
+            for b in range(n // 2):
+                cell = [0, 0, 0]
+                cell[d] = (plane_c - 1 if s else plane_c) % Nc
+                cell[hi], cell[lo] = corner(c)[hi] + oa + a, corner(c)[lo] + ob + b
+                key = (tuple(cell), d, s)
+                assert key not in covered
+                covered.add(key)
+    want = set()
+    rc = np.repeat(np.repeat(np.repeat(ref, 8, 0), 8, 1), 8, 2)     # [z, y, x]
+    for z, y, x in np.argwhere(~rc):
+        for d in range(3):
+            for s in (0, 1):
+                q = [x, y, z]
+                q[d] = (q[d] + (1 if s else -1)) % Nc
+                if rc[q[2], q[1], q[0]]:
+                    want.add(((x, y, z), d, s))
+    assert covered == want
+
+
+def test_refined_levels_sibling_table():
+    ref = _L_refined()
+    L = layout.RefinedLevels(32, ref, 8)
+    fo = L.origins
+    pos = {tuple(o): b for b, o in enumerate(fo.tolist())}
+    for b in range(L.fine.n_blocks):
+        for r in range(27):
+            rx, ry, rz = r % 3 - 1, (r // 3) % 3 - 1, r // 9 - 1
+            o = ((fo[b][0] + 8 * rz) % 64, (fo[b][1] + 8 * ry) % 64, (fo[b][2] + 8 * rx) % 64)
+            assert L.fine.nbr[b, r] == pos.get(o, -1)

@@ -10,7 +10,7 @@ GAMMA = 5.0 / 3.0
 
 
 def _ml():
-    return wl.multilevel(base=32, n_over=4, seed=3, radius=0.05)
+    return wl.multilevel(base=32, n_over=4, seed=5, radius=0.07)
 
 
 def test_group_blocks_contain_the_patch_blocks():
@@ -42,3 +42,47 @@ def test_oracle_patches_and_groups_agree():
             p = outp[pidx[(lev, 2 * gx + cx, 2 * gy + cy, 2 * gz + cz)]]
             assert np.array_equal(p, outg[gi][:, 8 * cz:8 * cz + 8, 8 * cy:8 * cy + 8,
                                               8 * cx:8 * cx + 8])
+
+
+def test_hierarchy_is_properly_nested():
+    """Sec. 2.1: refinement never jumps more than one level across adjacent
+    patches, so every face of a level-l patch (l >= 1) without a same-level
+    neighbour borders a level-(l-1) patch."""
+    ml = _ml()
+    assert set(np.unique(ml.levels)) == {0, 1, 2, 3}
+    present = set(ml.patches)
+    nb = ml.base // 8
+    for lev, px, py, pz in ml.patches:
+        for rz in (-1, 0, 1):
+            for ry in (-1, 0, 1):
+                for rx in (-1, 0, 1):
+                    n_l = nb << lev
+                    q = ((px + rx) % n_l, (py + ry) % n_l, (pz + rz) % n_l)
+                    if (lev, *q) not in present:
+                        assert lev > 0 and (lev - 1, q[0] // 2, q[1] // 2, q[2] // 2) in present
+
+
+def test_closing_tables_cover_every_coarse_fine_face():
+    """The face rows of all level pairs cover each coarse-fine interface cell
+    face once, in patch and in patch-group blocks, and the restriction rows
+    cover each refined patch once."""
+    ml = _ml()
+    nb = ml.base // 8
+    present = set(ml.patches)
+    want = 0
+    for lev, px, py, pz in ml.patches:
+        if (lev + 1, 2 * px, 2 * py, 2 * pz) in present:
+            continue
+        for d in range(3):
+            for s in (-1, 1):
+                q = [px, py, pz]
+                q[d] = (q[d] + s) % (nb << lev)
+                if (lev, *q) in present and (lev + 1, 2 * q[0], 2 * q[1], 2 * q[2]) in present:
+                    want += 64     # an 8 x 8 coarse face
+    n_refined = sum(1 for p in ml.patches if (p[0] + 1, 2 * p[1], 2 * p[2], 2 * p[3]) in present)
+    for edge in (8, 16):
+        tabs = ml.closing(edge)
+        got = sum(int(((fr[:, 6] >= 0).sum())) * (edge // 2) ** 2 for _, fr, _ in tabs.values())
+        assert got == want
+        cells = sum(len(rr) * (edge // 2) ** 3 for rr, _, _ in tabs.values())
+        assert cells == n_refined * 512
