@@ -27,9 +27,12 @@ Reported (one JSON line on stdout):
 * amr_ghost_fill: the coarse-fine ghost fill (sibling copy, else Min-Mod
   limited interpolation from the coarser level) of 8^3 patches and 16^3
   groups covering a refined 256^3-cell box;
-* multilevel_batch: one step of a 4-level patch hierarchy (19 592 patches,
+* multilevel_batch: one step of a 4-level patch hierarchy (18 152 patches,
   per-block dt and dh) as one persistent FP32 launch on patches and on 2^3
-  patch groups, and as plain FP64 launches level by level.
+  patch groups, and as plain FP64 launches level by level;
+* closing_step: on the same hierarchy with one dt, the advance writing
+  patch-boundary flux records, and the restriction and coarse-fine flux
+  correction of every level pair.
 """
 from __future__ import annotations
 
@@ -222,16 +225,16 @@ def run_uneven(ctx, graph_steps=50):
     return res
 
 
-def run_multilevel(ctx, reps=10):
+def run_multilevel(ctx, ml, reps=10):
     """The multi-level batch: a 128^3 base of 8^3 patches and levels 1-3
-    around 32 seeded overdensities (19 592 patches, ghost zones pre-filled by
-    sibling copy or trilinear coarse-to-fine interpolation), per-block dt_b =
-    C dh_b / S computed on the device.  Timed: one step of every patch as one
-    persistent FP32 launch on the patches and on their 2^3 patch groups (16^3
-    blocks), against the plain FP64 kernel launched level by level."""
+    around 32 seeded overdensities (18 152 patches, properly nested, ghost
+    zones pre-filled by sibling copy or trilinear coarse-to-fine
+    interpolation), per-block dt_b = C dh_b / S computed on the device.
+    Timed: one step of every patch as one persistent FP32 launch on the
+    patches and on their 2^3 patch groups (16^3 blocks), against the plain
+    FP64 kernel launched level by level."""
     import torch
-    from paper_0907_3390_amd import tvd, workloads as wl
-    ml = wl.multilevel()
+    from paper_0907_3390_amd import tvd
     groups, G, gdh = ml.group_blocks()
     cells = len(ml.patches) * 512
     res = {"workload": "multi-level batch: 128^3 base + levels 1-3 around 32 Gaussian "
@@ -289,6 +292,106 @@ def run_multilevel(ctx, reps=10):
         torch.cuda.empty_cache()
     res["speedup_fp32_groups_vs_fp64_plain"] = (res["fp32_persistent_groups"]["value"] /
                                                 res["fp64_plain_per_level"]["value"])
+    return res
+
+
+def run_closing(ctx, ml, reps=10):
+    """The closing step on the multi-level hierarchy (FP32, one dt on every
+    level): the advance writing the patch-boundary flux records of every
+    block (one persistent launch), then, level pair by level pair from the
+    finest, the restriction of the fine blocks into their parents and the
+    coarse-fine flux correction (six passes).  Timed with HIP events on the
+    launch stream over `reps` steps: the advance with and without records,
+    and the closing alone, as one launch per level pair (tvd_close_level) and
+    as separate restriction and six correction passes.  The closing kernels are bound by HBM;
+    their algorithmic bytes: restriction reads the fine interior and writes
+    1/8 of it; correction reads and writes one coarse cell and reads one
+    coarse and four fine fluxes per coarse face cell and variable."""
+    import torch
+    from paper_0907_3390_amd import layout, tvd
+    res = {"workload": "multi-level batch (128^3 base, levels 1-3, 18 152 patches), FP32, one dt"}
+    stream = torch.cuda.current_stream()
+    groups, G, gdh = ml.group_blocks()
+    for name, ghosted, dhs, edge in (("groups", G, gdh, 16), ("patches", ml.ghosted, ml.dh, 8)):
+        tabs = ml.closing(edge)
+        nb = len(dhs)
+        cells = nb * edge ** 3
+        u_in = torch.from_numpy(np.ascontiguousarray(ghosted)).float().cuda().reshape(-1)
+        u_out = torch.zeros(nb * 5 * edge ** 3, dtype=torch.float32, device="cuda")
+        flux = torch.zeros(nb * layout.flux_record_size(edge), dtype=torch.float32, device="cuda")
+        d_dh = torch.from_numpy(np.ascontiguousarray(dhs)).cuda()
+        sm = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.tvd_reserve(nb)
+        ctx.tvd_max_signal_speed(tvd.Batch(tvd.TVD_F32, nb, edge, d_dh=d_dh), u_in,
+                                 tvd.TVD_LAYOUT_GHOSTED, GAMMA, sm)
+        dt = CFL * float(np.min(dhs)) / float(sm.item())   # one dt on every level
+        b = tvd.Batch(tvd.TVD_F32, nb, edge, dt=dt, d_dh=d_dh)
+        dev = {}
+        for lev, (rr, fr, cnt) in tabs.items():
+            gr, gs = layout.group_face_rows(fr)
+            dev[lev] = tuple(torch.from_numpy(a).cuda() for a in (rr, fr, gr, gs)) + (cnt,)
+
+        def advance(o, rec):
+            if rec:
+                ctx.tvd_patch_advance_flux(b, u_in, u_out, flux, None, o, GAMMA,
+                                           flags=tvd.TVD_KERNEL_PERSISTENT)
+            else:
+                ctx.tvd_patch_advance(b, u_in, u_out, o, GAMMA, flags=tvd.TVD_KERNEL_PERSISTENT)
+
+        def close():
+            # one launch per level pair, finest pair first
+            for lev in sorted(dev, reverse=True):
+                rr, fr, gr, gs, cnt = dev[lev]
+                ctx.tvd_close_level(b, u_out, flux, None, b, u_out, flux, None, rr, gr, gs)
+
+        def close_separate():
+            # restriction, then six correction passes, per level pair
+            for lev in sorted(dev, reverse=True):
+                rr, fr, gr, gs, cnt = dev[lev]
+                ctx.tvd_restrict(b, u_out, b, u_out, rr)
+                ctx.tvd_flux_correct(b, u_out, flux, None, b, flux, None, fr, cnt)
+
+        def timed(fn):
+            fn(0)
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for r in range(reps):
+                fn(r % 2)
+            e.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(e) / reps
+
+        ms_plain = timed(lambda o: advance(o, False))
+        ms_flux = timed(lambda o: advance(o, True))
+        ms_close = timed(lambda o: close())
+        ms_close_sep = timed(lambda o: close_separate())
+        n_rr = sum(len(v[0]) for v in tabs.values())
+        n_fr = sum(len(v[1]) for v in tabs.values())
+        h = edge // 2
+        # algorithmic bytes of one closing (FP32)
+        b_restrict = n_rr * 4 * 5 * (edge ** 3 + h ** 3)
+        b_correct = n_fr * 4 * 5 * h * h * (2 + 1 + 4)
+        rec_bytes = nb * 4 * layout.flux_record_size(edge)
+        res[name] = {
+            "blocks": nb, "block_edge": edge, "restrict_rows": n_rr, "face_rows": n_fr,
+            "launches_per_closing": len(tabs),
+            "closing_separate_calls_ms": ms_close_sep,
+            "advance_ms": ms_plain, "advance_with_records_ms": ms_flux,
+            "record_overhead": ms_flux / ms_plain - 1.0,
+            "record_bytes_per_step": rec_bytes,
+            "closing_ms": ms_close,
+            "closing_algorithmic_bytes": b_restrict + b_correct,
+            "closing_GBs": (b_restrict + b_correct) / (ms_close * 1e-3) / 1e9,
+            "step_with_closing": {"value": cells / ((ms_flux + ms_close) * 1e-3),
+                                  "unit": "cell-updates/s"},
+        }
+        log(f"bench: closing ({name}): advance {ms_plain:.3f} ms, with records {ms_flux:.3f} ms, "
+            f"closing {ms_close:.3f} ms ({res[name]['closing_GBs']:.0f} GB/s algorithmic; "
+            f"{ms_close_sep:.3f} ms as separate calls), "
+            f"step {res[name]['step_with_closing']['value'] / 1e9:.2f} G cell-updates/s")
+        del u_in, u_out, flux
+        torch.cuda.empty_cache()
     return res
 
 
@@ -416,7 +519,9 @@ def main():
     ap.add_argument("--no-amr-fill", action="store_true",
                     help="skip the coarse-fine ghost-fill throughput")
     ap.add_argument("--no-multilevel", action="store_true",
-                    help="skip the multi-level (19 592 patches) throughput")
+                    help="skip the multi-level (18 152 patches) throughput")
+    ap.add_argument("--no-closing", action="store_true",
+                    help="skip the closing step (flux records, restriction, flux correction)")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch (4000 mixed boxes) throughput")
     ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
@@ -549,10 +654,18 @@ def main():
         log("bench: coarse-fine ghost fill")
         torch.cuda.empty_cache()
         out["amr_ghost_fill"] = run_amr_fill(ctx)
+    if not args.no_multilevel or not args.no_closing:
+        from paper_0907_3390_amd import workloads as wl
+        log("bench: building the multi-level hierarchy")
+        ml = wl.multilevel()
     if not args.no_multilevel:
         log("bench: multi-level batch")
         torch.cuda.empty_cache()
-        out["multilevel_batch"] = run_multilevel(ctx)
+        out["multilevel_batch"] = run_multilevel(ctx, ml)
+    if not args.no_closing:
+        log("bench: closing step on the multi-level hierarchy")
+        torch.cuda.empty_cache()
+        out["closing_step"] = run_closing(ctx, ml)
     if not args.no_uneven:
         log("bench: uneven batch of 4000 boxes")
         torch.cuda.empty_cache()

@@ -361,6 +361,30 @@ int tvd_flux_correct(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse,
                      const int64_t *d_fine_flux_off, const int32_t *d_rows,
                      const int32_t pass_count[6], void *stream);
 
+/*
+ * The closing of one level pair in a single launch: the restriction rows of
+ * tvd_restrict and the face rows of tvd_flux_correct, the latter grouped by
+ * coarse block instead of by pass.  Group g holds the rows
+ * [d_face_start[g], d_face_start[g+1]) of d_face_rows (n_face_rows rows in
+ * all, d_face_start has n_face_groups + 1 entries); all rows of a group name
+ * the same coarse block, no two groups name the same one, and a group's
+ * rows are sorted by pass 2 d + s.  Each group is applied by one workgroup in
+ * that order, so a cell on several interfaces gets its corrections in the
+ * order x-, x+, y-, y+, z-, z+, with the same arithmetic as
+ * tvd_flux_correct: the result is bit for bit that of tvd_restrict followed
+ * by tvd_flux_correct.  The restriction rows and the face rows must not
+ * write the same cell (refined and unrefined patches never share one).  A
+ * group whose rows name different coarse blocks or whose range leaves
+ * [0, n_face_rows) is skipped and counted once as non-physical; rows as for
+ * the two separate calls otherwise.  Asynchronous on stream.
+ */
+int tvd_close_level(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse,
+                    const void *d_coarse_flux, const int64_t *d_coarse_flux_off,
+                    const tvd_batch *fine, const void *d_fine, const void *d_fine_flux,
+                    const int64_t *d_fine_flux_off, const int32_t *d_restrict_rows,
+                    int32_t n_restrict, const int32_t *d_face_rows, int32_t n_face_rows,
+                    const int32_t *d_face_start, int32_t n_face_groups, void *stream);
+
 /* ---- step sequences as HIP graphs --------------------------------------------- */
 
 typedef struct tvd_graph tvd_graph;

@@ -466,6 +466,43 @@ int tvd_flux_correct(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse,
   return TVD_OK;
 }
 
+int tvd_close_level(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse,
+                    const void* d_coarse_flux, const int64_t* d_coarse_flux_off,
+                    const tvd_batch* fine, const void* d_fine, const void* d_fine_flux,
+                    const int64_t* d_fine_flux_off, const int32_t* d_restrict_rows,
+                    int32_t n_restrict, const int32_t* d_face_rows, int32_t n_face_rows,
+                    const int32_t* d_face_start, int32_t n_face_groups, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, coarse);
+  if (st) return st;
+  if ((st = check_batch(ctx, fine))) return st;
+  if (coarse->dtype != fine->dtype)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "coarse and fine batches differ in dtype");
+  if (n_restrict < 0 || n_face_rows < 0 || n_face_groups < 0 ||
+      (int64_t)n_restrict + n_face_groups > INT32_MAX)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "row counts");
+  if (n_restrict + n_face_groups == 0) return TVD_OK;
+  if (!d_coarse || (n_restrict && (!d_fine || !d_restrict_rows)) ||
+      (n_face_groups && (!d_coarse_flux || !d_fine_flux || !d_face_rows || !d_face_start)))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if ((coarse->d_edge && !d_coarse_flux_off) || (fine->d_edge && !d_fine_flux_off))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "mixed edges need flux record offsets");
+  if (d_coarse == d_coarse_flux || d_coarse == d_fine_flux)
+    return fail(ctx, TVD_ERR_ALIAS, "the state overlaps a flux record buffer");
+  DeviceGuard g(ctx->device);
+  tvd::KParams ck = make_params(ctx, coarse, nullptr, d_coarse, 1.0, 0.0);
+  ck.flux = const_cast<void*>(d_coarse_flux);
+  ck.flux_off = d_coarse_flux_off;
+  tvd::KParams fk = make_params(ctx, fine, d_fine, nullptr, 1.0, 0.0);
+  fk.flux = const_cast<void*>(d_fine_flux);
+  fk.flux_off = d_fine_flux_off;
+  hipError_t e = tvd::launch_close_level(coarse->dtype, ck, fk, d_restrict_rows, n_restrict,
+                                         d_face_rows, n_face_rows, d_face_start, n_face_groups,
+                                         (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "closing launch");
+  return TVD_OK;
+}
+
 int tvd_autotune(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr, const void* d_u_in,
                  void* d_u_out, double gamma, double p_floor, int32_t reps,
                  int32_t* chosen_index, float* best_ms) {

@@ -90,6 +90,10 @@ hipError_t launch_restrict(int dtype, const KParams& ck, const KParams& fk, cons
                            int nrows, hipStream_t s);
 hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, const int32_t* rows,
                                int nrows, hipStream_t s);
+// Restriction rows and grouped face rows of a level pair in one launch.
+hipError_t launch_close_level(int dtype, const KParams& ck, const KParams& fk,
+                              const int32_t* rrows, int nr, const int32_t* frows, int nf,
+                              const int32_t* start, int ngroups, hipStream_t s);
 
 // Variants compiled into the library.
 int variant_count();

@@ -1100,13 +1100,12 @@ __device__ __forceinline__ const T* record_of(const KParams& k, int b, int e) {
 
 __device__ __forceinline__ bool edge_ok(int e) { return e == 8 || e == 16; }
 
-// Restriction: row r = (f, c, ox, oy, oz); the (e_f/2)^3 coarse cells of
-// block c at offset (ox, oy, oz) become the mean of their eight children in
-// fine block f, summed in the order (dz, dy, dx) = 000, 001, .., 111, then
-// times 1/8.  One workgroup per row.
+// Restriction of one row (f, c, ox, oy, oz) by the calling workgroup: the
+// (e_f/2)^3 coarse cells of block c at offset (ox, oy, oz) become the mean of
+// their eight children in fine block f, summed in the order (dz, dy, dx) =
+// 000, 001, .., 111, then times 1/8.
 template <typename T>
-__global__ __launch_bounds__(kCloseNT) void k_restrict(KParams ck, KParams fk, const int32_t* rows) {
-  const int32_t* r = rows + 5 * (int64_t)blockIdx.x;
+__device__ __forceinline__ void restrict_row(const KParams& ck, const KParams& fk, const int32_t* r) {
   const int f = r[0], c = r[1], ox = r[2], oy = r[3], oz = r[4];
   const bool fin = f >= 0 && f < fk.nblocks, cin = c >= 0 && c < ck.nblocks;
   const int ef = fin ? block_edge(fk, f) : 0, ec = cin ? block_edge(ck, c) : 0;
@@ -1122,7 +1121,7 @@ __global__ __launch_bounds__(kCloseNT) void k_restrict(KParams ck, KParams fk, c
   const int h3 = h * h * h;
   const int64_t ef3 = (int64_t)ef * ef * ef, ec3 = (int64_t)ec * ec * ec;
   const T eighth = T(0.125);
-  for (int i = threadIdx.x; i < kNV * h3; i += kCloseNT) {
+  for (int i = threadIdx.x; i < kNV * h3; i += blockDim.x) {
     const int k = i / h3, cell = i % h3;
     const int x = cell % h, y = (cell / h) % h, z = cell / (h * h);
     const T* p = u + k * ef3 + 2 * x + ef * (2 * y + ef * (2 * z));
@@ -1139,17 +1138,16 @@ __global__ __launch_bounds__(kCloseNT) void k_restrict(KParams ck, KParams fk, c
   }
 }
 
-// Flux correction: row r = (c, d, s, qc, oa, ob, f, qf).  Face cells
-// (oa + a, ob + b), a, b < e_f/2, of plane qc along axis d of coarse block c
-// are covered by the 2 x 2 fine face cells (2a.., 2b..) of plane qf of fine
-// block f; the coarse cell on the s side of the plane (s = 1: below it, the
-// interface is its + face) takes u + lam (H_c - H_f), or u - lam (H_c - H_f)
-// for s = 0, with lam = dt_c / dh_c and H_f the mean of the four fine fluxes
-// summed ((f00 + f01) + f10) + f11.  One workgroup per row; rows of one pass
-// (one d and s) never share a cell.
+// Flux correction of one row (c, d, s, qc, oa, ob, f, qf) by the calling
+// workgroup.  Face cells (oa + a, ob + b), a, b < e_f/2, of plane qc along
+// axis d of coarse block c are covered by the 2 x 2 fine face cells
+// (2a.., 2b..) of plane qf of fine block f; the coarse cell on the s side of
+// the plane (s = 1: below it, the interface is its + face) takes
+// u + lam (H_c - H_f), or u - lam (H_c - H_f) for s = 0, with lam =
+// dt_c / dh_c and H_f the mean of the four fine fluxes summed
+// ((f00 + f01) + f10) + f11.
 template <typename T>
-__global__ __launch_bounds__(kCloseNT) void k_flux_correct(KParams ck, KParams fk, const int32_t* rows) {
-  const int32_t* r = rows + 8 * (int64_t)blockIdx.x;
+__device__ __forceinline__ void correct_row(const KParams& ck, const KParams& fk, const int32_t* r) {
   const int c = r[0], d = r[1], s = r[2], qc = r[3], oa = r[4], ob = r[5], f = r[6], qf = r[7];
   const bool fin = f >= 0 && f < fk.nblocks, cin = c >= 0 && c < ck.nblocks;
   const int ef = fin ? block_edge(fk, f) : 0, ec = cin ? block_edge(ck, c) : 0;
@@ -1164,7 +1162,7 @@ __global__ __launch_bounds__(kCloseNT) void k_flux_correct(KParams ck, KParams f
   T* u = const_cast<T*>(interior_of<T>(ck, ck.uout, c, ec));
   const T* Hc = record_of<T>(ck, c, ec) + (int64_t)(d * (ec / kPatch + 1) + qc) * kNV * ec * ec;
   const T* Hf = record_of<T>(fk, f, ef) + (int64_t)(d * (ef / kPatch + 1) + qf) * kNV * ef * ef;
-  double dt = ck.d_dt ? ck.d_dt[c] : ck.dt, dh = ck.d_dh ? ck.d_dh[c] : ck.dh;
+  const double dt = ck.d_dt ? ck.d_dt[c] : ck.dt, dh = ck.d_dh ? ck.d_dh[c] : ck.dh;
   const T lam = (T)(dt / dh);
   const T quarter = T(0.25);
   // cell strides along d and along the face axes (the higher-numbered first)
@@ -1172,13 +1170,61 @@ __global__ __launch_bounds__(kCloseNT) void k_flux_correct(KParams ck, KParams f
   const int dhi = d == 0 ? 2 : d == 1 ? 2 : 1, dlo = d == 0 ? 1 : 0;
   const int i_d = s ? kPatch * qc - 1 : kPatch * qc;
   const int64_t ec3 = (int64_t)ec * ec * ec;
-  for (int i = threadIdx.x; i < kNV * h * h; i += kCloseNT) {
+  for (int i = threadIdx.x; i < kNV * h * h; i += blockDim.x) {
     const int k = i / (h * h), a = (i / h) % h, b = i % h;
     const T* F = Hf + k * ef * ef + (2 * a) * ef + 2 * b;
     const T hf = (((F[0] + F[1]) + F[ef]) + F[ef + 1]) * quarter;
     const T t = Hc[k * ec * ec + (oa + a) * ec + (ob + b)] - hf;
     T* p = u + k * ec3 + i_d * st[d] + (oa + a) * st[dhi] + (ob + b) * st[dlo];
     *p = s ? *p + lam * t : *p - lam * t;
+  }
+}
+
+// One workgroup per restriction row.
+template <typename T>
+__global__ __launch_bounds__(kCloseNT) void k_restrict(KParams ck, KParams fk, const int32_t* rows) {
+  restrict_row<T>(ck, fk, rows + 5 * (int64_t)blockIdx.x);
+}
+
+// One workgroup per face row of one pass (rows of one pass never share a
+// cell).
+template <typename T>
+__global__ __launch_bounds__(kCloseNT) void k_flux_correct(KParams ck, KParams fk, const int32_t* rows) {
+  correct_row<T>(ck, fk, rows + 8 * (int64_t)blockIdx.x);
+}
+
+// The closing of a level pair in one launch: workgroups [0, nr) restrict one
+// row each; workgroup nr + g applies the face rows [start[g], start[g+1]) of
+// one coarse block in pass order, with a barrier wherever the pass changes,
+// so that a cell on several interfaces takes its corrections in the order
+// x-, x+, y-, y+, z-, z+.  A group whose rows name different coarse blocks,
+// or whose range leaves [0, nf), is skipped and counted as non-physical.
+template <typename T>
+__global__ __launch_bounds__(kCloseNT) void k_close_level(KParams ck, KParams fk,
+                                                          const int32_t* rrows, int nr,
+                                                          const int32_t* frows, int nf,
+                                                          const int32_t* start) {
+  if ((int)blockIdx.x < nr) {
+    restrict_row<T>(ck, fk, rrows + 5 * (int64_t)blockIdx.x);
+    return;
+  }
+  const int g = blockIdx.x - nr;
+  const int lo = start[g], hi = start[g + 1];
+  bool ok = lo >= 0 && lo <= hi && hi <= nf;
+  for (int r = lo; ok && r < hi; ++r) ok = frows[8 * (int64_t)r] == frows[8 * (int64_t)lo];
+  if (!ok) {
+    if (threadIdx.x == 0) atomicAdd(&ck.counters[1], 1ull);
+    return;
+  }
+  int prev = -1;
+  for (int r = lo; r < hi; ++r) {
+    const int32_t* row = frows + 8 * (int64_t)r;
+    const int pass = 2 * row[1] + row[2];
+    if (pass != prev) {
+      __syncthreads();  // the previous pass's corrections are in place
+      prev = pass;
+    }
+    correct_row<T>(ck, fk, row);
   }
 }
 
@@ -1363,6 +1409,20 @@ hipError_t launch_restrict(int dtype, const KParams& ck, const KParams& fk, cons
   if (nrows <= 0) return hipSuccess;
   if (dtype == 1) hipLaunchKernelGGL((k_restrict<float>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
   else hipLaunchKernelGGL((k_restrict<double>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_close_level(int dtype, const KParams& ck, const KParams& fk,
+                              const int32_t* rrows, int nr, const int32_t* frows, int nf,
+                              const int32_t* start, int ngroups, hipStream_t s) {
+  const int grid = nr + ngroups;
+  if (grid <= 0) return hipSuccess;
+  if (dtype == 1)
+    hipLaunchKernelGGL((k_close_level<float>), dim3(grid), dim3(kCloseNT), 0, s, ck, fk, rrows, nr,
+                       frows, nf, start);
+  else
+    hipLaunchKernelGGL((k_close_level<double>), dim3(grid), dim3(kCloseNT), 0, s, ck, fk, rrows, nr,
+                       frows, nf, start);
   return hipGetLastError();
 }
 

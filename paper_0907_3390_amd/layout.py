@@ -327,6 +327,21 @@ def closing_tables(patches, base: int, locate):
     return out
 
 
+def group_face_rows(face_rows):
+    """Face rows regrouped for tvd_close_level: sorted by coarse block, then
+    pass 2d + s, then fine block; returns (rows int32 [F, 8], start int32
+    [G + 1]) with group g = rows[start[g]:start[g+1]] naming one coarse
+    block."""
+    fr = np.asarray(face_rows, dtype=np.int32).reshape(-1, 8)
+    if len(fr) == 0:
+        return fr.copy(), np.zeros(1, dtype=np.int32)
+    order = np.lexsort((fr[:, 6], 2 * fr[:, 1] + fr[:, 2], fr[:, 0]))
+    rows = np.ascontiguousarray(fr[order])
+    cut = np.nonzero(np.diff(rows[:, 0]))[0] + 1
+    start = np.concatenate([[0], cut, [len(rows)]]).astype(np.int32)
+    return rows, start
+
+
 class RefinedLevels:
     """A two-level periodic hierarchy: the coarse level of Nc^3 cells as 8^3
     patches numbered x fastest, and the refined patches ``refined[pz, py, px]``

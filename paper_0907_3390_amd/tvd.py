@@ -41,6 +41,7 @@ EXPORTS = [
     "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
     "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
+    "tvd_close_level",
 ]
 
 
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH):
         "tvd_restrict": (ctypes.c_int, [vp, bp, vp, bp, vp, vp, i32, vp]),
         "tvd_flux_correct": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), vp]),
+        "tvd_close_level": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp, vp, i32, vp, i32,
+                                           vp, i32, vp]),
         "tvd_variant_count": (ctypes.c_int, []),
         "tvd_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 4),
         "tvd_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
@@ -221,6 +224,19 @@ class Context:
         st = self.lib.tvd_flux_correct(self.h, coarse.ref, _ptr(u_coarse), _ptr(coarse_flux),
                                        _ptr(coarse_flux_off), fine.ref, _ptr(fine_flux),
                                        _ptr(fine_flux_off), _ptr(rows), pc, _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_close_level(self, coarse: Batch, u_coarse, coarse_flux, coarse_flux_off, fine: Batch,
+                        u_fine, fine_flux, fine_flux_off, restrict_rows, face_rows, face_start,
+                        stream=None, check: bool = True):
+        nr = 0 if restrict_rows is None else int(restrict_rows.shape[0])
+        nf = 0 if face_rows is None else int(face_rows.shape[0])
+        ng = 0 if face_start is None else int(face_start.shape[0]) - 1
+        st = self.lib.tvd_close_level(self.h, coarse.ref, _ptr(u_coarse), _ptr(coarse_flux),
+                                      _ptr(coarse_flux_off), fine.ref, _ptr(u_fine),
+                                      _ptr(fine_flux), _ptr(fine_flux_off), _ptr(restrict_rows),
+                                      nr, _ptr(face_rows), nf, _ptr(face_start), ng,
+                                      _stream(stream))
         return self._check(st) if check else st
 
     def tvd_max_signal_speed(self, batch: Batch, u, layout: int, gamma: float, smax,

@@ -225,6 +225,39 @@ def test_flux_correct_bitwise(ctx, dtype, n):
     assert not np.array_equal(got, coarse)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [8, 16])
+def test_close_level_matches_separate_calls(ctx, dtype, n):
+    """The one-launch closing of a level pair gives the bits of restriction
+    followed by the six correction passes (seeded states and records)."""
+    note(f"one-launch closing dtype={dtype} n={n}")
+    Nc = 32
+    L = layout.RefinedLevels(Nc, _refined(), n)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    r = wl.rng(95 + n)
+    coarse = layout.grid_to_blocks(r.lognormal(size=(5, Nc, Nc, Nc)).astype(npd), 8)
+    fine = r.lognormal(size=(L.fine.n_blocks, 5, n, n, n)).astype(npd)
+    crec = r.standard_normal((L.coarse.n_blocks, layout.flux_record_size(8))).astype(npd)
+    frec = r.standard_normal((L.fine.n_blocks, layout.flux_record_size(n))).astype(npd)
+    rr, fr, count = L.tables()
+    gr, gs = layout.group_face_rows(fr)
+    code = tvd.dtype_code(dtype)
+    cb = tvd.Batch(code, L.coarse.n_blocks, 8, dt=2e-3, dh=1.0 / Nc)
+    fb = tvd.Batch(code, L.fine.n_blocks, n, dt=2e-3, dh=0.5 / Nc)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    f_dev, c_rec, f_rec = dev(fine).reshape(-1), dev(crec).reshape(-1), dev(frec).reshape(-1)
+    a = dev(coarse).reshape(-1)
+    b = a.clone()
+    ctx.tvd_read_flags()
+    ctx.tvd_restrict(cb, a, fb, f_dev, dev(rr))
+    ctx.tvd_flux_correct(cb, a, c_rec, None, fb, f_rec, None, dev(fr), count)
+    ctx.tvd_close_level(cb, b, c_rec, None, fb, f_dev, f_rec, None, dev(rr), dev(gr), dev(gs))
+    torch.cuda.synchronize()
+    assert ctx.tvd_read_flags()[2] == 0
+    assert torch.equal(a, b)
+    assert not torch.equal(b, dev(coarse).reshape(-1))
+
+
 def _device_two_level_step(ctx, L, coarse, fine_blocks, dt, order, dtype):
     """The two-level step on the device: periodic sibling ghost fill of the
     coarse patches, coarse-fine ghost fill of the fine blocks (from the coarse
@@ -315,52 +348,80 @@ def _hierarchy_sums(ml, blocks, n, leaf_only):
     return out[0] if leaf_only else out
 
 
-def test_multilevel_closing_conserves_full_size(ctx):
-    """The full multi-level hierarchy (128^3 base, levels 0-3) as 8^3 FP64
-    patches in one flux-recording launch with one dt on every level, then
-    restriction and flux correction level pair by level pair, finest first:
-    the leaf totals are conserved to round-off, and the root level's total
-    equals the leaf total after restriction.  Without the correction the
-    totals drift by orders of magnitude more."""
-    note("multi-level closing, full size, fp64 patches")
-    ml = wl.multilevel()
-    nb = len(ml.patches)
-    note(f"  {nb} patches per level {np.bincount(ml.levels).tolist()}")
-    tabs = ml.closing(8)
-    code = tvd.TVD_F64
-    u_in = torch.from_numpy(np.ascontiguousarray(ml.ghosted)).cuda().reshape(-1)
-    interior = np.ascontiguousarray(ml.ghosted[:, :, 3:-3, 3:-3, 3:-3])
+@pytest.fixture(scope="module")
+def hierarchy():
+    return wl.multilevel()
+
+
+@pytest.mark.parametrize("mode", ["fp64_patches", "fp32_groups"])
+def test_multilevel_closing_conserves_full_size(ctx, hierarchy, mode):
+    """The full multi-level hierarchy (128^3 base, levels 0-3) in one
+    flux-recording launch with one dt on every level (FP64 8^3 patches,
+    batched; FP32 2^3 patch groups, persistent), then restriction and flux
+    correction level pair by level pair, finest first (one launch per pair):
+    the leaf totals are conserved to round-off (FP32: to its last bits), and
+    the root level's total equals the leaf total after restriction.  Without
+    the closing step the totals drift by orders of magnitude more."""
+    note(f"multi-level closing, full size, {mode}")
+    ml = hierarchy
+    if mode == "fp64_patches":
+        dtype, edge, kernel = torch.float64, 8, tvd.TVD_KERNEL_BATCHED
+        ghosted, dhs = ml.ghosted, ml.dh
+        blocks_of = lambda a: a                                  # patches are the blocks
+    else:
+        dtype, edge, kernel = torch.float32, 16, tvd.TVD_KERNEL_PERSISTENT
+        groups, ghosted, dhs = ml.group_blocks()
+        gidx = {g: i for i, g in enumerate(groups)}
+
+        def blocks_of(a):                                        # groups -> patches
+            out = np.empty((len(ml.patches), 5, 8, 8, 8), dtype=a.dtype)
+            for i, (lev, px, py, pz) in enumerate(ml.patches):
+                g = a[gidx[(lev, px // 2, py // 2, pz // 2)]]
+                out[i] = g[:, 8 * (pz & 1):8 * (pz & 1) + 8, 8 * (py & 1):8 * (py & 1) + 8,
+                           8 * (px & 1):8 * (px & 1) + 8]
+            return out
+    nb = len(dhs)
+    note(f"  {nb} blocks of {edge}^3, patches per level {np.bincount(ml.levels).tolist()}")
+    tabs = ml.closing(edge)
+    code = tvd.dtype_code(dtype)
+    u_in = torch.from_numpy(np.ascontiguousarray(ghosted)).to(dtype).cuda().reshape(-1)
+    interior = np.ascontiguousarray(ghosted[:, :, 3:-3, 3:-3, 3:-3])
+    if dtype == torch.float32:
+        interior = interior.astype(np.float32).astype(np.float64)
     S = oracle.max_signal_speed(np.ascontiguousarray(interior.transpose(1, 0, 2, 3, 4)), GAMMA)
-    dt = 0.5 * float(ml.dh.min()) / S
-    d_dh = torch.from_numpy(np.ascontiguousarray(ml.dh)).cuda()
-    b = tvd.Batch(code, nb, 8, dt=dt, d_dh=d_dh)
-    u_out = torch.zeros(nb * 5 * 512, dtype=torch.float64, device="cuda")
-    flux = torch.zeros(nb * layout.flux_record_size(8), dtype=torch.float64, device="cuda")
+    dt = 0.5 * float(np.min(dhs)) / S
+    d_dh = torch.from_numpy(np.ascontiguousarray(dhs)).cuda()
+    b = tvd.Batch(code, nb, edge, dt=dt, d_dh=d_dh)
+    u_out = torch.zeros(nb * 5 * edge ** 3, dtype=dtype, device="cuda")
+    flux = torch.zeros(nb * layout.flux_record_size(edge), dtype=dtype, device="cuda")
     ctx.tvd_reserve(nb)
     ctx.tvd_read_flags()
-    ctx.tvd_patch_advance_flux(b, u_in, u_out, flux, None, 0, GAMMA, flags=tvd.TVD_KERNEL_BATCHED)
+    ctx.tvd_patch_advance_flux(b, u_in, u_out, flux, None, 0, GAMMA, flags=kernel)
     torch.cuda.synchronize()
-    raw = u_out.cpu().numpy().reshape(nb, 5, 8, 8, 8)
+    raw = u_out.double().cpu().numpy().reshape(nb, 5, edge, edge, edge)
+    dev = lambda a: torch.from_numpy(a).cuda()
     for lev in sorted(tabs, reverse=True):
         rr, fr, count = tabs[lev]
-        ctx.tvd_restrict(b, u_out, b, u_out, torch.from_numpy(rr).cuda())
-        ctx.tvd_flux_correct(b, u_out, flux, None, b, flux, None, torch.from_numpy(fr).cuda(), count)
+        gr, gs = layout.group_face_rows(fr)
+        ctx.tvd_close_level(b, u_out, flux, None, b, u_out, flux, None, dev(rr), dev(gr), dev(gs))
     torch.cuda.synchronize()
     assert ctx.tvd_read_flags()[2] == 0
-    got = u_out.cpu().numpy().reshape(nb, 5, 8, 8, 8)
-    before = _hierarchy_sums(ml, interior, 8, True)
-    scale = _hierarchy_sums(ml, np.abs(interior), 8, True)
+    got = u_out.double().cpu().numpy().reshape(nb, 5, edge, edge, edge)
+    P_in, P_raw, P_got = blocks_of(interior), blocks_of(raw), blocks_of(got)
+    before = _hierarchy_sums(ml, P_in, 8, True)
+    scale = _hierarchy_sums(ml, np.abs(P_in), 8, True)
     # the gas starts at rest: momentum is measured against total mass times
     # the signal speed
     scale[1:4] = scale[0] * S
-    after = _hierarchy_sums(ml, got, 8, True)
-    leak = _hierarchy_sums(ml, raw, 8, True)
+    after = _hierarchy_sums(ml, P_got, 8, True)
+    leak = _hierarchy_sums(ml, P_raw, 8, True)
     rel = np.abs(after - before) / scale
     rel_raw = np.abs(leak - before) / scale
     note(f"  leaf total change / scale {rel.max():.1e} (without the closing step {rel_raw.max():.1e})")
-    assert np.all(rel <= 1e-12)
-    assert rel_raw[0] > 1e3 * max(rel[0], 1e-16)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    assert np.all(rel <= tol)
+    assert rel_raw[0] > (1e3 if dtype == torch.float64 else 10.0) * max(rel[0], 1e-16)
     # the root level covers the whole box: after restriction its total is
     # the leaf total
-    root = _hierarchy_sums(ml, got, 8, False)[0]
-    assert np.all(np.abs(root - after) <= 1e-12 * scale)
+    root = _hierarchy_sums(ml, P_got, 8, False)[0]
+    assert np.all(np.abs(root - after) <= tol * scale)

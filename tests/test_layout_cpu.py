@@ -134,3 +134,20 @@ def test_refined_levels_sibling_table():
             rx, ry, rz = r % 3 - 1, (r // 3) % 3 - 1, r // 9 - 1
             o = ((fo[b][0] + 8 * rz) % 64, (fo[b][1] + 8 * ry) % 64, (fo[b][2] + 8 * rx) % 64)
             assert L.fine.nbr[b, r] == pos.get(o, -1)
+
+
+def test_group_face_rows():
+    ref = _L_refined()
+    L = layout.RefinedLevels(32, ref, 8)
+    _, fr, _ = L.tables()
+    rows, start = layout.group_face_rows(fr)
+    assert sorted(map(tuple, rows.tolist())) == sorted(map(tuple, fr.tolist()))
+    assert start[0] == 0 and start[-1] == len(rows) and np.all(np.diff(start) > 0)
+    seen = set()
+    for g in range(len(start) - 1):
+        grp = rows[start[g]:start[g + 1]]
+        assert np.all(grp[:, 0] == grp[0, 0]) and grp[0, 0] not in seen
+        seen.add(grp[0, 0])
+        assert np.all(np.diff(2 * grp[:, 1] + grp[:, 2]) >= 0)
+    r0, s0 = layout.group_face_rows(np.zeros((0, 8), np.int32))
+    assert len(r0) == 0 and s0.tolist() == [0]
