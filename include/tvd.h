@@ -3,7 +3,7 @@
  * batch of ghosted cubic blocks of cells by one step of GAMER's dimensionally
  * split relaxing TVD scheme for the Euler equations (Schive, Tsai & Chiueh,
  * "GAMER: a GPU-Accelerated Adaptive Mesh Refinement Code for Astrophysics",
- * Sec. 2.2, Sec. 3.1 and Sec. 3.3).
+ * Sec. 2.2, Sec. 3.1 and Sec. 3.4).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -215,7 +215,7 @@ int tvd_max_signal_speed(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u,
                          double *d_smax, void *stream);
 
 /*
- * Time step from a signal speed (Eq. CFL with Courant number cfl, Sec. 3.3):
+ * Time step from a signal speed (Eq. CFL with Courant number cfl, Sec. 3.4):
  * d_dt_out[b] = cfl * dh_b / d_smax[0] for every block, on the device, so
  * that the next advance can read it through batch->d_dt without a host
  * round trip.

@@ -21,7 +21,7 @@
  *   Sec. 2.2 (last paragraphs)    dimensional splitting, forward xyz /
  *                                 backward zyx, seven-point stencil, three
  *                                 ghost zones
- *   Eq.  (CFL), Sec. 3.3          maximum signal speed for the time step
+ *   Eq.  (CFL), Sec. 3.4          maximum signal speed for the time step
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes):

@@ -1,10 +1,15 @@
-// HIP kernels for gfx950: the batched and the plain relaxing-TVD advance,
-// the CFL signal speed, compensated conservation sums, their finalisation,
-// the device time step and the sibling ghost-zone fill.
+// HIP kernels for gfx950: the batched, persistent and plain relaxing-TVD
+// advance (optionally writing patch-boundary flux records), the CFL signal
+// speed, compensated conservation sums, their finalisation, the device time
+// step, the sibling and coarse-fine ghost-zone fills, and the closing step of
+// a level pair (restriction and coarse-fine flux correction).
 //
 // Scheme: Schive, Tsai & Chiueh, GAMER, Sec. 2.2 (equations cited in
-// tvd_device.hpp); signal speed Eq. (CFL), Sec. 3.3.
+// tvd_device.hpp); signal speed Eq. (CFL), Sec. 3.4; AMR ghost zones and the
+// closing step, Secs. 2.1, 2.2 and 3.1.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "tvd_device.hpp"
 #include "tvd_internal.hpp"
@@ -1086,7 +1091,7 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
 // region outside its blocks is skipped and its cells are counted as
 // non-physical.
 
-constexpr int kCloseNT = 128;
+constexpr int kCloseNT = 256;
 
 template <typename T>
 __device__ __forceinline__ const T* interior_of(const KParams& k, const void* base, int b, int e) {
@@ -1121,6 +1126,38 @@ __device__ __forceinline__ void restrict_row(const KParams& ck, const KParams& f
   const int h3 = h * h * h;
   const int64_t ef3 = (int64_t)ef * ef * ef, ec3 = (int64_t)ec * ec * ec;
   const T eighth = T(0.125);
+  if ((reinterpret_cast<uintptr_t>(u) & 15) == 0) {
+    // 16-byte loads along x: W = 16 / sizeof(T) children per row load,
+    // W / 2 coarse cells per item; same sums in the same order
+    constexpr int W = 16 / sizeof(T), O = W / 2;
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const int hx = h / O;
+    const int items = kNV * h * h * hx;
+    for (int i = threadIdx.x; i < items; i += blockDim.x) {
+      const int k = i / (h * h * hx), rem = i % (h * h * hx);
+      const int xq = rem % hx, y = (rem / hx) % h, z = rem / (hx * h);
+      const T* p = u + k * ef3 + W * xq + ef * (2 * y + ef * (2 * z));
+      T a[W], b[W], cz[W], d[W];
+      *reinterpret_cast<V*>(a) = *reinterpret_cast<const V*>(p);                // dz 0, dy 0
+      *reinterpret_cast<V*>(b) = *reinterpret_cast<const V*>(p + ef);           // dz 0, dy 1
+      *reinterpret_cast<V*>(cz) = *reinterpret_cast<const V*>(p + ef * ef);     // dz 1, dy 0
+      *reinterpret_cast<V*>(d) = *reinterpret_cast<const V*>(p + ef * ef + ef); // dz 1, dy 1
+      T* q = v + k * ec3 + (ox + O * xq) + ec * ((oy + y) + (int64_t)ec * (oz + z));
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        T sum = a[2 * o];
+        sum = sum + a[2 * o + 1];
+        sum = sum + b[2 * o];
+        sum = sum + b[2 * o + 1];
+        sum = sum + cz[2 * o];
+        sum = sum + cz[2 * o + 1];
+        sum = sum + d[2 * o];
+        sum = sum + d[2 * o + 1];
+        q[o] = sum * eighth;
+      }
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < kNV * h3; i += blockDim.x) {
     const int k = i / h3, cell = i % h3;
     const int x = cell % h, y = (cell / h) % h, z = cell / (h * h);
@@ -1193,22 +1230,25 @@ __global__ __launch_bounds__(kCloseNT) void k_flux_correct(KParams ck, KParams f
   correct_row<T>(ck, fk, rows + 8 * (int64_t)blockIdx.x);
 }
 
-// The closing of a level pair in one launch: workgroups [0, nr) restrict one
-// row each; workgroup nr + g applies the face rows [start[g], start[g+1]) of
-// one coarse block in pass order, with a barrier wherever the pass changes,
-// so that a cell on several interfaces takes its corrections in the order
-// x-, x+, y-, y+, z-, z+.  A group whose rows name different coarse blocks,
-// or whose range leaves [0, nf), is skipped and counted as non-physical.
+// The closing of a level pair in one launch: workgroup g < ngroups applies
+// the face rows [start[g], start[g+1]) of one coarse block in pass order,
+// with a barrier wherever the pass changes, so that a cell on several
+// interfaces takes its corrections in the order x-, x+, y-, y+, z-, z+; the
+// workgroups after them restrict one row each.  The face groups come first
+// so that their short dependent chains start early and overlap the
+// bandwidth-bound restriction.  A group whose rows name different coarse
+// blocks, or whose range leaves [0, nf), is skipped and counted as
+// non-physical.
 template <typename T>
 __global__ __launch_bounds__(kCloseNT) void k_close_level(KParams ck, KParams fk,
-                                                          const int32_t* rrows, int nr,
+                                                          const int32_t* rrows, int ngroups,
                                                           const int32_t* frows, int nf,
                                                           const int32_t* start) {
-  if ((int)blockIdx.x < nr) {
-    restrict_row<T>(ck, fk, rrows + 5 * (int64_t)blockIdx.x);
+  if ((int)blockIdx.x >= ngroups) {
+    restrict_row<T>(ck, fk, rrows + 5 * (int64_t)(blockIdx.x - ngroups));
     return;
   }
-  const int g = blockIdx.x - nr;
+  const int g = blockIdx.x;
   const int lo = start[g], hi = start[g + 1];
   bool ok = lo >= 0 && lo <= hi && hi <= nf;
   for (int r = lo; ok && r < hi; ++r) ok = frows[8 * (int64_t)r] == frows[8 * (int64_t)lo];
@@ -1418,11 +1458,11 @@ hipError_t launch_close_level(int dtype, const KParams& ck, const KParams& fk,
   const int grid = nr + ngroups;
   if (grid <= 0) return hipSuccess;
   if (dtype == 1)
-    hipLaunchKernelGGL((k_close_level<float>), dim3(grid), dim3(kCloseNT), 0, s, ck, fk, rrows, nr,
-                       frows, nf, start);
+    hipLaunchKernelGGL((k_close_level<float>), dim3(grid), dim3(kCloseNT), 0, s, ck, fk, rrows,
+                       ngroups, frows, nf, start);
   else
-    hipLaunchKernelGGL((k_close_level<double>), dim3(grid), dim3(kCloseNT), 0, s, ck, fk, rrows, nr,
-                       frows, nf, start);
+    hipLaunchKernelGGL((k_close_level<double>), dim3(grid), dim3(kCloseNT), 0, s, ck, fk, rrows,
+                       ngroups, frows, nf, start);
   return hipGetLastError();
 }
 
