@@ -827,8 +827,8 @@ def test_multilevel_batch_one_launch(ctx):
 
 def test_multilevel_full_size_fp32(ctx):
     """The multi-level batch at full size: a 128^3 base (4096 patches) and
-    levels 1-3 around 32 overdensities (19 592 patches in all): one persistent
-    FP32 launch on the patches and on their 2^3 patch groups (2449 blocks of
+    levels 1-3 around 32 overdensities (18 152 patches in all): one persistent
+    FP32 launch on the patches and on their 2^3 patch groups (2269 blocks of
     16^3), and the plain FP64 kernel per level, against the oracle."""
     note("multi-level batch, full size")
     ml = wl.multilevel()
