@@ -20,6 +20,10 @@ Chiueh (GAMER, 2010) it follows:
 * ``oracle.ghosts``    Sec. 2.2 coarse-fine ghost zones: sibling copy, else
                        linear interpolation with the Min-Mod limiter from one
                        level coarser (numpy).
+* ``oracle.closing``   Sec. 2.1 step 3 and Sec. 3.1 closing step: restriction
+                       and coarse-fine flux correction (numpy).
+* ``oracle.poisson``   Sec. 2.3 and Sec. 3.2: red-black SOR for the Poisson
+                       equation on patch groups (numpy).
 """
 from __future__ import annotations
 
