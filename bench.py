@@ -32,7 +32,9 @@ Reported (one JSON line on stdout):
   patch groups, and as plain FP64 launches level by level;
 * closing_step: on the same hierarchy with one dt, the advance writing
   patch-boundary flux records, and the restriction and coarse-fine flux
-  correction of every level pair.
+  correction of every level pair;
+* poisson_sor: red-black SOR for the Poisson equation on 4096 patch groups,
+  50 fixed iterations and solves to the stopping rule, FP32 and FP64.
 """
 from __future__ import annotations
 
@@ -395,6 +397,67 @@ def run_closing(ctx, ml, reps=10):
     return res
 
 
+def run_poisson(ctx, reps=5, n_groups=4096):
+    """Red-black SOR for the Poisson equation on patch groups (18^3 potential,
+    16^3 density, Dirichlet ghosts): n_groups groups (the 2^3 patch groups of
+    a 256^3 domain), lognormal densities, seeded.  Timed with HIP events:
+    50 iterations per group (fixed count), and solves run to the stopping
+    rule (optimal omega, 16 unit roundoffs), FP32 and FP64.  A cell update
+    moves 4 LDS values (three neighbour reads and the write; the other three
+    operands are in registers), which bounds the kernel: the LDS peak is
+    128 B per clock per CU."""
+    import torch
+    from paper_0907_3390_amd import tvd
+    r = np.random.default_rng(SEED + 7)
+    rho = r.lognormal(0.0, 1.0, size=(n_groups, 16, 16, 16))
+    c = (np.arange(-1, 17) + 0.5) / 16
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    phi = (np.sin(2 * x) * np.cos(3 * y) + 0.5 * z * z)[None] * r.uniform(0.5, 2.0, (n_groups, 1, 1, 1))
+    lds_peak = 256 * 128 * 2.4e9
+    res = {"workload": f"{n_groups} patch groups (16^3 + 1 ghost layer), lognormal density (seed {SEED + 7}), "
+                       "Dirichlet ghosts from a smooth potential, G = 1, dh = 1/256"}
+    stream = torch.cuda.current_stream()
+    for name, dtype in (("fp32", torch.float32), ("fp64", torch.float64)):
+        code = tvd.dtype_code(dtype)
+        es = 4 if dtype == torch.float32 else 8
+        p_in = torch.from_numpy(phi).to(dtype).cuda().reshape(-1)
+        rh = torch.from_numpy(rho).to(dtype).cuda().reshape(-1)
+        out = torch.zeros(n_groups * 4096, dtype=dtype, device="cuda")
+        iters = torch.zeros(n_groups, dtype=torch.int32, device="cuda")
+
+        def timed(**kw):
+            ctx.tvd_poisson_sor(code, n_groups, p_in, rh, out, 1.0, 1.0 / 256, iters=iters, **kw)
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                ctx.tvd_poisson_sor(code, n_groups, p_in, rh, out, 1.0, 1.0 / 256, iters=iters, **kw)
+            e.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(e) / reps
+
+        ms_fixed = timed(min_iter=50, max_iter=50)
+        updates = n_groups * 4096 * 50
+        ms_conv = timed(max_iter=1000)
+        it = iters.cpu().numpy()
+        upd_conv = n_groups * 4096 * float(it.sum()) / n_groups
+        res[name] = {
+            "fixed_50_iterations_ms": ms_fixed,
+            "cell_updates_per_s": updates / (ms_fixed * 1e-3),
+            "lds_GBs": updates * 4 * es / (ms_fixed * 1e-3) / 1e9,
+            "lds_frac": updates * 4 * es / (ms_fixed * 1e-3) / lds_peak,
+            "converged_ms": ms_conv, "iterations_min_mean_max": [int(it.min()), float(it.mean()), int(it.max())],
+            "converged_groups_per_s": n_groups / (ms_conv * 1e-3),
+            "converged_cell_updates_per_s": upd_conv / (ms_conv * 1e-3),
+        }
+        log(f"bench: SOR {name}: {res[name]['cell_updates_per_s'] / 1e9:.1f} G cell-updates/s at 50 "
+            f"iterations ({res[name]['lds_frac'] * 100:.0f} % of the LDS peak); to convergence "
+            f"{ms_conv:.3f} ms for {n_groups} groups, {it.mean():.1f} iterations on average")
+        del p_in, rh, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_amr_fill(ctx, reps=20):
     """Coarse-fine ghost fill (sibling copy, else Min-Mod limited linear
     interpolation from the coarser level): a periodic 256^3 coarse level
@@ -522,6 +585,8 @@ def main():
                     help="skip the multi-level (18 152 patches) throughput")
     ap.add_argument("--no-closing", action="store_true",
                     help="skip the closing step (flux records, restriction, flux correction)")
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="skip the red-black SOR Poisson solver on patch groups")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch (4000 mixed boxes) throughput")
     ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
@@ -666,6 +731,10 @@ def main():
         log("bench: closing step on the multi-level hierarchy")
         torch.cuda.empty_cache()
         out["closing_step"] = run_closing(ctx, ml)
+    if not args.no_poisson:
+        log("bench: Poisson SOR on patch groups")
+        torch.cuda.empty_cache()
+        out["poisson_sor"] = run_poisson(ctx)
     if not args.no_uneven:
         log("bench: uneven batch of 4000 boxes")
         torch.cuda.empty_cache()

@@ -385,6 +385,43 @@ int tvd_close_level(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse,
                     int32_t n_restrict, const int32_t *d_face_rows, int32_t n_face_rows,
                     const int32_t *d_face_start, int32_t n_face_groups, void *stream);
 
+/* ---- Poisson equation on patch groups (Sec. 2.3, Sec. 3.2) -------------------- */
+
+/*
+ * Red-black successive overrelaxation for the discrete Poisson equation
+ * (Eq. DiscretePoisson, the 7-point Laplacian) on n_groups patch groups of
+ * 16^3 cells, each with Dirichlet values in a one-cell ghost layer (Sec. 2.3:
+ * refined levels are solved patch by patch with boundary values from the
+ * coarser level; Sec. 3.2: a patch group holds 18^3 potentials and 16^3
+ * densities).  Per iteration, the even cells (x + y + z even, interior
+ * indices 0..15) are updated from the odd ones, then the odd cells from the
+ * updated even ones, each by Eq. (Residual)
+ *   R = (phi_x+1 + phi_y+1 + phi_z+1 + phi_x-1 + phi_y-1 + phi_z-1 - 6 phi) - s,
+ *   s = (4 pi G dh^2) rho   (the factor computed in FP64, rounded once),
+ * and Eq. (SOR) phi <- phi + (omega/6) R, summed in that order in the
+ * batch's precision without contraction.  A group stops after max_iter
+ * iterations, or, once min_iter are done, after the first iteration whose
+ * residual one-norm (the |R| of that iteration's updates, summed in FP64) is
+ * <= tol * (sum |s| + 6 sum |phi|).
+ *   dtype      TVD_F32 or TVD_F64.
+ *   d_phi_in   [n_groups][18][18][18] (x fastest): initial guess inside, the
+ *              Dirichlet values on the ghost layer; read only.
+ *   d_rho      [n_groups][16][16][16] densities.
+ *   d_phi_out  [n_groups][16][16][16] the solution (must not overlap d_phi_in).
+ *   G, dh      gravitational constant and zone size (d_dh: [n_groups] FP64
+ *              zone sizes, or NULL).
+ *   omega      in (0, 2); 0 selects 2 / (1 + sin(pi/17)), the optimum for a
+ *              16^3 Dirichlet box.
+ *   tol        in (0, 1); 0 selects 16 unit roundoffs of the dtype.
+ *   d_iters    optional [n_groups] int32: iterations done per group.
+ *   d_resid    optional [n_groups] FP64: the last residual one-norm.
+ * Asynchronous on stream.
+ */
+int tvd_poisson_sor(tvd_ctx *ctx, int32_t dtype, int32_t n_groups, const void *d_phi_in,
+                    const void *d_rho, void *d_phi_out, double G, double dh, const double *d_dh,
+                    double omega, int32_t min_iter, int32_t max_iter, double tol,
+                    int32_t *d_iters, double *d_resid, void *stream);
+
 /* ---- step sequences as HIP graphs --------------------------------------------- */
 
 typedef struct tvd_graph tvd_graph;

@@ -3,6 +3,7 @@
 // can be made on the host is made before anything is launched.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -500,6 +501,36 @@ int tvd_close_level(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse,
                                          d_face_rows, n_face_rows, d_face_start, n_face_groups,
                                          (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "closing launch");
+  return TVD_OK;
+}
+
+int tvd_poisson_sor(tvd_ctx* ctx, int32_t dtype, int32_t n_groups, const void* d_phi_in,
+                    const void* d_rho, void* d_phi_out, double G, double dh, const double* d_dh,
+                    double omega, int32_t min_iter, int32_t max_iter, double tol,
+                    int32_t* d_iters, double* d_resid, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (dtype != TVD_F32 && dtype != TVD_F64) return fail(ctx, TVD_ERR_INVALID_ARG, "dtype %d", dtype);
+  if (n_groups < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_groups %d", n_groups);
+  if (!(G == G) || G < -1e300 || G > 1e300) return fail(ctx, TVD_ERR_INVALID_ARG, "G %g", G);
+  if (!d_dh && !(dh > 0.0 && dh < 1e300)) return fail(ctx, TVD_ERR_INVALID_ARG, "dh %g", dh);
+  if (omega == 0.0) omega = 2.0 / (1.0 + sin(3.141592653589793 / 17.0));
+  if (!(omega > 0.0 && omega < 2.0)) return fail(ctx, TVD_ERR_INVALID_ARG, "omega %g", omega);
+  if (max_iter < 1 || max_iter > 1000000 || min_iter < 0 || min_iter > max_iter)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "iteration limits %d..%d", min_iter, max_iter);
+  if (tol == 0.0) tol = 16.0 * (dtype == TVD_F32 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
+  if (!(tol > 0.0 && tol < 1.0)) return fail(ctx, TVD_ERR_INVALID_ARG, "tol %g", tol);
+  if (n_groups == 0) return TVD_OK;
+  if (!d_phi_in || !d_rho || !d_phi_out) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  const size_t es = elem_size(dtype);
+  const char* a = (const char*)d_phi_in;
+  const char* b = (const char*)d_phi_out;
+  const size_t la = (size_t)n_groups * 18 * 18 * 18 * es, lb = (size_t)n_groups * 4096 * es;
+  if (a < b + lb && b < a + la) return fail(ctx, TVD_ERR_ALIAS, "phi_in and phi_out overlap");
+  DeviceGuard g(ctx->device);
+  hipError_t e = tvd::launch_sor(dtype == TVD_F32 ? 1 : 2, n_groups, d_phi_in, d_rho, d_phi_out,
+                                 d_dh, dh, G, omega, tol, min_iter, max_iter, d_iters, d_resid,
+                                 (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "SOR launch");
   return TVD_OK;
 }
 

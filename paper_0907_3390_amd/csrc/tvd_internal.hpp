@@ -94,6 +94,11 @@ hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, 
 hipError_t launch_close_level(int dtype, const KParams& ck, const KParams& fk,
                               const int32_t* rrows, int nr, const int32_t* frows, int nf,
                               const int32_t* start, int ngroups, hipStream_t s);
+// Red-black SOR on ngroups patch groups (18^3 potential in, 16^3 density in,
+// 16^3 potential out).
+hipError_t launch_sor(int dtype, int ngroups, const void* phi_in, const void* rho, void* phi_out,
+                      const double* d_dh, double dh, double G, double omega, double tol,
+                      int min_iter, int max_iter, int32_t* iters, double* resid, hipStream_t s);
 
 // Variants compiled into the library.
 int variant_count();
