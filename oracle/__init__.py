@@ -24,6 +24,7 @@ Chiueh (GAMER, 2010) it follows:
                        and coarse-fine flux correction (numpy).
 * ``oracle.poisson``   Sec. 2.3 and Sec. 3.2: red-black SOR for the Poisson
                        equation on patch groups (numpy).
+* ``oracle.gravity``   Sec. 2.3: the self-gravity source operator G (numpy).
 """
 from __future__ import annotations
 
