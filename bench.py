@@ -34,7 +34,8 @@ Reported (one JSON line on stdout):
   patch-boundary flux records, and the restriction and coarse-fine flux
   correction of every level pair;
 * poisson_sor: red-black SOR for the Poisson equation on 4096 patch groups,
-  50 fixed iterations and solves to the stopping rule, FP32 and FP64.
+  50 fixed iterations and solves to the stopping rule, FP32 and FP64;
+* gravity_operator: the self-gravity source operator on the 256^3 state.
 """
 from __future__ import annotations
 
@@ -458,6 +459,42 @@ def run_poisson(ctx, reps=5, n_groups=4096):
     return res
 
 
+def run_gravity(ctx, grid32, reps=20):
+    """The self-gravity operator G on the 256^3 state as 4096 groups of 16^3
+    (FP32, in place), with a seeded potential of one ghost layer per group.
+    HBM-bound: per cell it reads rho, m and e (5 values) and the potential,
+    and writes m and e (4 values); the potential is read with its ghost layer
+    ((18/16)^3 values per cell)."""
+    import torch
+    from paper_0907_3390_amd import layout, tvd
+    n = 16
+    u = torch.from_numpy(layout.grid_to_blocks(grid32, n)).float().cuda().reshape(-1)
+    nb = (N_GRID // n) ** 3
+    phi = torch.from_numpy(np.random.default_rng(SEED + 9).standard_normal((nb, 18, 18, 18))).float().cuda()
+    b = tvd.Batch(tvd.TVD_F32, nb, n, dt=1e-9, dh=1.0 / N_GRID)
+    stream = torch.cuda.current_stream()
+    ctx.tvd_gravity(b, u, phi)
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        ctx.tvd_gravity(b, u, phi)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    cells = N_GRID ** 3
+    alg = cells * 4 * (5 + 4) + nb * 18 ** 3 * 4
+    del u, phi
+    torch.cuda.empty_cache()
+    res = {"workload": "256^3 lognormal state as 4096 groups of 16^3, FP32, seeded potential",
+           "ms": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+           "algorithmic_bytes": alg, "GBs": alg / (ms * 1e-3) / 1e9,
+           "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"bench: gravity operator {ms:.3f} ms ({res['GBs']:.0f} GB/s, "
+        f"{res['hbm_frac'] * 100:.0f} % of 8 TB/s)")
+    return res
+
+
 def run_amr_fill(ctx, reps=20):
     """Coarse-fine ghost fill (sibling copy, else Min-Mod limited linear
     interpolation from the coarser level): a periodic 256^3 coarse level
@@ -735,6 +772,7 @@ def main():
         log("bench: Poisson SOR on patch groups")
         torch.cuda.empty_cache()
         out["poisson_sor"] = run_poisson(ctx)
+        out["gravity_operator"] = run_gravity(ctx, grid32)
     if not args.no_uneven:
         log("bench: uneven batch of 4000 boxes")
         torch.cuda.empty_cache()

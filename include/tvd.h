@@ -422,6 +422,24 @@ int tvd_poisson_sor(tvd_ctx *ctx, int32_t dtype, int32_t n_groups, const void *d
                     double omega, int32_t min_iter, int32_t max_iter, double tol,
                     int32_t *d_iters, double *d_resid, void *stream);
 
+/*
+ * The self-gravity source operator G (Sec. 2.3: accelerations from 3-point
+ * central differences of the potential; Eqs. MomConserve and EnergyConserve
+ * with the flux terms dropped; in the split order xyzGGzyx the two G merge
+ * into one with twice the time step, so pass 2 dt there).  For every
+ * interior cell of every block (uniform edge 8 or 16, interior layout at
+ * the batch's out offsets, updated in place), with dt and dh of the block:
+ *   m_d' = m_d + (a rho)(phi_-d - phi_+d),          a = dt / (2 dh),
+ *   e'   = e + ((s_x + s_y) + s_z) b,  s_d = (m_d + m_d')(phi_-d - phi_+d),
+ *                                                    b = dt / (4 dh),
+ * a and b rounded once from FP64; rho unchanged.  The energy gain is the
+ * work of the time-centred momentum, so the internal energy is unchanged.
+ *   d_phi  [n_blocks][(edge+2)^3] potential with one ghost layer (x fastest),
+ *          e.g. a tvd_poisson_sor input whose interior holds its output.
+ * TVD_ERR_UNSUPPORTED with mixed edges.  Asynchronous on stream.
+ */
+int tvd_gravity(tvd_ctx *ctx, const tvd_batch *batch, void *d_u, const void *d_phi, void *stream);
+
 /* ---- step sequences as HIP graphs --------------------------------------------- */
 
 typedef struct tvd_graph tvd_graph;

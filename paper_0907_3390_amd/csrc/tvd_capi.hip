@@ -504,6 +504,22 @@ int tvd_close_level(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse,
   return TVD_OK;
 }
 
+int tvd_gravity(tvd_ctx* ctx, const tvd_batch* batch, void* d_u, const void* d_phi,
+                void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if (batch->d_edge) return fail(ctx, TVD_ERR_UNSUPPORTED, "the gravity operator takes a uniform edge");
+  if (batch->n_blocks == 0) return TVD_OK;
+  if (!d_u || !d_phi) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if (d_u == d_phi) return fail(ctx, TVD_ERR_ALIAS, "state and potential are one buffer");
+  DeviceGuard g(ctx->device);
+  const tvd::KParams kp = make_params(ctx, batch, nullptr, d_u, 1.0, 0.0);
+  hipError_t e = tvd::launch_gravity(batch->dtype == TVD_F32 ? 1 : 2, kp, d_phi, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "gravity launch");
+  return TVD_OK;
+}
+
 int tvd_poisson_sor(tvd_ctx* ctx, int32_t dtype, int32_t n_groups, const void* d_phi_in,
                     const void* d_rho, void* d_phi_out, double G, double dh, const double* d_dh,
                     double omega, int32_t min_iter, int32_t max_iter, double tol,

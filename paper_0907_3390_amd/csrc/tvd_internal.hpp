@@ -94,6 +94,9 @@ hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, 
 hipError_t launch_close_level(int dtype, const KParams& ck, const KParams& fk,
                               const int32_t* rrows, int nr, const int32_t* frows, int nf,
                               const int32_t* start, int ngroups, hipStream_t s);
+// The self-gravity operator on the interior blocks at kp.uout (uniform edge
+// kp.edge, 8 or 16), potential [nblocks][(edge+2)^3].
+hipError_t launch_gravity(int dtype, const KParams& kp, const void* phi, hipStream_t s);
 // Red-black SOR on ngroups patch groups (18^3 potential in, 16^3 density in,
 // 16^3 potential out).
 hipError_t launch_sor(int dtype, int ngroups, const void* phi_in, const void* rho, void* phi_out,

@@ -1406,6 +1406,43 @@ __global__ __launch_bounds__(kSorNT) void k_sor(SorParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// self-gravity source operator G (Sec. 2.3)
+// ---------------------------------------------------------------------------
+//
+// One thread per interior cell of a uniform-edge batch: accelerations from
+// 3-point central differences of the potential (one ghost layer), momentum
+// m_d + (a rho)(phi_-d - phi_+d) with a = dt/(2 dh), energy
+// e + ((s_x + s_y) + s_z) b with s_d = (m_d + m_d')(phi_-d - phi_+d) and
+// b = dt/(4 dh) (the work of the time-centred momentum, which leaves the
+// internal energy unchanged), a and b rounded once from FP64.  The state is
+// updated in place; density is not touched.  HBM-bound: per cell it reads
+// four state values and the potential and writes four.
+
+constexpr int kGravNT = 256;
+
+template <typename T, int N>
+__global__ __launch_bounds__(kGravNT) void k_gravity(KParams kp, const T* __restrict__ phi) {
+  constexpr int M = N + 2, N3 = N * N * N, M3 = M * M * M;
+  const int64_t i = (int64_t)blockIdx.x * kGravNT + threadIdx.x;
+  if (i >= (int64_t)kp.nblocks * N3) return;
+  const int b = (int)(i / N3), c = (int)(i % N3);
+  const int x = c % N, y = (c / N) % N, z = c / (N * N);
+  T* u = static_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * N3) + c;
+  const T* p = phi + (int64_t)b * M3 + (x + 1) + M * ((y + 1) + M * (z + 1));
+  const double dt = kp.d_dt ? kp.d_dt[b] : kp.dt, dh = kp.d_dh ? kp.d_dh[b] : kp.dh;
+  const T a = (T)(dt / (2.0 * dh)), bq = (T)(dt / (4.0 * dh));
+  const T dpx = p[-1] - p[1], dpy = p[-M] - p[M], dpz = p[-M * M] - p[M * M];
+  const T ar = a * u[0];
+  const T mx = u[N3], my = u[2 * N3], mz = u[3 * N3];
+  const T nx = mx + ar * dpx, ny = my + ar * dpy, nz = mz + ar * dpz;
+  const T sx = (mx + nx) * dpx, sy = (my + ny) * dpy, sz = (mz + nz) * dpz;
+  u[N3] = nx;
+  u[2 * N3] = ny;
+  u[3 * N3] = nz;
+  u[4 * N3] = u[4 * N3] + ((sx + sy) + sz) * bq;
+}
+
+// ---------------------------------------------------------------------------
 // launchers and the variant table
 // ---------------------------------------------------------------------------
 
@@ -1621,6 +1658,20 @@ hipError_t launch_sor(int dtype, int ngroups, const void* phi_in, const void* rh
               resid};
   if (dtype == 1) hipLaunchKernelGGL(k_sor<float>, dim3(ngroups), dim3(kSorNT), 0, s, p);
   else hipLaunchKernelGGL(k_sor<double>, dim3(ngroups), dim3(kSorNT), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_gravity(int dtype, const KParams& kp, const void* phi, hipStream_t s) {
+  const int64_t cells = (int64_t)kp.nblocks * kp.edge * kp.edge * kp.edge;
+  if (cells <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((cells + kGravNT - 1) / kGravNT)), block(kGravNT);
+  if (dtype == 1) {
+    if (kp.edge == 16) hipLaunchKernelGGL((k_gravity<float, 16>), grid, block, 0, s, kp, static_cast<const float*>(phi));
+    else hipLaunchKernelGGL((k_gravity<float, 8>), grid, block, 0, s, kp, static_cast<const float*>(phi));
+  } else {
+    if (kp.edge == 16) hipLaunchKernelGGL((k_gravity<double, 16>), grid, block, 0, s, kp, static_cast<const double*>(phi));
+    else hipLaunchKernelGGL((k_gravity<double, 8>), grid, block, 0, s, kp, static_cast<const double*>(phi));
+  }
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
     "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
-    "tvd_close_level", "tvd_poisson_sor",
+    "tvd_close_level", "tvd_poisson_sor", "tvd_gravity",
 ]
 
 
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
                                            vp, i32, vp]),
         "tvd_poisson_sor": (ctypes.c_int, [vp, i32, i32, vp, vp, vp, dbl, dbl, vp, dbl, i32, i32,
                                            dbl, vp, vp, vp]),
+        "tvd_gravity": (ctypes.c_int, [vp, bp, vp, vp, vp]),
         "tvd_variant_count": (ctypes.c_int, []),
         "tvd_variant_info": (ctypes.c_int, [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int32)] * 4),
         "tvd_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
@@ -248,6 +249,10 @@ class Context:
         st = self.lib.tvd_poisson_sor(self.h, dtype, n_groups, _ptr(phi_in), _ptr(rho),
                                       _ptr(phi_out), G, dh, _ptr(d_dh), omega, min_iter, max_iter,
                                       tol, _ptr(iters), _ptr(resid), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_gravity(self, batch: Batch, u, phi, stream=None, check: bool = True):
+        st = self.lib.tvd_gravity(self.h, batch.ref, _ptr(u), _ptr(phi), _stream(stream))
         return self._check(st) if check else st
 
     def tvd_max_signal_speed(self, batch: Batch, u, layout: int, gamma: float, smax,
