@@ -1302,6 +1302,7 @@ struct SorParams {
 template <typename T>
 __global__ __launch_bounds__(kSorNT) void k_sor(SorParams p) {
   constexpr int N = kSorN, M = kSorM, M3 = M * M * M, N3 = N * N * N;
+  constexpr int CH = sizeof(T) == 4 ? 8 : 1;  // slices whose loads are issued together (FP64: registers are full)
   __shared__ T s[M3];
   __shared__ double red[2][kSorNT / 64];
   const int g = blockIdx.x;
@@ -1334,52 +1335,78 @@ __global__ __launch_bounds__(kSorNT) void k_sor(SorParams p) {
     c0[z] = s[at(x0, y, z - 1)];
     c1[z] = s[at(x0 + 1, y, z - 1)];
   }
-  // reduce one double over the workgroup (every thread gets the sum)
-  auto block_sum = [&](double v, int slot) {
+  // reduce two doubles over the workgroup in one pass (every thread gets
+  // both sums, in the same order)
+  auto block_sum2 = [&](double& a, double& b) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((tid & 63) == 0) red[slot][tid >> 6] = v;
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off);
+      b += __shfl_xor(b, off);
+    }
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = a;
+      red[1][tid >> 6] = b;
+    }
     __syncthreads();
-    double t = 0.0;
+    a = 0.0;
+    b = 0.0;
 #pragma unroll
-    for (int w = 0; w < kSorNT / 64; ++w) t += red[slot][w];
-    return t;
+    for (int w = 0; w < kSorNT / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    __syncthreads();  // read before the next reduction writes
   };
-  src_norm = block_sum(src_norm, 0);
-  __syncthreads();
+  double unused = 0.0;
+  block_sum2(src_norm, unused);
   int it = 0;
   double rnorm = 0.0;
   for (;;) {
     double racc = 0.0;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
+      // slices in chunks of CH: the chunk's LDS neighbours (all of the other
+      // parity, which this half-step never writes) are loaded first, so the
+      // loads overlap instead of each waiting behind the previous slice's
+      // store
 #pragma unroll
-      for (int z = 0; z < N; ++z) {
-        // the cell of this parity in slice z: column 0 if x0 + y + z has it
-        const bool one = ((x0 + y + z + half) & 1) != 0;
-        const int x = x0 + (one ? 1 : 0);
-        const T c = one ? c1[z + 1] : c0[z + 1];
-        // x neighbours: the pair partner from registers, the outer one from LDS
-        const T xin = one ? c0[z + 1] : c1[z + 1];
-        const T xout = s[at(one ? x + 1 : x - 1, y, z)];
-        const T xp1 = one ? xout : xin;
-        const T xm1 = one ? xin : xout;
-        const T yp1 = s[at(x, y + 1, z)];
-        const T ym1 = s[at(x, y - 1, z)];
-        const T zp1 = one ? c1[z + 2] : c0[z + 2];
-        const T zm1 = one ? c1[z] : c0[z];
-        T sum = xp1;
-        sum = sum + yp1;
-        sum = sum + zp1;
-        sum = sum + xm1;
-        sum = sum + ym1;
-        sum = sum + zm1;
-        const T R = (sum - six * c) - (one ? q1[z] : q0[z]);
-        const T v = c + w6 * R;
-        if (one) c1[z + 1] = v;
-        else c0[z + 1] = v;
-        s[at(x, y, z)] = v;
-        racc += (double)(R < T(0) ? -R : R);
+      for (int z0 = 0; z0 < N; z0 += CH) {
+        T xo[CH], yu[CH], yd[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int z = z0 + k;
+          const bool one = ((x0 + y + z + half) & 1) != 0;
+          const int x = x0 + (one ? 1 : 0);
+          xo[k] = s[at(one ? x + 1 : x - 1, y, z)];
+          yu[k] = s[at(x, y + 1, z)];
+          yd[k] = s[at(x, y - 1, z)];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int z = z0 + k;
+          // the cell of this parity in slice z: column 0 if x0 + y + z has it
+          const bool one = ((x0 + y + z + half) & 1) != 0;
+          const int x = x0 + (one ? 1 : 0);
+          const T c = one ? c1[z + 1] : c0[z + 1];
+          // x neighbours: the pair partner from registers, the outer one from LDS
+          const T xin = one ? c0[z + 1] : c1[z + 1];
+          const T xp1 = one ? xo[k] : xin;
+          const T xm1 = one ? xin : xo[k];
+          const T zp1 = one ? c1[z + 2] : c0[z + 2];
+          const T zm1 = one ? c1[z] : c0[z];
+          T sum = xp1;
+          sum = sum + yu[k];
+          sum = sum + zp1;
+          sum = sum + xm1;
+          sum = sum + yd[k];
+          sum = sum + zm1;
+          const T R = (sum - six * c) - (one ? q1[z] : q0[z]);
+          const T v = c + w6 * R;
+          if (one) c1[z + 1] = v;
+          else c0[z + 1] = v;
+          s[at(x, y, z)] = v;
+          racc += (double)(R < T(0) ? -R : R);
+        }
       }
       __syncthreads();
     }
@@ -1388,10 +1415,9 @@ __global__ __launch_bounds__(kSorNT) void k_sor(SorParams p) {
 #pragma unroll
     for (int z = 1; z <= N; ++z)
       pacc += (double)(c0[z] < T(0) ? -c0[z] : c0[z]) + (double)(c1[z] < T(0) ? -c1[z] : c1[z]);
-    rnorm = block_sum(racc, 0);
-    const double pnorm = block_sum(pacc, 1);
-    __syncthreads();  // the partial sums have been read before they are reused
-    if (it >= p.max_iter || (it >= p.min_iter && rnorm <= p.tol * (src_norm + 6.0 * pnorm))) break;
+    block_sum2(racc, pacc);
+    rnorm = racc;
+    if (it >= p.max_iter || (it >= p.min_iter && rnorm <= p.tol * (src_norm + 6.0 * pacc))) break;
   }
   T* out = static_cast<T*>(p.phi_out) + (int64_t)g * N3;
 #pragma unroll
