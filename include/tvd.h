@@ -327,8 +327,9 @@ int tvd_patch_advance_flux(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u
  * order (dz, dy, dx) = 000, 001, .., 111 and multiplied by 1/8.  Rows must
  * not write one cell twice, and no row may read a block another row writes.
  * A row naming a block out of range, an edge other than 8 or 16, or cells
- * outside its blocks is skipped and its cells counted as non-physical.
- * d_coarse and d_fine may be the same buffer (one batch holding both
+ * outside its blocks is skipped and its cells counted as non-physical (once
+ * when its fine block is not a block of the batch).  d_coarse and d_fine may
+ * be the same buffer (one batch holding both
  * levels).  Asynchronous on stream.
  */
 int tvd_restrict(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse, const tvd_batch *fine,
@@ -353,7 +354,8 @@ int tvd_restrict(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse, const tv
  * read and written (interior layout, the coarse batch's out offsets); flux
  * offsets as for tvd_patch_advance_flux.  A row naming a block out of range
  * or cells outside its blocks is skipped and its cells counted as
- * non-physical.  Asynchronous on stream.
+ * non-physical (once when its fine block is not a block of the batch).
+ * Asynchronous on stream.
  */
 int tvd_flux_correct(tvd_ctx *ctx, const tvd_batch *coarse, void *d_coarse,
                      const void *d_coarse_flux, const int64_t *d_coarse_flux_off,
