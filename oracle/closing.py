@@ -16,10 +16,16 @@ with FP64 inputs (or FP32 ones, to mirror a lower-precision run operation by
 operation).
 
 Readings (the paper names the operations, not their arithmetic):
-  * The advance used one time step dt on both levels (the paper's uniform
-    time step), so the fine flux through a coarse face is the mean of the
-    2 x 2 fine face fluxes covering it, summed ((f00 + f01) + f10) + f11 over
-    (a, b) = the face's two axes, the higher-numbered first, then times 1/4.
+  * The fine flux through a coarse face is the mean of the 2 x 2 fine face
+    fluxes covering it, summed ((f00 + f01) + f10) + f11 over (a, b) = the
+    face's two axes, the higher-numbered first, then times 1/4, of the fine
+    records over the coarse step: the fluxes themselves with one dt on both
+    levels (the paper's uniform time step), or, with the fine level
+    sub-cycled in two steps of dt/2, 1/2 H of the first plus 1/2 H of the
+    second (``two_level_step_subcycled``).
+  * Sub-cycling: the second fine step takes its ghost zones from the coarse
+    level half-way through its step, the mean of its old and advanced states
+    (linear interpolation in time), and sweeps in the other order.
   * A coarse cell whose + face along d is a coarse-fine interface gets
     u + lam (H_c - H_f); one whose - face is gets u - lam (H_c - H_f), with
     lam = dt / dh_c: the coarse flux H_c is replaced by H_f in the cell's
@@ -214,6 +220,69 @@ def two_level_step(coarse, fine, refined, n_f: int, dt: float, order: int, gamma
         faces = fine_face_fluxes(f_rec, refined, n_f, Nf)
         new_c = flux_correct(new_c, refined, recs, faces, dt / dh_c)
     return new_c, new_f
+
+
+def lerp(a, b, w: float):
+    """a + w (b - a) in the dtype of a, w rounded to it: linear interpolation
+    in time between two states of a level."""
+    a = np.asarray(a)
+    return a + a.dtype.type(w) * (np.asarray(b) - a)
+
+
+def _advance_grid_fine(coarse, fine, refined, n_f, dt, order, gamma, p_floor):
+    fb = ghosted_fine_blocks(coarse, fine, refined, n_f)
+    f_out, f_rec = advance_ragged(list(fb), order, dt, 0.5 / coarse.shape[1], gamma, p_floor,
+                                  fluxes=True)
+    new_f = fine.copy()
+    for blk, (oz, oy, ox) in zip(f_out, fine_block_origins(refined, n_f)):
+        new_f[:, oz:oz + n_f, oy:oy + n_f, ox:ox + n_f] = blk
+    return new_f, f_rec
+
+
+def two_level_step_subcycled(coarse, fine, refined, n_f: int, dt: float, order: int,
+                             gamma: float, p_floor: float = 0.0, correct: bool = True):
+    """One coarse step of dt with the fine level sub-cycled (Sec. 2.1: the
+    step of level l may be half that of level l-1), FP64.  The coarse level
+    advances by dt (sweep order `order`); the fine level advances twice by
+    dt/2 (orders `order`, then the other), the first time with ghost zones
+    from the coarse level at the old time, the second from the coarse level
+    half-way through its step (the mean of the old and the advanced coarse
+    states, linear in time) and its own siblings after the first sub-step.
+    The fine flux records of the two sub-steps are summed with weight 1/2
+    each (the first written as 1/2 H, the second added as 1/2 H), which makes
+    them the fine fluxes over the coarse step; then restriction and the flux
+    correction as in ``two_level_step``.  Returns (coarse, fine)."""
+    coarse = np.asarray(coarse, dtype=np.float64)
+    fine = np.asarray(fine, dtype=np.float64)
+    N = coarse.shape[1]
+    P = N // PATCH
+    dh_c = 1.0 / N
+    cb = periodic_ghosted_blocks(coarse, PATCH)
+    c_out, c_rec = advance_ragged(list(cb), order, dt, dh_c, gamma, p_floor, fluxes=True)
+    new_c = np.empty_like(coarse)
+    recs = np.empty((P, P, P) + c_rec[0].shape)
+    i = 0
+    for pz in range(P):
+        for py in range(P):
+            for px in range(P):
+                new_c[:, PATCH * pz:PATCH * pz + PATCH, PATCH * py:PATCH * py + PATCH,
+                      PATCH * px:PATCH * px + PATCH] = c_out[i]
+                recs[pz, py, px] = c_rec[i]
+                i += 1
+    half = 0.5
+    f1, r1 = _advance_grid_fine(coarse, fine, refined, n_f, dt * half, order, gamma, p_floor)
+    c_half = lerp(coarse, new_c, half)
+    f2, r2 = _advance_grid_fine(c_half, f1, refined, n_f, dt * half, 1 - order, gamma, p_floor)
+    f_rec = [half * a + half * b for a, b in zip(r1, r2)]
+    for pz, py, px in refined_patches(refined):
+        s = 2 * PATCH
+        new_c[:, PATCH * pz:PATCH * pz + PATCH, PATCH * py:PATCH * py + PATCH,
+              PATCH * px:PATCH * px + PATCH] = restrict(
+            f2[:, s * pz:s * pz + s, s * py:s * py + s, s * px:s * px + s])
+    if correct:
+        faces = fine_face_fluxes(f_rec, refined, n_f, 2 * N)
+        new_c = flux_correct(new_c, refined, recs, faces, dt / dh_c)
+    return new_c, f2
 
 
 def leaf_sums(coarse, fine, refined):

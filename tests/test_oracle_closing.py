@@ -11,7 +11,9 @@ conservation law they exist for, not against their own formulas:
 * the correction touches exactly the coarse cells that share a face with a
   refined patch, and a uniform state is left unchanged;
 * the masked ghost fill agrees with the box fill of the coarse-fine ghost
-  zones where both apply.
+  zones where both apply;
+* with the fine level sub-cycled (two steps of dt/2) and its flux records
+  summed with weight 1/2, the leaf totals are again conserved to round-off.
 Planted mistakes (the correction's sign, the 1/4 of the fine mean, the coarse
 flux of the other face, a restriction from one child) each fail one of these.
 """
@@ -102,6 +104,36 @@ def test_two_level_step_conserves_leaf_totals(n_f, order):
     for k in range(5):
         tot = math.fsum(c1[k].ravel())
         assert abs(tot - after[k]) <= 1e-13 * scale[k]
+
+
+@pytest.mark.parametrize("n_f", [8, 16])
+def test_subcycled_step_conserves_leaf_totals(n_f):
+    """With the fine level sub-cycled (two steps of dt/2, ghosts from the
+    coarse level at the old time and half-way), the time-weighted fine flux
+    records make the correction exactly conservative again; without it the
+    coarse-fine faces leak.  The result differs from the one-dt step."""
+    N = 32
+    coarse, fine = _two_level_state(N, seed=60 + n_f)
+    refined = _refined_L()
+    dt = 0.25 / N
+    before = closing.leaf_sums(coarse, fine, refined)
+    scale = closing.leaf_sums(np.abs(coarse), np.abs(fine), refined)
+    c1, f1 = closing.two_level_step_subcycled(coarse, fine, refined, n_f, dt, 0, G53)
+    after = closing.leaf_sums(c1, f1, refined)
+    assert np.all(np.abs(after - before) <= 1e-13 * scale), (after - before) / scale
+    c0, f0 = closing.two_level_step_subcycled(coarse, fine, refined, n_f, dt, 0, G53, correct=False)
+    leak = np.abs(closing.leaf_sums(c0, f0, refined) - before) / scale
+    assert leak[0] > 1e-9 and leak[4] > 1e-9, leak
+    cu, fu = closing.two_level_step(coarse, fine, refined, n_f, dt, 0, G53)
+    assert not np.allclose(fu, f1, rtol=1e-9, atol=0)
+
+
+def test_lerp():
+    a = np.array([1.0, 2.0, -3.0])
+    b = np.array([3.0, 2.0, 5.0])
+    assert np.array_equal(closing.lerp(a, b, 0.5), [2.0, 2.0, 1.0])
+    assert np.array_equal(closing.lerp(a, b, 0.0), a) and np.array_equal(closing.lerp(a, b, 1.0), b)
+    assert closing.lerp(a.astype(np.float32), b.astype(np.float32), 0.5).dtype == np.float32
 
 
 def test_correction_touches_only_interface_cells():
