@@ -306,16 +306,31 @@ int tvd_fill_ghosts_amr(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nb
 
 /*
  * tvd_patch_advance that also writes every block's flux record to d_flux
- * (at d_flux_off[b], or densely when NULL; required with mixed edges).
- * Ghosted input as for tvd_patch_advance; flags AUTO, BATCHED or PERSISTENT
- * (TVD_KERNEL_PLAIN is TVD_ERR_UNSUPPORTED).  The batched kernel runs its
- * default launch variant here whatever the tuner chose.  d_flux must not
- * overlap the state buffers.
+ * (at d_flux_off[b], or densely when NULL; required with mixed edges): each
+ * entry receives w H with w = flux_weight rounded to the dtype, replacing
+ * the entry (accumulate = 0) or added to it (accumulate = 1), so that the
+ * records of a level's sub-steps can be summed with time weights (w = 1/2
+ * for each of two sub-steps of half the coarse step; w = 1, accumulate = 0
+ * gives H itself).  Ghosted input as for tvd_patch_advance; flags AUTO,
+ * BATCHED or PERSISTENT (TVD_KERNEL_PLAIN is TVD_ERR_UNSUPPORTED).  The
+ * batched kernel runs its default launch variant here whatever the tuner
+ * chose.  d_flux must not overlap the state buffers.
  */
 int tvd_patch_advance_flux(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u_in,
                            void *d_u_out, void *d_flux, const int64_t *d_flux_off,
-                           int32_t sweep_order, double gamma, double p_floor, int32_t flags,
-                           double *d_smax, double *d_sums, void *stream);
+                           double flux_weight, int32_t accumulate, int32_t sweep_order,
+                           double gamma, double p_floor, int32_t flags, double *d_smax,
+                           double *d_sums, void *stream);
+
+/*
+ * d_out[i] = d_a[i] + w (d_b[i] - d_a[i]), i < n, in the dtype (w rounded
+ * to it): linear interpolation in time between two states of a level, e.g.
+ * the coarse level half-way through its step for the ghost zones of a fine
+ * sub-step (Sec. 2.1: the time step of level l may be half that of level
+ * l-1).  d_out may be d_a or d_b.  Asynchronous on stream.
+ */
+int tvd_lerp(tvd_ctx *ctx, int32_t dtype, int64_t n, const void *d_a, const void *d_b,
+             void *d_out, double w, void *stream);
 
 /*
  * Restriction (Sec. 2.1: a coarse patch overlaid by its children takes the

@@ -152,6 +152,8 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
   kp.counters = ctx->counters;
   kp.flux = nullptr;
   kp.flux_off = nullptr;
+  kp.flux_w = 1.0;
+  kp.flux_acc = 0;
   return kp;
 }
 
@@ -281,7 +283,8 @@ namespace {
 int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
                  int32_t sweep_order, double gamma, double p_floor, int32_t flags,
                  double* d_smax, double* d_sums, void* stream, const int32_t* d_nbr,
-                 void* d_flux = nullptr, const int64_t* d_flux_off = nullptr) {
+                 void* d_flux = nullptr, const int64_t* d_flux_off = nullptr,
+                 double flux_w = 1.0, int flux_acc = 0) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   int st = check_batch(ctx, batch);
   if (st) return st;
@@ -333,6 +336,8 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
   kp.flux = d_flux;
   kp.flux_off = d_flux_off;
+  kp.flux_w = flux_w;
+  kp.flux_acc = flux_acc;
   const bool gather = d_nbr != nullptr;
   // the flux-recording advance has one variant per (type, edge): the default
   auto variant = [&](int edge) {
@@ -396,12 +401,32 @@ int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
 
 int tvd_patch_advance_flux(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in,
                            void* d_u_out, void* d_flux, const int64_t* d_flux_off,
-                           int32_t sweep_order, double gamma, double p_floor, int32_t flags,
-                           double* d_smax, double* d_sums, void* stream) {
+                           double flux_weight, int32_t accumulate, int32_t sweep_order,
+                           double gamma, double p_floor, int32_t flags, double* d_smax,
+                           double* d_sums, void* stream) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   if (!d_flux) return fail(ctx, TVD_ERR_INVALID_ARG, "d_flux is NULL");
+  if (!(flux_weight == flux_weight) || flux_weight < -1e300 || flux_weight > 1e300)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "flux_weight %g", flux_weight);
+  if (accumulate != 0 && accumulate != 1)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "accumulate %d is neither 0 nor 1", accumulate);
   return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
-                      d_sums, stream, nullptr, d_flux, d_flux_off);
+                      d_sums, stream, nullptr, d_flux, d_flux_off, flux_weight, accumulate);
+}
+
+int tvd_lerp(tvd_ctx* ctx, int32_t dtype, int64_t n, const void* d_a, const void* d_b,
+             void* d_out, double w, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (dtype != TVD_F32 && dtype != TVD_F64) return fail(ctx, TVD_ERR_INVALID_ARG, "dtype %d", dtype);
+  if (n < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n %lld", (long long)n);
+  if (!(w == w) || w < -1e300 || w > 1e300) return fail(ctx, TVD_ERR_INVALID_ARG, "w %g", w);
+  if (n == 0) return TVD_OK;
+  if (!d_a || !d_b || !d_out) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  DeviceGuard g(ctx->device);
+  hipError_t e = tvd::launch_lerp(dtype == TVD_F32 ? 1 : 2, n, d_a, d_b, d_out, w,
+                                  (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "lerp launch");
+  return TVD_OK;
 }
 
 int tvd_restrict(tvd_ctx* ctx, const tvd_batch* coarse, void* d_coarse, const tvd_batch* fine,

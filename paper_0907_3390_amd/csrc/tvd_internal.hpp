@@ -30,6 +30,8 @@ struct KParams {
   unsigned long long* counters;  // [0] floored, [1] non-physical
   void* flux;                    // patch-boundary flux records (null: none)
   const int64_t* flux_off;       // [nblocks] record offsets, or null for dense
+  double flux_w;                 // records receive flux_w * H ...
+  int flux_acc;                  // ... added to what they hold (1) or replacing it (0)
 };
 
 // Patch edge: boundary fluxes are recorded on the planes at its multiples.
@@ -97,6 +99,9 @@ hipError_t launch_close_level(int dtype, const KParams& ck, const KParams& fk,
 // The self-gravity operator on the interior blocks at kp.uout (uniform edge
 // kp.edge, 8 or 16), potential [nblocks][(edge+2)^3].
 hipError_t launch_gravity(int dtype, const KParams& kp, const void* phi, hipStream_t s);
+// out[i] = a[i] + w (b[i] - a[i]) over n values.
+hipError_t launch_lerp(int dtype, int64_t n, const void* a, const void* b, void* out, double w,
+                       hipStream_t s);
 // Red-black SOR on ngroups patch groups (18^3 potential in, 16^3 density in,
 // 16^3 potential out).
 hipError_t launch_sor(int dtype, int ngroups, const void* phi_in, const void* rho, void* phi_out,

@@ -351,17 +351,21 @@ struct Held {
 
 // A sweep destination that also records the patch-boundary fluxes of its
 // pencil: the flux through every interface on a multiple of the patch edge
-// goes to the block's flux record (the closing step's input, Sec. 3.1).  fp
-// is the record entry of this pencil's face cell on plane 0, variable 0 (null
-// for a pencil outside the interior, which records nothing); planes are
-// 5 N^2 apart, variables N^2, in global component order.  off is the first
-// cell of a half pencil: the interface the two halves share is recorded by
-// the first half only.
+// goes to the block's flux record (the closing step's input, Sec. 3.1), as
+// w H, replacing the record's value or (acc) added to it, so that the
+// records of several sub-steps can be summed with time weights.  fp is the
+// record entry of this pencil's face cell on plane 0, variable 0 (null for a
+// pencil outside the interior, which records nothing); planes are 5 N^2
+// apart, variables N^2, in global component order.  off is the first cell
+// of a half pencil: the interface the two halves share is recorded by the
+// first half only.
 template <typename T, int N, int D, class Dst>
 struct FluxTap {
   const Dst& dst;
   T* fp;
   int off;
+  T w;
+  bool acc;
   static constexpr bool kFlux = true;
   __device__ inline void store(int i, const T u[kNV]) const { dst.store(i, u); }
   __device__ inline void flux(int f, const T H[kNV]) const {
@@ -369,19 +373,24 @@ struct FluxTap {
     if (fp != nullptr && g % kPatch == 0 && (f > 0 || off == 0)) {
       T* p = fp + (g / kPatch) * (kNV * N * N);
 #pragma unroll
-      for (int k = 0; k < kNV; ++k) p[gcomp<D>(k) * (N * N)] = H[k];
+      for (int k = 0; k < kNV; ++k) {
+        T* q = p + gcomp<D>(k) * (N * N);
+        const T v = w * H[k];
+        *q = acc ? *q + v : v;
+      }
     }
   }
 };
 
 // dst itself, or dst recording fluxes when FLUX is set.
 template <bool FLUX, typename T, int N, int D, class Dst>
-__device__ __forceinline__ decltype(auto) tap(const Dst& dst, T* fp, int off) {
+__device__ __forceinline__ decltype(auto) tap(const Dst& dst, T* fp, int off, const KParams& kp) {
   if constexpr (FLUX) {
-    return FluxTap<T, N, D, Dst>{dst, fp, off};
+    return FluxTap<T, N, D, Dst>{dst, fp, off, (T)kp.flux_w, kp.flux_acc != 0};
   } else {
     (void)fp;
     (void)off;
+    (void)kp;
     return (dst);
   }
 }
@@ -514,7 +523,7 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
                                    (ORDER == 0 ? c1 : c2) - kG)
                 : nullptr;
       }
-      pencil_sweep<T, N>(src, tap<FLUX, T, N, D0>(dst, fp, 0), cf);
+      pencil_sweep<T, N>(src, tap<FLUX, T, N, D0>(dst, fp, 0, kp), cf);
     }
   }
   __syncthreads();
@@ -537,9 +546,9 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
     T* fp = nullptr;
     if constexpr (FLUX) fp = sweep1_flux(acc.a.c0, acc.a.c2);
     if (active && t < F) {
-      pencil_sweep<T, N>(acc.a, tap<FLUX, T, N, D1>(acc.a, fp, 0), cf);
+      pencil_sweep<T, N>(acc.a, tap<FLUX, T, N, D1>(acc.a, fp, 0, kp), cf);
     } else if (half) {
-      pencil_sweep<T, N / 2>(acc, tap<FLUX, T, N, D1>(held, fp, acc.off), cf);
+      pencil_sweep<T, N / 2>(acc, tap<FLUX, T, N, D1>(held, fp, acc.off, kp), cf);
     }
     __syncthreads();
     if (half) held.flush(acc);
@@ -548,7 +557,7 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
       const LdsPencil1<T, L, D1> acc{S, p % N, p / N};
       T* fp = nullptr;
       if constexpr (FLUX) fp = sweep1_flux(acc.c0, acc.c2);
-      pencil_sweep<T, N>(acc, tap<FLUX, T, N, D1>(acc, fp, 0), cf);
+      pencil_sweep<T, N>(acc, tap<FLUX, T, N, D1>(acc, fp, 0, kp), cf);
     }
   }
   __syncthreads();
@@ -582,11 +591,11 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
         // 16-byte runs along x (along z the lanes' stores already coalesce;
         // FP64 keeps the direct stores, its registers are already full)
         Held<T, N / 2> held;
-        pencil_sweep<T, N / 2>(src, tap<FLUX, T, N, D2>(held, fp, off), cf);
+        pencil_sweep<T, N / 2>(src, tap<FLUX, T, N, D2>(held, fp, off, kp), cf);
         out_pencil(c0, c1).template store_run<N / 2>(off, held.v);
       } else {
         const Shifted<GlobalOut<T, N, D2>> dst{out_pencil(c0, c1), off};
-        pencil_sweep<T, N / 2>(src, tap<FLUX, T, N, D2>(dst, fp, off), cf);
+        pencil_sweep<T, N / 2>(src, tap<FLUX, T, N, D2>(dst, fp, off, kp), cf);
       }
     }
   } else {
@@ -596,7 +605,7 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
       T* fp = nullptr;
       if constexpr (FLUX) fp = sweep2_flux(c0, c1);
       const auto dst = out_pencil(c0, c1);
-      pencil_sweep<T, N>(src, tap<FLUX, T, N, D2>(dst, fp, 0), cf);
+      pencil_sweep<T, N>(src, tap<FLUX, T, N, D2>(dst, fp, 0, kp), cf);
     }
   }
   __syncthreads();
@@ -1673,6 +1682,29 @@ hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, 
     hipLaunchKernelGGL((k_flux_correct<float>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
   else
     hipLaunchKernelGGL((k_flux_correct<double>), dim3(nrows), dim3(kCloseNT), 0, s, ck, fk, rows);
+  return hipGetLastError();
+}
+
+__global__ void k_lerp_f32(int64_t n, const float* a, const float* b, float* out, float w) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] + w * (b[i] - a[i]);
+}
+
+__global__ void k_lerp_f64(int64_t n, const double* a, const double* b, double* out, double w) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = a[i] + w * (b[i] - a[i]);
+}
+
+hipError_t launch_lerp(int dtype, int64_t n, const void* a, const void* b, void* out, double w,
+                       hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (dtype == 1)
+    hipLaunchKernelGGL(k_lerp_f32, grid, block, 0, s, n, static_cast<const float*>(a),
+                       static_cast<const float*>(b), static_cast<float*>(out), (float)w);
+  else
+    hipLaunchKernelGGL(k_lerp_f64, grid, block, 0, s, n, static_cast<const double*>(a),
+                       static_cast<const double*>(b), static_cast<double*>(out), w);
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "tvd_variant_count", "tvd_variant_info", "tvd_set_variant", "tvd_patch_advance_gather",
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
     "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
-    "tvd_close_level", "tvd_poisson_sor", "tvd_gravity",
+    "tvd_close_level", "tvd_poisson_sor", "tvd_gravity", "tvd_lerp",
 ]
 
 
@@ -90,8 +90,9 @@ def load(path: str = LIB_PATH):
         "tvd_read_flags": (ctypes.c_int, [vp, i64p, i64p, vp]),
         "tvd_fill_ghosts": (ctypes.c_int, [vp, bp, vp, vp, vp, vp]),
         "tvd_fill_ghosts_amr": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp, vp]),
-        "tvd_patch_advance_flux": (ctypes.c_int, [vp, bp, vp, vp, vp, vp, i32, dbl, dbl, i32, vp,
-                                                  vp, vp]),
+        "tvd_patch_advance_flux": (ctypes.c_int, [vp, bp, vp, vp, vp, vp, dbl, i32, i32, dbl, dbl,
+                                                  i32, vp, vp, vp]),
+        "tvd_lerp": (ctypes.c_int, [vp, i32, ctypes.c_int64, vp, vp, vp, dbl, vp]),
         "tvd_restrict": (ctypes.c_int, [vp, bp, vp, bp, vp, vp, i32, vp]),
         "tvd_flux_correct": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), vp]),
@@ -206,11 +207,16 @@ class Context:
 
     def tvd_patch_advance_flux(self, batch: Batch, u_in, u_out, flux, flux_off, sweep_order: int,
                                gamma: float, p_floor: float = 0.0, flags: int = TVD_KERNEL_AUTO,
-                               smax=None, sums=None, stream=None, check: bool = True):
+                               smax=None, sums=None, stream=None, check: bool = True,
+                               flux_weight: float = 1.0, accumulate: int = 0):
         st = self.lib.tvd_patch_advance_flux(self.h, batch.ref, _ptr(u_in), _ptr(u_out),
-                                             _ptr(flux), _ptr(flux_off), sweep_order, gamma,
-                                             p_floor, flags, _ptr(smax), _ptr(sums),
-                                             _stream(stream))
+                                             _ptr(flux), _ptr(flux_off), flux_weight, accumulate,
+                                             sweep_order, gamma, p_floor, flags, _ptr(smax),
+                                             _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_lerp(self, dtype: int, n: int, a, b, out, w: float, stream=None, check: bool = True):
+        st = self.lib.tvd_lerp(self.h, dtype, n, _ptr(a), _ptr(b), _ptr(out), w, _stream(stream))
         return self._check(st) if check else st
 
     def tvd_restrict(self, coarse: Batch, u_coarse, fine: Batch, u_fine, rows, stream=None,
