@@ -327,7 +327,7 @@ int tvd_patch_advance_flux(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u
  * to it): linear interpolation in time between two states of a level, e.g.
  * the coarse level half-way through its step for the ghost zones of a fine
  * sub-step (Sec. 2.1: the time step of level l may be half that of level
- * l-1).  d_out may be d_a or d_b.  Asynchronous on stream.
+ * l-1).  d_out may be d_a or d_b; n <= 2^38.  Asynchronous on stream.
  */
 int tvd_lerp(tvd_ctx *ctx, int32_t dtype, int64_t n, const void *d_a, const void *d_b,
              void *d_out, double w, void *stream);
@@ -453,7 +453,8 @@ int tvd_poisson_sor(tvd_ctx *ctx, int32_t dtype, int32_t n_groups, const void *d
  * work of the time-centred momentum, so the internal energy is unchanged.
  *   d_phi  [n_blocks][(edge+2)^3] potential with one ghost layer (x fastest),
  *          e.g. a tvd_poisson_sor input whose interior holds its output.
- * TVD_ERR_UNSUPPORTED with mixed edges.  Asynchronous on stream.
+ * TVD_ERR_UNSUPPORTED with mixed edges; at most 2^38 cells per call.
+ * Asynchronous on stream.
  */
 int tvd_gravity(tvd_ctx *ctx, const tvd_batch *batch, void *d_u, const void *d_phi, void *stream);
 

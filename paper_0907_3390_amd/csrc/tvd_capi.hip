@@ -418,7 +418,8 @@ int tvd_lerp(tvd_ctx* ctx, int32_t dtype, int64_t n, const void* d_a, const void
              void* d_out, double w, void* stream) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   if (dtype != TVD_F32 && dtype != TVD_F64) return fail(ctx, TVD_ERR_INVALID_ARG, "dtype %d", dtype);
-  if (n < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n %lld", (long long)n);
+  if (n < 0 || n > ((int64_t)1 << 38))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "n %lld outside [0, 2^38]", (long long)n);
   if (!(w == w) || w < -1e300 || w > 1e300) return fail(ctx, TVD_ERR_INVALID_ARG, "w %g", w);
   if (n == 0) return TVD_OK;
   if (!d_a || !d_b || !d_out) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
@@ -536,6 +537,8 @@ int tvd_gravity(tvd_ctx* ctx, const tvd_batch* batch, void* d_u, const void* d_p
   if (st) return st;
   if (batch->d_edge) return fail(ctx, TVD_ERR_UNSUPPORTED, "the gravity operator takes a uniform edge");
   if (batch->n_blocks == 0) return TVD_OK;
+  if ((int64_t)batch->n_blocks * batch->edge * batch->edge * batch->edge > ((int64_t)1 << 38))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "more than 2^38 cells in one call");
   if (!d_u || !d_phi) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
   if (d_u == d_phi) return fail(ctx, TVD_ERR_ALIAS, "state and potential are one buffer");
   DeviceGuard g(ctx->device);

@@ -83,3 +83,24 @@ def test_split_sequence_with_gravity_fp64(ctx):
     merr = max(np.abs(got[k] - want[k]).sum() / np.abs(want[0]).sum() for k in (1, 2, 3))
     note(f"  xyzGGzyx relL1 rho/e {err:.1e}, momentum {merr:.1e}")
     assert err <= 1e-12 and merr <= 1e-12
+
+
+def test_gravity_full_size_fp32(ctx):
+    """The bench configuration: the 256^3 lognormal state as 4096 groups of
+    16^3 (FP32) with a seeded potential, one launch; 32 sampled blocks
+    against the oracle, bit for bit, and density untouched everywhere."""
+    note("gravity operator full size (256^3 as 4096 groups, fp32)")
+    n, N = 16, 256
+    g = wl.lognormal(N, seed=320, sigma_ln=1.0).astype(np.float32)
+    u = layout.grid_to_blocks(g, n)
+    B = u.shape[0]
+    phi = np.random.default_rng(321).standard_normal((B, n + 2, n + 2, n + 2)).astype(np.float32)
+    d_u = torch.from_numpy(u).cuda().reshape(-1)
+    b = tvd.Batch(tvd.TVD_F32, B, n, dt=1e-4, dh=1.0 / N)
+    ctx.tvd_gravity(b, d_u, torch.from_numpy(phi).cuda())
+    torch.cuda.synchronize()
+    got = d_u.cpu().numpy().reshape(u.shape)
+    picks = wl.rng(322).choice(B, size=32, replace=False)
+    want = gravity.apply(u[picks], phi[picks], 1e-4, 1.0 / N)
+    assert np.array_equal(got[picks], want)
+    assert np.array_equal(got[:, 0], u[:, 0])
