@@ -352,20 +352,19 @@ struct Held {
 // A sweep destination that also records the patch-boundary fluxes of its
 // pencil: the flux through every interface on a multiple of the patch edge
 // goes to the block's flux record (the closing step's input, Sec. 3.1), as
-// w H, replacing the record's value or (acc) added to it, so that the
+// w H, replacing the record's value or (ACC) added to it, so that the
 // records of several sub-steps can be summed with time weights.  fp is the
 // record entry of this pencil's face cell on plane 0, variable 0 (null for a
 // pencil outside the interior, which records nothing); planes are 5 N^2
 // apart, variables N^2, in global component order.  off is the first cell
 // of a half pencil: the interface the two halves share is recorded by the
 // first half only.
-template <typename T, int N, int D, class Dst>
+template <typename T, int N, int D, bool ACC, class Dst>
 struct FluxTap {
   const Dst& dst;
   T* fp;
   int off;
   T w;
-  bool acc;
   static constexpr bool kFlux = true;
   __device__ inline void store(int i, const T u[kNV]) const { dst.store(i, u); }
   __device__ inline void flux(int f, const T H[kNV]) const {
@@ -375,18 +374,19 @@ struct FluxTap {
 #pragma unroll
       for (int k = 0; k < kNV; ++k) {
         T* q = p + gcomp<D>(k) * (N * N);
-        const T v = w * H[k];
-        *q = acc ? *q + v : v;
+        if constexpr (ACC) *q = *q + w * H[k];
+        else *q = w * H[k];
       }
     }
   }
 };
 
-// dst itself, or dst recording fluxes when FLUX is set.
-template <bool FLUX, typename T, int N, int D, class Dst>
+// dst itself (FLUX = 0), or dst recording fluxes: writing them (1) or adding
+// them to the records (2).
+template <int FLUX, typename T, int N, int D, class Dst>
 __device__ __forceinline__ decltype(auto) tap(const Dst& dst, T* fp, int off, const KParams& kp) {
-  if constexpr (FLUX) {
-    return FluxTap<T, N, D, Dst>{dst, fp, off, (T)kp.flux_w, kp.flux_acc != 0};
+  if constexpr (FLUX != 0) {
+    return FluxTap<T, N, D, FLUX == 2, Dst>{dst, fp, off, (T)kp.flux_w};
   } else {
     (void)fp;
     (void)off;
@@ -425,7 +425,7 @@ struct BlockLds {
 // to draw the next ticket from once the second sweep is done, so that the
 // atomic's latency hides behind the third sweep; the ticket goes to *ticket.
 template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER,
-          bool FLUX = false>
+          int FLUX = 0>
 __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
                                               BlockLds<T, N, PAD>& sm,
                                               unsigned* lookahead = nullptr,
@@ -616,7 +616,7 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
 // With mixed edges each edge has its own launch and a workgroup whose block
 // has the other edge exits at once.
 template <typename T, int N, int ORDER, int NT, int PAD, int SPLIT, bool GATHER,
-          bool FLUX = false>
+          int FLUX = 0>
 __global__ __launch_bounds__(NT) void k_batched(KParams kp) {
   __shared__ BlockLds<T, N, PAD> sm;
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -720,7 +720,7 @@ __device__ __forceinline__ int part_lo(int n, int k) {
   return k * q + (k < r ? k : r);
 }
 
-template <typename T, int ORDER, bool GATHER, bool FLUX = false>
+template <typename T, int ORDER, bool GATHER, int FLUX = 0>
 __global__ __launch_bounds__(512) void k_fused(KParams kp, FusedPlan pl) {
   using B16 = BlockLds<T, 16, kFusedPad16>;
   using B8 = BlockLds<T, 8, kFusedPad8>;
@@ -1516,8 +1516,13 @@ static hipError_t launch_b(int order, bool gather, const KParams& kp, hipStream_
   if (kp.flux) {
     if constexpr (kFluxVariant<T, N, NT, PAD, SPLIT>) {
       if (gather) return hipErrorInvalidValue;
-      if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, false, true>), grid, block, 0, s, kp);
-      else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, false, true>), grid, block, 0, s, kp);
+      if (kp.flux_acc) {
+        if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, false, 2>), grid, block, 0, s, kp);
+        else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, false, 2>), grid, block, 0, s, kp);
+      } else {
+        if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, false, 1>), grid, block, 0, s, kp);
+        else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, false, 1>), grid, block, 0, s, kp);
+      }
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -1572,8 +1577,13 @@ hipError_t launch_fused(int dtype, int order, bool gather, const KParams& kp, co
   const dim3 grid(workgroups), block(512);
   if (kp.flux) {
     if (gather) return hipErrorInvalidValue;
-    if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, false, true>), grid, block, 0, s, kp, pl);
-    else hipLaunchKernelGGL((k_fused<float, 1, false, true>), grid, block, 0, s, kp, pl);
+    if (kp.flux_acc) {
+      if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, false, 2>), grid, block, 0, s, kp, pl);
+      else hipLaunchKernelGGL((k_fused<float, 1, false, 2>), grid, block, 0, s, kp, pl);
+    } else {
+      if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, false, 1>), grid, block, 0, s, kp, pl);
+      else hipLaunchKernelGGL((k_fused<float, 1, false, 1>), grid, block, 0, s, kp, pl);
+    }
   } else if (gather) {
     if (order == 0) hipLaunchKernelGGL((k_fused<float, 0, true>), grid, block, 0, s, kp, pl);
     else hipLaunchKernelGGL((k_fused<float, 1, true>), grid, block, 0, s, kp, pl);
