@@ -296,3 +296,113 @@ def leaf_sums(coarse, fine, refined):
     return np.array([math.fsum(np.asarray(coarse[k], dtype=np.float64)[cm].tolist()) +
                      math.fsum((np.asarray(fine[k], dtype=np.float64)[fm] / 8.0).tolist())
                      for k in range(NVAR)])
+
+
+def _dense_records(recs, refined, n_f: int = PATCH):
+    """Flux records of the blocks over ``refined`` (``fine_block_origins``
+    order, 8^3 patches) scattered to a [pz, py, px] array over the fine
+    level's patch grid; patches that do not exist hold NaN."""
+    P = 2 * np.asarray(refined).shape[0]
+    out = np.full((P, P, P) + np.asarray(recs[0]).shape, np.nan)
+    for rec, (oz, oy, ox) in zip(recs, fine_block_origins(refined, n_f)):
+        out[oz // PATCH, oy // PATCH, ox // PATCH] = rec
+    return out
+
+
+def _close(coarse, fine, refined, coarse_recs, fine_recs, lam, correct):
+    """Restriction of the refined patches from ``fine``, then the flux
+    correction of the coarse level with the fine records (Sec. 2.1, step 3)."""
+    new_c = np.array(coarse, copy=True)
+    s = 2 * PATCH
+    for pz, py, px in refined_patches(refined):
+        new_c[:, PATCH * pz:PATCH * pz + PATCH, PATCH * py:PATCH * py + PATCH,
+              PATCH * px:PATCH * px + PATCH] = restrict(
+            fine[:, s * pz:s * pz + s, s * py:s * py + s, s * px:s * px + s])
+    if correct:
+        faces = fine_face_fluxes(fine_recs, refined, PATCH, fine.shape[1])
+        new_c = flux_correct(new_c, refined, coarse_recs, faces, lam)
+    return new_c
+
+
+def _subcycle(states, refined, lev, c_old, c_new, dt, order, gamma, p_floor, correct):
+    """Level ``lev`` (>= 1) takes two steps of dt/2 inside its parent's step
+    of dt, whose level went from c_old to c_new (before its closing step):
+    the first with ghost zones from c_old, the second from lerp(c_old, c_new,
+    1/2), in sweep orders ``order`` and 1 - order.  After each sub-step the
+    next finer level, if any, does the same inside it and then closes into
+    this one.  Returns this level's records over dt: lerp of the two
+    sub-steps' records at 1/2 (their mean)."""
+    half = 0.5
+    c_half = lerp(c_old, c_new, half)
+    recs = []
+    for k in (0, 1):
+        o = order if k == 0 else 1 - order
+        old = states[lev]
+        new, rec = _advance_grid_fine(c_old if k == 0 else c_half, old, refined[lev - 1], PATCH,
+                                      dt * half, o, gamma, p_floor)
+        if lev + 1 < len(states):
+            fine_recs = _subcycle(states, refined, lev + 1, old, new, dt * half, o, gamma,
+                                  p_floor, correct)
+            new = _close(new, states[lev + 1], refined[lev],
+                         _dense_records(rec, refined[lev - 1]), fine_recs,
+                         dt * half * new.shape[1], correct)
+        states[lev] = new
+        recs.append(rec)
+    return [lerp(a, b, half) for a, b in zip(*recs)]
+
+
+def nested_step_subcycled(states, refined, dt: float, order: int, gamma: float,
+                          p_floor: float = 0.0, correct: bool = True):
+    """One root step of dt on a periodic hierarchy of any depth, every level
+    sub-cycled (Sec. 2.1: the step of level l is half that of level l-1, and
+    a level's update is: advance, let the finer level catch up, correct with
+    it), FP64, 8^3 patches on every level.
+
+    states[l] is level l's state on its whole periodic grid (5, N 2^l, ...),
+    meaningful inside its patches; refined[l] (over level l's patch grid)
+    marks the patches refined into level l+1 (proper nesting assumed).  The
+    root level advances by dt with periodic ghost zones; each finer level as
+    in ``_subcycle`` (recursively); each level is then closed with the next
+    finer one (restriction, then the flux correction with the finer level's
+    records averaged over the step), finest pair first.  Returns the new
+    states."""
+    states = [np.array(s, dtype=np.float64) for s in states]
+    c0 = states[0]
+    N = c0.shape[1]
+    P = N // PATCH
+    cb = periodic_ghosted_blocks(c0, PATCH)
+    c_out, c_rec = advance_ragged(list(cb), order, dt, 1.0 / N, gamma, p_floor, fluxes=True)
+    new0 = np.empty_like(c0)
+    recs0 = np.empty((P, P, P) + c_rec[0].shape)
+    i = 0
+    for pz in range(P):
+        for py in range(P):
+            for px in range(P):
+                new0[:, PATCH * pz:PATCH * pz + PATCH, PATCH * py:PATCH * py + PATCH,
+                     PATCH * px:PATCH * px + PATCH] = c_out[i]
+                recs0[pz, py, px] = c_rec[i]
+                i += 1
+    if len(states) > 1:
+        fine_recs = _subcycle(states, refined, 1, c0, new0, dt, order, gamma, p_floor, correct)
+        new0 = _close(new0, states[1], refined[0], recs0, fine_recs, dt * N, correct)
+    states[0] = new0
+    return states
+
+
+def nested_leaf_sums(states, refined):
+    """Totals of the conserved variables over the leaf cells of a nested
+    hierarchy (cells of existing patches that are not refined; level l's
+    cells weigh 8^-l), summed exactly."""
+    import math
+    L = len(states)
+    exist = np.ones((states[0].shape[1] // PATCH,) * 3, dtype=bool)
+    tot = np.zeros(NVAR)
+    for lev in range(L):
+        leaf = exist & ~refined[lev] if lev + 1 < L else exist
+        m = np.repeat(np.repeat(np.repeat(leaf, PATCH, 0), PATCH, 1), PATCH, 2)
+        w = 8.0 ** -lev
+        for k in range(NVAR):
+            tot[k] += math.fsum((np.asarray(states[lev][k], dtype=np.float64)[m] * w).tolist())
+        if lev + 1 < L:
+            exist = np.repeat(np.repeat(np.repeat(refined[lev], 2, 0), 2, 1), 2, 2)
+    return tot

@@ -411,3 +411,99 @@ class RefinedLevels:
     def tables(self):
         """(restrict_rows, face_rows, pass_count) of the level pair."""
         return closing_tables(self.patches, self.Nc // PATCH, self.locate)[0]
+
+
+class NestedLevels:
+    """A periodic hierarchy of 8^3 patches on any number of levels: level 0
+    is the Nc^3 root grid, numbered x fastest; ``refined[l]`` (a boolean
+    array over level l's patch grid, Nc/8 * 2^l per axis, indexed [pz, py,
+    px]) marks the level-l patches refined into eight children on level l+1.
+    Level l+1 numbers its patches refined parent by refined parent (pz
+    slowest, px fastest), then child by child (z slowest, x fastest).
+
+    Proper nesting (Sec. 2.1) is checked: a refined patch must exist on its
+    level and so must its 26 neighbours (periodic), so that every coarse-fine
+    ghost zone and flux interface has its coarse patches.
+
+    Per level l: blocks[l] (a BlockSet; the sibling table is -1 where the
+    neighbouring patch does not exist on level l), origins[l] [B, 3]
+    (cell corners z, y, x on level l's grid); for l >= 1 also cnbr[l] [B, 27]
+    and corigin[l] [B, 3] for the coarse-fine ghost fill (the level-(l-1)
+    patches around each patch's parent, and the patch's corner in coarse
+    cells inside its parent, x first).  patches and locate describe the
+    octree for closing_tables."""
+
+    def __init__(self, Nc: int, refined):
+        npc = Nc // PATCH
+        if Nc % PATCH:
+            raise ValueError("Nc must be a multiple of 8")
+        self.Nc = Nc
+        self.refined = [np.asarray(r, dtype=bool) for r in refined]
+        self.n_levels = len(self.refined) + 1
+        index = {(px, py, pz): px + npc * (py + npc * pz)
+                 for pz in range(npc) for py in range(npc) for px in range(npc)}
+        self._index = [index]
+        coords = [sorted(index, key=index.get)]
+        for lev, r in enumerate(self.refined):
+            n_l = npc << lev
+            if r.shape != (n_l, n_l, n_l):
+                raise ValueError(f"refined[{lev}] must be ({n_l},)*3")
+            prev = self._index[lev]
+            nxt, cl = {}, []
+            for pz, py, px in (tuple(int(v) for v in q) for q in np.argwhere(r)):
+                if (px, py, pz) not in prev:
+                    raise ValueError(f"level {lev} patch {(px, py, pz)} is refined but does not exist")
+                for rz in (-1, 0, 1):
+                    for ry in (-1, 0, 1):
+                        for rx in (-1, 0, 1):
+                            q = ((px + rx) % n_l, (py + ry) % n_l, (pz + rz) % n_l)
+                            if q not in prev:
+                                raise ValueError(f"level {lev} patch {(px, py, pz)} is refined "
+                                                 f"but its neighbour {q} does not exist "
+                                                 "(proper nesting)")
+                for c in range(8):
+                    ch = (2 * px + (c & 1), 2 * py + (c >> 1 & 1), 2 * pz + (c >> 2))
+                    nxt[ch] = len(cl)
+                    cl.append(ch)
+            self._index.append(nxt)
+            coords.append(cl)
+        self.blocks, self.origins, self.cnbr, self.corigin = [], [], [None], [None]
+        for lev, cl in enumerate(coords):
+            n_l = npc << lev
+            idx = self._index[lev]
+            nbr = np.full((len(cl), 27), -1, dtype=np.int32)
+            for b, (px, py, pz) in enumerate(cl):
+                for rz in (-1, 0, 1):
+                    for ry in (-1, 0, 1):
+                        for rx in (-1, 0, 1):
+                            q = ((px + rx) % n_l, (py + ry) % n_l, (pz + rz) % n_l)
+                            nbr[b, (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)] = idx.get(q, -1)
+            self.blocks.append(BlockSet(np.full(len(cl), PATCH),
+                                        np.full(len(cl), 1.0 / (Nc << lev)), nbr))
+            self.origins.append(np.array([(PATCH * pz, PATCH * py, PATCH * px)
+                                          for px, py, pz in cl], dtype=np.int64).reshape(-1, 3))
+            if lev == 0:
+                continue
+            n_p = npc << (lev - 1)
+            prev = self._index[lev - 1]
+            cnbr = np.empty((len(cl), 27), dtype=np.int32)
+            corigin = np.empty((len(cl), 3), dtype=np.int32)
+            for b, (px, py, pz) in enumerate(cl):
+                par = (px // 2, py // 2, pz // 2)
+                corigin[b] = [PATCH // 2 * (px % 2), PATCH // 2 * (py % 2), PATCH // 2 * (pz % 2)]
+                for rz in (-1, 0, 1):
+                    for ry in (-1, 0, 1):
+                        for rx in (-1, 0, 1):
+                            q = ((par[0] + rx) % n_p, (par[1] + ry) % n_p, (par[2] + rz) % n_p)
+                            cnbr[b, (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)] = prev[q]
+            self.cnbr.append(cnbr)
+            self.corigin.append(corigin)
+        self.patches = [(lev, px, py, pz) for lev, cl in enumerate(coords) for px, py, pz in cl]
+
+    def locate(self, level, px, py, pz):
+        return self._index[level][(px, py, pz)], (0, 0, 0)
+
+    def tables(self):
+        """{level l: (restrict_rows, face_rows, pass_count)} of every pair
+        (l, l+1)."""
+        return closing_tables(self.patches, self.Nc // PATCH, self.locate)

@@ -101,3 +101,25 @@ def test_bad_rows_are_skipped_and_counted(ctx):
         gr_mix[gs[0] + 1, 0] = (gr_mix[gs[0], 0] + 1) % L.coarse.n_blocks
         got, bad = close(rr, gr_mix, gs)
         assert bad == 1
+
+
+def test_empty_inputs_are_no_ops(ctx):
+    """Zero blocks, groups, elements or rows: every entry point returns OK
+    and leaves its buffers as they were."""
+    sentinel = lambda n, dt=torch.float32: torch.full((n,), 7.0, dtype=dt, device="cuda")
+    u, o, f = sentinel(5 * 14 ** 3), sentinel(5 * 512), sentinel(layout.flux_record_size(8))
+    b0 = tvd.Batch(tvd.TVD_F32, 0, 8, dt=1e-3, dh=1.0 / 32)
+    ctx.tvd_patch_advance_flux(b0, u, o, f, None, 0, GAMMA)
+    ctx.tvd_gravity(b0, o, u)
+    a, c = sentinel(64), sentinel(64)
+    ctx.tvd_lerp(tvd.TVD_F32, 0, a, a, c, 0.5)
+    phi, rho, out = sentinel(18 ** 3), sentinel(4096), sentinel(4096)
+    ctx.tvd_poisson_sor(tvd.TVD_F32, 0, phi, rho, out, 1.0, 0.1)
+    b1 = tvd.Batch(tvd.TVD_F32, 1, 8, dt=1e-3, dh=1.0 / 32)
+    uc = sentinel(5 * 512)
+    ctx.tvd_restrict(b1, uc, b1, o, None)
+    ctx.tvd_close_level(b1, uc, f, None, b1, o, f, None, None, None, None)
+    ctx.tvd_flux_correct(b1, uc, f, None, b1, f, None, None, [0] * 6)
+    torch.cuda.synchronize()
+    for t in (u, o, f, a, c, phi, rho, out, uc):
+        assert bool((t == 7.0).all())

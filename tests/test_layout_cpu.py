@@ -151,3 +151,43 @@ def test_group_face_rows():
         assert np.all(np.diff(2 * grp[:, 1] + grp[:, 2]) >= 0)
     r0, s0 = layout.group_face_rows(np.zeros((0, 8), np.int32))
     assert len(r0) == 0 and s0.tolist() == [0]
+
+
+def test_nested_levels_tables():
+    """A three-level hierarchy: block counts, sibling tables (-1 where no
+    patch exists), the coarse patches around every parent, and the closing
+    rows of both level pairs; a refinement that breaks proper nesting is
+    rejected."""
+    r0 = np.zeros((4, 4, 4), dtype=bool)
+    r0[1:3, 1:3, 1:3] = True
+    r1 = np.zeros((8, 8, 8), dtype=bool)
+    r1[3, 3, 3] = r1[3, 3, 4] = r1[3, 4, 3] = True
+    L = layout.NestedLevels(32, [r0, r1])
+    assert [b.n_blocks for b in L.blocks] == [64, 64, 24]
+    assert (L.blocks[0].nbr >= 0).all()
+    # level 1 is a 4^3 cube of patches: a corner patch has 7 of its 27
+    # regions (itself included) on the level
+    assert sorted(set((L.blocks[1].nbr >= 0).sum(1))) == [8, 12, 18, 27]
+    for lev in (1, 2):
+        o = L.origins[lev] // 8
+        par = {tuple(v) for v in (L.origins[lev - 1] // 8)}
+        for b in range(L.blocks[lev].n_blocks):
+            z, y, x = o[b]
+            assert L.corigin[lev][b].tolist() == [4 * (x % 2), 4 * (y % 2), 4 * (z % 2)]
+            pz, py, px = L.origins[lev - 1][L.cnbr[lev][b, 13]] // 8
+            assert (pz, py, px) == (z // 2, y // 2, x // 2) and (pz, py, px) in par
+    t = L.tables()
+    assert sorted(t) == [0, 1]
+    assert t[0][0].shape[0] == 64 and t[1][0].shape[0] == 24
+    # faces: the 2^3 cube shows 24 coarse faces, each covered by 4 fine patches
+    assert t[0][1].shape[0] == 96 and int(sum(t[0][2])) == 96
+    # the L of three patches shows 14 faces
+    assert t[1][1].shape[0] == 4 * 14
+    bad = r1.copy()
+    bad[2, 3, 3] = True
+    with pytest.raises(ValueError, match="proper nesting"):
+        layout.NestedLevels(32, [r0, bad])
+    with pytest.raises(ValueError, match="does not exist"):
+        r2 = np.zeros((16, 16, 16), dtype=bool)
+        r2[0, 0, 0] = True
+        layout.NestedLevels(32, [r0, r1, r2])

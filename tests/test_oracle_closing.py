@@ -13,7 +13,9 @@ conservation law they exist for, not against their own formulas:
 * the masked ghost fill agrees with the box fill of the coarse-fine ghost
   zones where both apply;
 * with the fine level sub-cycled (two steps of dt/2) and its flux records
-  summed with weight 1/2, the leaf totals are again conserved to round-off.
+  summed with weight 1/2, the leaf totals are again conserved to round-off;
+  so they are on three levels, each sub-cycled in its parent's step, and
+  with two levels that step is the two-level one.
 Planted mistakes (the correction's sign, the 1/4 of the fine mean, the coarse
 flux of the other face, a restriction from one child) each fail one of these.
 """
@@ -201,3 +203,81 @@ def test_planted_mistakes_are_caught(name, monkeypatch):
             except AssertionError:
                 failed.append(test.__name__)
     assert failed, f"mutant '{name}' passed every pin"
+
+
+def _three_levels():
+    """Level 0: 32^3; a 2^3 cube of refined root patches; on level 1 an L of
+    three refined patches inside it (their 26 neighbours exist: proper
+    nesting)."""
+    r0 = np.zeros((4, 4, 4), dtype=bool)
+    r0[1:3, 1:3, 1:3] = True
+    r1 = np.zeros((8, 8, 8), dtype=bool)
+    r1[3, 3, 3] = r1[3, 3, 4] = r1[3, 4, 3] = True
+    return [r0, r1]
+
+
+def _three_level_states(seed):
+    N = 32
+    s0 = wl.lognormal(N, seed=seed, sigma_ln=0.5)
+    out = [s0]
+    for lev in (1, 2):
+        M = N << lev
+        g = np.meshgrid(np.arange(M), np.arange(M), np.arange(M), indexing="ij")
+        f = ghosts.coarse_to_fine(out[-1], *g)
+        bump = wl.smooth_random(M, seed=seed + lev, amplitude=1.0)[0:1]
+        out.append(f * (1.0 + 0.05 * bump / np.abs(bump).max()))
+    return out
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_nested_subcycled_step_conserves_leaf_totals(order):
+    """Three levels, each sub-cycled in its parent's step (four level-2 steps
+    per root step): with the time-averaged records of every finer level the
+    leaf totals are conserved to round-off, and visibly not without the
+    correction; after the closing chain the root total is the leaf total."""
+    refined = _three_levels()
+    states = _three_level_states(80 + order)
+    dt = 0.25 / 32
+    before = closing.nested_leaf_sums(states, refined)
+    scale = closing.nested_leaf_sums([np.abs(s) for s in states], refined)
+    new = closing.nested_step_subcycled(states, refined, dt, order, G53)
+    after = closing.nested_leaf_sums(new, refined)
+    assert np.all(np.abs(after - before) <= 1e-13 * scale), (after - before) / scale
+    for k in range(5):
+        assert abs(math.fsum(new[0][k].ravel()) - after[k]) <= 1e-13 * scale[k]
+    leaky = closing.nested_step_subcycled(states, refined, dt, order, G53, correct=False)
+    leak = np.abs(closing.nested_leaf_sums(leaky, refined) - before) / scale
+    assert leak[0] > 1e-9 and leak[4] > 1e-9, leak
+
+
+def test_nested_two_levels_is_the_two_level_step():
+    """With two levels the nested step is the two-level sub-cycled step (the
+    fine records averaged as a lerp instead of 1/2 H1 + 1/2 H2: equal to
+    round-off)."""
+    coarse, fine = _two_level_state(32, seed=90)
+    refined = _refined_L()
+    dt = 0.25 / 32
+    c1, f1 = closing.two_level_step_subcycled(coarse, fine, refined, 8, dt, 1, G53)
+    c2, f2 = closing.nested_step_subcycled([coarse, fine], [refined], dt, 1, G53)
+    np.testing.assert_allclose(c2, c1, rtol=1e-14, atol=0)
+    m = np.repeat(np.repeat(np.repeat(refined, 16, 0), 16, 1), 16, 2)
+    np.testing.assert_allclose(f2[:, m], f1[:, m], rtol=1e-14, atol=0)
+
+
+def test_nested_uniform_state_is_unchanged():
+    refined = _three_levels()
+    states = [wl.uniform(32 << l, rho=1.2, v=(0.3, -0.1, 0.2), P=0.9, gamma=G53) for l in range(3)]
+    new = closing.nested_step_subcycled(states, refined, 0.25 / 32, 0, G53)
+    for a, b in zip(new, states):
+        np.testing.assert_allclose(a, b, rtol=1e-15, atol=0)
+
+
+def test_nested_planted_mistake_is_caught(monkeypatch):
+    """The sub-steps' records summed instead of averaged."""
+    orig = closing._subcycle
+
+    def summed(states, refined, lev, *a):
+        return [2 * r for r in orig(states, refined, lev, *a)]
+    monkeypatch.setattr(closing, "_subcycle", summed)
+    with pytest.raises(AssertionError):
+        test_nested_subcycled_step_conserves_leaf_totals(0)
