@@ -99,3 +99,103 @@ class TwoLevelDevice:
         self.c_int, self.c_out = self.c_out, self.c_int
         if f_new is self.f_mid:
             self.f_int, self.f_mid = self.f_mid, self.f_int
+
+
+class NestedDevice:
+    """A periodic hierarchy of 8^3 patches on any number of levels
+    (layout.NestedLevels) advanced on the device, every level sub-cycled.
+
+    One root step of dt (Sec. 2.1, a level's update: advance, let the finer
+    level catch up, correct with it):
+      * level 0: sibling ghost fill, advance writing flux records;
+      * level l >= 1, inside each step of dt' of level l-1: two steps of
+        dt'/2 (sweep orders o, then 1 - o), each a coarse-fine ghost fill
+        (sibling copy, else interpolation from level l-1 at the start of the
+        step for the first, half-way through it, linear in time, for the
+        second) and an advance writing this sub-step's flux records; after
+        each, level l+1 catches up in the same way and level l is closed
+        with it (restriction, flux correction with level l+1's records
+        averaged over the step);
+      * level l's records over its parent's step: the mean of its two
+        sub-steps' records (tvd_lerp at 1/2);
+      * finally level 0 is closed with level 1.
+    Per level: interior, new and ghosted states, two flux record buffers and
+    their mean; per coarse level a time-interpolated state."""
+
+    def __init__(self, ctx: tvd.Context, Nc: int, refined, dtype=torch.float64,
+                 gamma: float = GAMMA):
+        self.ctx, self.dtype, self.gamma = ctx, dtype, gamma
+        self.L = L = layout.NestedLevels(Nc, refined)
+        self.code = tvd.dtype_code(dtype)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
+        self.nb = [b.n_blocks for b in L.blocks]
+        rs = layout.flux_record_size(8)
+        self.u = [z(n * 5 * 512) for n in self.nb]
+        self.u_new = [z(n * 5 * 512) for n in self.nb]
+        self.u_gh = [z(n * 5 * 14 ** 3) for n in self.nb]
+        self.u_half = [z(n * 5 * 512) for n in self.nb[:-1]]
+        self.rec = [[z(n * rs), z(n * rs)] for n in self.nb]
+        self.rec_mean = [None] + [z(n * rs) for n in self.nb[1:]]
+        self.nbr = [dev(b.nbr) for b in L.blocks]
+        self.cnbr = [None] + [dev(t) for t in L.cnbr[1:]]
+        self.corigin = [None] + [dev(t) for t in L.corigin[1:]]
+        self.rows = {}
+        for lev, (rr, fr, _) in L.tables().items():
+            gr, gs = layout.group_face_rows(fr)
+            self.rows[lev] = (dev(rr), dev(gr), dev(gs))
+
+    def upload(self, states):
+        """Per level the patch interiors (B_l, 5, 8, 8, 8) in NestedLevels
+        order."""
+        for buf, s in zip(self.u, states):
+            buf.copy_(torch.from_numpy(np.ascontiguousarray(s)).reshape(-1))
+
+    def download(self):
+        """Per level the patch interiors (B_l, 5, 8, 8, 8), FP64 numpy."""
+        return [b.double().cpu().numpy().reshape(n, 5, 8, 8, 8) for b, n in zip(self.u, self.nb)]
+
+    def _batch(self, lev, dt):
+        return tvd.Batch(self.code, self.nb[lev], 8, dt=dt, dh=1.0 / (self.L.Nc << lev))
+
+    def _close(self, lev, dt):
+        rr, gr, gs = self.rows[lev]
+        self.ctx.tvd_close_level(self._batch(lev, dt), self.u_new[lev], self.rec[lev][self._k[lev]],
+                                 None, self._batch(lev + 1, 0.5 * dt), self.u[lev + 1],
+                                 self.rec_mean[lev + 1], None, rr, gr, gs)
+
+    def _subcycle(self, lev, dt, order):
+        """Level lev takes two steps of dt/2 inside level lev-1's step of dt,
+        whose old state is u[lev-1] and whose advanced one u_new[lev-1]."""
+        ctx, h = self.ctx, 0.5 * dt
+        ctx.tvd_lerp(self.code, self.nb[lev - 1] * 5 * 512, self.u[lev - 1], self.u_new[lev - 1],
+                     self.u_half[lev - 1], 0.5)
+        fb, cb = self._batch(lev, h), self._batch(lev - 1, h)
+        for k in (0, 1):
+            o = order if k == 0 else 1 - order
+            src = self.u[lev - 1] if k == 0 else self.u_half[lev - 1]
+            ctx.tvd_fill_ghosts_amr(fb, self.nbr[lev], self.u[lev], self.u_gh[lev], cb, src,
+                                    self.cnbr[lev], self.corigin[lev])
+            ctx.tvd_patch_advance_flux(fb, self.u_gh[lev], self.u_new[lev], self.rec[lev][k], None,
+                                       o, self.gamma)
+            if lev + 1 < self.L.n_levels:
+                self._k[lev] = k
+                self._subcycle(lev + 1, h, o)
+                self._close(lev, h)
+            self.u[lev], self.u_new[lev] = self.u_new[lev], self.u[lev]
+        ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(8), self.rec[lev][0],
+                     self.rec[lev][1], self.rec_mean[lev], 0.5)
+
+    def step(self, dt: float, order: int):
+        """One root step of dt in sweep order `order` (every level sub-cycled,
+        every pair closed)."""
+        ctx = self.ctx
+        self._k = [0] * self.L.n_levels
+        b0 = self._batch(0, dt)
+        ctx.tvd_fill_ghosts(b0, self.nbr[0], self.u[0], self.u_gh[0])
+        ctx.tvd_patch_advance_flux(b0, self.u_gh[0], self.u_new[0], self.rec[0][0], None, order,
+                                   self.gamma)
+        if self.L.n_levels > 1:
+            self._subcycle(1, dt, order)
+            self._close(0, dt)
+        self.u[0], self.u_new[0] = self.u_new[0], self.u[0]
