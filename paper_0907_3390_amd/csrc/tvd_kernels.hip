@@ -1010,16 +1010,20 @@ struct CoarseNbhd {
   const int64_t* coff;  // coarse out offsets (or null: dense)
   const int32_t* cnbr;  // 27 entries of this fine block
   int ncoarse;
+  // Branch-free, so that the seven reads of a cell's stencil issue together:
+  // a cell outside the 27 patches or a missing patch reads block 0 instead
+  // (ncoarse >= 1 is checked by the caller) and reports false.
   __device__ inline bool get(int ix, int iy, int iz, T u[kNV]) const {
     const int qx = ix >> 3, qy = iy >> 3, qz = iz >> 3;
-    if (qx < -1 || qx > 1 || qy < -1 || qy > 1 || qz < -1 || qz > 1) return false;
-    const int cb = cnbr[(qx + 1) + 3 * (qy + 1) + 9 * (qz + 1)];
-    if (cb < 0 || cb >= ncoarse) return false;
-    const T* c = cin + (coff ? coff[cb] : (int64_t)cb * kNV * 512) + (ix & 7) + 8 * (iy & 7) +
+    const bool in = qx >= -1 && qx <= 1 && qy >= -1 && qy <= 1 && qz >= -1 && qz <= 1;
+    const int cb = cnbr[in ? (qx + 1) + 3 * (qy + 1) + 9 * (qz + 1) : 13];
+    const bool ok = in && cb >= 0 && cb < ncoarse;
+    const int cs = ok ? cb : 0;
+    const T* c = cin + (coff ? coff[cs] : (int64_t)cs * kNV * 512) + (ix & 7) + 8 * (iy & 7) +
                  64 * (iz & 7);
 #pragma unroll
     for (int k = 0; k < kNV; ++k) u[k] = c[k * 512];
-    return true;
+    return ok;
   }
 };
 
@@ -1065,21 +1069,28 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
   const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;  // floor
   const T q = T(0.25);
   const T dx = (fx & 1) ? q : -q, dy = (fy & 1) ? q : -q, dz = (fz & 1) ? q : -q;
+  if (ncoarse <= 0) {
+    atomicAdd(&kp.counters[1], 1ull);
+    return;
+  }
   const CoarseNbhd<T> cn{cin, coff, cnbr + 27 * (int64_t)b, ncoarse};
-  T u[kNV], p[kNV], mm[kNV], out[kNV];
+  // all seven stencil reads first (no short-circuit between them)
+  T u[kNV], xp[kNV], xm[kNV], yp[kNV], ym[kNV], zp[kNV], zm[kNV], out[kNV];
   bool ok = cn.get(cx, cy, cz, u);
-#pragma unroll
-  for (int k = 0; k < kNV; ++k) out[k] = u[k];
+  ok = cn.get(cx + 1, cy, cz, xp) & ok;
+  ok = cn.get(cx - 1, cy, cz, xm) & ok;
+  ok = cn.get(cx, cy + 1, cz, yp) & ok;
+  ok = cn.get(cx, cy - 1, cz, ym) & ok;
+  ok = cn.get(cx, cy, cz + 1, zp) & ok;
+  ok = cn.get(cx, cy, cz - 1, zm) & ok;
   // x, then y, then z (the order of the sum)
-  ok = ok && cn.get(cx + 1, cy, cz, p) && cn.get(cx - 1, cy, cz, mm);
 #pragma unroll
-  for (int k = 0; k < kNV; ++k) out[k] = out[k] + dx * minmod(p[k] - u[k], u[k] - mm[k]);
-  ok = ok && cn.get(cx, cy + 1, cz, p) && cn.get(cx, cy - 1, cz, mm);
-#pragma unroll
-  for (int k = 0; k < kNV; ++k) out[k] = out[k] + dy * minmod(p[k] - u[k], u[k] - mm[k]);
-  ok = ok && cn.get(cx, cy, cz + 1, p) && cn.get(cx, cy, cz - 1, mm);
-#pragma unroll
-  for (int k = 0; k < kNV; ++k) out[k] = out[k] + dz * minmod(p[k] - u[k], u[k] - mm[k]);
+  for (int k = 0; k < kNV; ++k) {
+    out[k] = u[k];
+    out[k] = out[k] + dx * minmod(xp[k] - u[k], u[k] - xm[k]);
+    out[k] = out[k] + dy * minmod(yp[k] - u[k], u[k] - ym[k]);
+    out[k] = out[k] + dz * minmod(zp[k] - u[k], u[k] - zm[k]);
+  }
   if (!ok) {
     atomicAdd(&kp.counters[1], 1ull);
     return;
