@@ -1027,52 +1027,30 @@ struct CoarseNbhd {
   }
 };
 
+// Ghosted cells per thread in the coarse-fine fill: a thread resolves the
+// source of each of its cells first and then issues all their sibling reads
+// together, so the chain of table lookups before a copy is paid once per
+// kFillCPT cells.
+constexpr int kFillCPT = 4;
+
+// Interpolated ghost cell (x, y, z) of fine block b: Min-Mod limited linear
+// interpolation from the coarse level.
 template <typename T>
-__global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const int32_t* nbr,
-                                                            int chunks, const T* cin,
-                                                            const int64_t* coff, int ncoarse,
-                                                            const int32_t* cnbr,
-                                                            const int32_t* corigin) {
-  const int b = blockIdx.x / chunks;
-  const int chunk = blockIdx.x % chunks;
-  const int n = block_edge(kp, b);
-  const int m = n + 2 * kG;
-  const int m3 = m * m * m;
-  const int n3 = n * n * n;
-  const int cell = chunk * kFillNT + threadIdx.x;
-  if (cell >= m3) return;
-  const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
-  const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
-  const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
-  const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
-  T* d = reinterpret_cast<T*>(const_cast<void*>(kp.uin)) +
-         (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
-  const int src = nbr[27 * b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
-  if (src >= 0) {
-    // sibling copy
-    if (src >= kp.nblocks || block_edge(kp, src) != n) {
-      atomicAdd(&kp.counters[1], 1ull);
-      return;
-    }
-    const int sx = x - kG - rx * n, sy = y - kG - ry * n, sz = z - kG - rz * n;
-    const int so = sx + n * (sy + n * sz);
-    const T* s = reinterpret_cast<const T*>(kp.uout) +
-                 (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n3);
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = s[(int64_t)k * n3 + so];
+__device__ __forceinline__ void fill_interp(const KParams& kp, int b, int x, int y, int z,
+                                            T* d, int64_t m3, int cell, const T* cin,
+                                            const int64_t* coff, int ncoarse,
+                                            const int32_t* cnbr, const int32_t* corigin) {
+  if (ncoarse <= 0) {
+    atomicAdd(&kp.counters[1], 1ull);
     return;
   }
-  // interpolation: fine index relative to the parent's corner, in fine cells
+  // fine index relative to the parent's corner, in fine cells
   const int fx = 2 * corigin[3 * b + 0] + x - kG;
   const int fy = 2 * corigin[3 * b + 1] + y - kG;
   const int fz = 2 * corigin[3 * b + 2] + z - kG;
   const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;  // floor
   const T q = T(0.25);
   const T dx = (fx & 1) ? q : -q, dy = (fy & 1) ? q : -q, dz = (fz & 1) ? q : -q;
-  if (ncoarse <= 0) {
-    atomicAdd(&kp.counters[1], 1ull);
-    return;
-  }
   const CoarseNbhd<T> cn{cin, coff, cnbr + 27 * (int64_t)b, ncoarse};
   // all seven stencil reads first (no short-circuit between them)
   T u[kNV], xp[kNV], xm[kNV], yp[kNV], ym[kNV], zp[kNV], zm[kNV], out[kNV];
@@ -1097,6 +1075,75 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
   }
 #pragma unroll
   for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = out[k];
+}
+
+// One workgroup per kFillNT * kFillCPT ghosted cells of a fine block; chunks
+// workgroups per block.  A cell is a sibling copy when the block's neighbour
+// table names a block for its region, else interpolated from the coarse
+// level.
+template <typename T>
+__global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const int32_t* nbr,
+                                                            int chunks, const T* cin,
+                                                            const int64_t* coff, int ncoarse,
+                                                            const int32_t* cnbr,
+                                                            const int32_t* corigin) {
+  const int b = blockIdx.x / chunks;
+  const int chunk = blockIdx.x % chunks;
+  const int n = block_edge(kp, b);
+  const int m = n + 2 * kG;
+  const int m3 = m * m * m;
+  const int n3 = n * n * n;
+  T* d = reinterpret_cast<T*>(const_cast<void*>(kp.uin)) +
+         (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
+  const T* own = reinterpret_cast<const T*>(kp.uout) +
+                 (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * n3);
+  // 0: no cell, 1: sibling copy from sp[i], 2: interpolated
+  int kind[kFillCPT];
+  const T* sp[kFillCPT];
+#pragma unroll
+  for (int i = 0; i < kFillCPT; ++i) {
+    const int cell = (chunk * kFillCPT + i) * kFillNT + threadIdx.x;
+    kind[i] = 0;
+    sp[i] = own;  // a valid address for the unconditional reads below
+    if (cell < m3) {
+      const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+      const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
+      const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
+      const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
+      const int src = nbr[27 * b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
+      if (src < 0) {
+        kind[i] = 2;
+      } else if (src >= kp.nblocks || block_edge(kp, src) != n) {
+        atomicAdd(&kp.counters[1], 1ull);
+      } else {
+        const int sx = x - kG - rx * n, sy = y - kG - ry * n, sz = z - kG - rz * n;
+        sp[i] = reinterpret_cast<const T*>(kp.uout) +
+                (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n3) +
+                (sx + n * (sy + n * sz));
+        kind[i] = 1;
+      }
+    }
+  }
+  T v[kFillCPT][kNV];
+#pragma unroll
+  for (int i = 0; i < kFillCPT; ++i)
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) v[i][k] = sp[i][(int64_t)k * n3];
+#pragma unroll
+  for (int i = 0; i < kFillCPT; ++i) {
+    const int cell = (chunk * kFillCPT + i) * kFillNT + threadIdx.x;
+    if (kind[i] == 1) {
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = v[i][k];
+    }
+  }
+#pragma unroll 1
+  for (int i = 0; i < kFillCPT; ++i) {
+    if (kind[i] != 2) continue;
+    const int cell = (chunk * kFillCPT + i) * kFillNT + threadIdx.x;
+    const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+    fill_interp<T>(kp, b, x, y, z, d, m3, cell, cin, coff, ncoarse, cnbr, corigin);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1658,7 +1705,7 @@ hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* n
                                   const void* cin, const int64_t* coff, int ncoarse,
                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s) {
   const int m = max_edge + 2 * kG;
-  const int chunks = (m * m * m + kFillNT - 1) / kFillNT;
+  const int chunks = (m * m * m + kFillNT * kFillCPT - 1) / (kFillNT * kFillCPT);
   const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
   if (dtype == 1)
     hipLaunchKernelGGL((k_fill_ghosts_amr<float>), grid, block, 0, s, kp, nbr, chunks,
