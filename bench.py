@@ -408,17 +408,8 @@ def run_nested(ctx, ml, reps=4):
     the timed steps (host sums of the downloaded state)."""
     import torch
     from paper_0907_3390_amd import amr, layout, tvd
-    base = ml.base // 8
-    pset = set(ml.patches)
-    top = max(p[0] for p in ml.patches)
-    refined = []
-    for lev in range(top):
-        n = base << lev
-        r = np.zeros((n, n, n), dtype=bool)
-        for (l, px, py, pz) in ml.patches:
-            if l == lev and (lev + 1, 2 * px, 2 * py, 2 * pz) in pset:
-                r[pz, py, px] = True
-        refined.append(r)
+    refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
+    top = len(refined)
     dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]

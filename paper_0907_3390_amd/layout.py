@@ -503,6 +503,23 @@ class NestedLevels:
     def locate(self, level, px, py, pz):
         return self._index[level][(px, py, pz)], (0, 0, 0)
 
+    @staticmethod
+    def refined_from_patches(Nc: int, patches):
+        """The ``refined`` masks of an octree given as (level, px, py, pz)
+        patches over an Nc^3 root grid: a patch is refined when its first
+        child is listed."""
+        pset = set(tuple(int(v) for v in p) for p in patches)
+        top = max(p[0] for p in pset)
+        out = []
+        for lev in range(top):
+            n = (Nc // PATCH) << lev
+            r = np.zeros((n, n, n), dtype=bool)
+            for (l, px, py, pz) in pset:
+                if l == lev and (lev + 1, 2 * px, 2 * py, 2 * pz) in pset:
+                    r[pz, py, px] = True
+            out.append(r)
+        return out
+
     def tables(self):
         """{level l: (restrict_rows, face_rows, pass_count)} of every pair
         (l, l+1)."""

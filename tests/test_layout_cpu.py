@@ -191,3 +191,13 @@ def test_nested_levels_tables():
         r2 = np.zeros((16, 16, 16), dtype=bool)
         r2[0, 0, 0] = True
         layout.NestedLevels(32, [r0, r1, r2])
+
+
+def test_nested_levels_masks_round_trip():
+    r0 = np.zeros((4, 4, 4), dtype=bool)
+    r0[1:3, 1:3, 1:3] = True
+    r1 = np.zeros((8, 8, 8), dtype=bool)
+    r1[3, 3, 3] = r1[3, 4, 4] = True
+    L = layout.NestedLevels(32, [r0, r1])
+    back = layout.NestedLevels.refined_from_patches(32, L.patches)
+    assert len(back) == 2 and all(np.array_equal(a, b) for a, b in zip(back, [r0, r1]))
