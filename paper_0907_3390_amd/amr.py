@@ -119,8 +119,9 @@ class NestedDevice:
       * level l's records over its parent's step: the mean of its two
         sub-steps' records (tvd_lerp at 1/2);
       * finally level 0 is closed with level 1.
-    Per level: interior, new and ghosted states, two flux record buffers and
-    their mean; per coarse level a time-interpolated state."""
+    Per level: interior, new and ghosted states, flux record buffers (one on
+    level 0, one per sub-step and their mean on the others); per coarse level
+    a time-interpolated state."""
 
     def __init__(self, ctx: tvd.Context, Nc: int, refined, dtype=torch.float64,
                  gamma: float = GAMMA):
@@ -135,7 +136,9 @@ class NestedDevice:
         self.u_new = [z(n * 5 * 512) for n in self.nb]
         self.u_gh = [z(n * 5 * 14 ** 3) for n in self.nb]
         self.u_half = [z(n * 5 * 512) for n in self.nb[:-1]]
-        self.rec = [[z(n * rs), z(n * rs)] for n in self.nb]
+        # level 0 takes one step per root step, the others two
+        self.rec = [[z(n * rs)] if lev == 0 else [z(n * rs), z(n * rs)]
+                    for lev, n in enumerate(self.nb)]
         self.rec_mean = [None] + [z(n * rs) for n in self.nb[1:]]
         self.nbr = [dev(b.nbr) for b in L.blocks]
         self.cnbr = [None] + [dev(t) for t in L.cnbr[1:]]
