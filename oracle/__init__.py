@@ -31,6 +31,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -44,12 +45,21 @@ GHOST = 3
 _lib = None
 
 
-def build(verbose: bool = False, src: str = _SRC, out: str = _LIB) -> str:
+# ISO C99 keeps floating-point contraction off, so -O3 and -march change the
+# speed, not the arithmetic.  The shipped build is portable (it may run on
+# another host than the one that compiled it); CFLAGS_NATIVE is for a build
+# made on the host that runs it.
+CFLAGS = ["-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall"]
+CFLAGS_NATIVE = CFLAGS + ["-march=native"]
+
+
+def build(verbose: bool = False, src: str = _SRC, out: str = _LIB, native: bool = False,
+          extra=()) -> str:
     """Compile the C oracle with gcc (default: ``oracle/_build/liboracle.so``)."""
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-           "-Wall", "-o", tmp, src, "-lm"]
+    cmd = (["gcc"] + (CFLAGS_NATIVE if native else CFLAGS) + list(extra)
+           + ["-o", tmp, src, "-lm"])
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -170,6 +180,7 @@ class Counts:
     floored: int = 0
     nonphysical: int = 0
     threads: int = 1
+    seconds: float = 0.0   # wall time inside the C advance (no marshalling)
 
 
 PATCH = 8
@@ -224,6 +235,7 @@ def advance_ragged(blocks_in, order: int, dt, dh, gamma: float, p_floor: float =
         flat_flux = np.full(int(f_sizes.sum()), np.nan)
         flux_p = _dptr(flat_flux)
         flux_off_p = flux_off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))
+    t0 = time.perf_counter()
     th = lib.oracle_advance_batch(
         _dptr(flat_in), _dptr(flat_out), nb,
         edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
@@ -231,7 +243,9 @@ def advance_ragged(blocks_in, order: int, dt, dh, gamma: float, p_floor: float =
         out_off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
         _dptr(dt_a), _dptr(dh_a), int(order), float(gamma), float(p_floor),
         flux_p, flux_off_p, ctypes.byref(fl), ctypes.byref(npy))
+    t1 = time.perf_counter()
     if counts is not None:
+        counts.seconds += t1 - t0
         counts.floored += fl.value
         counts.nonphysical += npy.value
         counts.threads = th

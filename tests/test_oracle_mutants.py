@@ -65,6 +65,27 @@ MUTANTS = {
     "boundary flux face coordinates transposed":
         ("const int a = a1 > a2 ? p1 : p2;\n                    const int b = a1 > a2 ? p2 : p1;",
          "const int a = a1 > a2 ? p2 : p1;\n                    const int b = a1 > a2 ? p1 : p2;"),
+    "freezing speed taken at time t in the midpoint fluxes":
+        ("""        oracle_split_fluxes(h + j * NVAR, d, gamma, p_floor, FRh + j * NVAR,
+                            FLh + j * NVAR, cnt);""",
+         """    {
+        const double ct = oracle_split_fluxes(q + j * NVAR, d, gamma, p_floor, FRh + j * NVAR,
+                                              FLh + j * NVAR, NULL);
+        const double ch = oracle_split_fluxes(h + j * NVAR, d, gamma, p_floor, FRh + j * NVAR,
+                                              FLh + j * NVAR, cnt);
+        for (int k = 0; k < NVAR; ++k) {
+            FRh[j * NVAR + k] += 0.5 * (ct - ch) * h[j * NVAR + k];
+            FLh[j * NVAR + k] += 0.5 * (ct - ch) * h[j * NVAR + k];
+        }
+    }"""),
+    "limiter on unhalved differences":
+        ("""            const double dR1 = (FRh[j * NVAR + k] - FRh[(j - 1) * NVAR + k]) / 2.0;
+            const double dR2 = (FRh[(j + 1) * NVAR + k] - FRh[j * NVAR + k]) / 2.0;""",
+         """            const double dR1 = (FRh[j * NVAR + k] - FRh[(j - 1) * NVAR + k]);
+            const double dR2 = (FRh[(j + 1) * NVAR + k] - FRh[j * NVAR + k]);"""),
+    "full step over half the dt":
+        ("(H[j * NVAR + k] - H[(j - 1) * NVAR + k]) / dh * dt;",
+         "(H[j * NVAR + k] - H[(j - 1) * NVAR + k]) / dh * (dt / 2.0);"),
     "boundary flux taken from the first-order flux":
         ("hface[i * NVAR + k] = H[(i + GHOST - 1) * NVAR + k];",
          "hface[i * NVAR + k] = G[(i + GHOST - 1) * NVAR + k];"),
@@ -87,6 +108,7 @@ PINS = [
     "test_pressureless_advection",
     "test_acoustic_wave_second_order",
     "test_sod_against_exact_riemann",
+    "test_pencil_against_mpmath_reference",
 ]
 
 RUNNER = r"""
