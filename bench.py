@@ -1,41 +1,36 @@
 #!/usr/bin/env python3
 """Throughput of the relaxing-TVD patch advance on one MI355X.
 
-Workload: a periodic 256^3 grid, i.e. 32768 octree patches of 8^3 cells,
-lognormal density (sigma_ln = 1), Gaussian velocities (sigma = 0.3 c_s),
-uniform pressure P = 1, gamma = 5/3, CFL 0.5, seeded.  A step is one pass of
-the whole hot path on the device: the Eq. (CFL) signal speed and the time
-step on even steps (fused into the previous odd step's advance), the
-sibling ghost-zone fill, and one triple of 1-D sweeps (xyz on even steps,
-zyx on odd steps).
+Headline workload: a periodic 512^3 grid, i.e. 262144 octree patches of 8^3
+cells run as 32768 Morton-ordered 2^3 patch groups of 16^3: a point blast
+(energy 1 as thermal energy in the central 2^3 cells, Sec. 4.3 set-up) on a
+lognormal background (sigma_ln = 0.5, gas at rest, P = 1e-5), gamma = 5/3,
+CFL 0.5, pressure floor 1e-10, seeded.  A step is one pass of the whole hot
+path on the device: the Eq. (CFL) time step on even steps (from the signal
+speed fused into the previous odd step), one triple of 1-D sweeps (xyz on
+even steps, zyx on odd steps) gathering the ghost zones from the 26
+neighbours' interiors, the fused signal speed on odd steps and the fused
+FP64 compensated conservation sums on every step.  The timed steps are
+replays of a HIP graph of one xyz/zyx pair; odd --steps / --warmup are
+rounded up to whole pairs (both counts are reported).
 
 Reported (one JSON line on stdout):
-* value: cell-updates/s of the FP32 batched kernel on 2^3 patch groups
-  (4096 blocks of 16^3 interior cells), inputs resident in HBM;
-* fp64_plain: the same steps with the plain FP64 per-patch kernel
-  (32768 blocks of 8^3) on the same FP32-rounded initial state;
-* fp64_batched, fp32_batched_edge8: the batched kernel in FP64 on 8^3
-  patches (with its largest difference from fp64_plain) and in FP32 on
-  single 8^3 patches instead of 2^3 patch groups;
-* l1_vs_fp64: relative L1 error per variable of the FP32 result against
-  the FP64 result after the same steps;
-* roofline: the advance kernel's algorithmic HBM bytes per launch over its
-  average duration (HIP events on the launch stream) against 8 TB/s;
-* cpu_baseline: the FP64 oracle on the host cores over a bounded sample;
-* uneven_batch: cell-updates/s of 4000 periodic boxes of mixed sizes in one
-  persistent launch per step, 50-step HIP graphs, block edge tuned;
-* amr_ghost_fill: the coarse-fine ghost fill (sibling copy, else Min-Mod
-  limited interpolation from the coarser level) of 8^3 patches and 16^3
-  groups covering a refined 256^3-cell box;
-* multilevel_batch: one step of a 4-level patch hierarchy (18 152 patches,
-  per-block dt and dh) as one persistent FP32 launch on patches and on 2^3
-  patch groups, and as plain FP64 launches level by level;
-* closing_step: on the same hierarchy with one dt, the advance writing
-  patch-boundary flux records, and the restriction and coarse-fine flux
-  correction of every level pair;
-* poisson_sor: red-black SOR for the Poisson equation on 4096 patch groups,
-  50 fixed iterations and solves to the stopping rule, FP32 and FP64;
-* gravity_operator: the self-gravity source operator on the 256^3 state.
+* value: cell-updates/s of the FP32 batched kernel, inputs resident in HBM;
+* roofline: the advance kernel's algorithmic FP32 work and HBM bytes per
+  launch over its average duration (HIP events on the launch stream)
+  against the FP32 vector peak and 8 TB/s, with the HBM traffic from the
+  committed rocprofv3 counters when they were taken on the current kernel;
+* fp64_plain, l1_vs_fp64: the same steps with the plain FP64 per-patch
+  kernel on the same FP32-rounded initial state, and the relative L1 error
+  per variable of the FP32 result against it;
+* lognormal_256cube: the same measurements on a rough 256^3 state
+  (lognormal density sigma_ln = 1, Gaussian velocities), with the batched
+  kernel in FP64 on 8^3 patches and in FP32 on single 8^3 patches;
+* cpu_baseline: the FP64 oracle, built for the host, on the host cores over
+  a bounded sample of the headline workload;
+* with --extras: the coarse-fine ghost fill, the multi-level batch, the
+  closing step, the nested sub-cycled step, red-black SOR, the gravity
+  operator and the uneven batch of 4000 boxes.
 """
 from __future__ import annotations
 
@@ -53,14 +48,19 @@ sys.path.insert(0, ROOT)
 
 N_GRID = 256
 SEED = 2024
+# the headline workload: 512^3 point blast on a lognormal background
+N_BLAST = 512
+SEED_BLAST = 5
+P_FLOOR_BLAST = 1e-10
 GAMMA = 5.0 / 3.0
 CFL = 0.5
 HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32 (turned off in this build):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batched_fp32_edge16_gather_256cube_traffic.txt")
-KERNEL_SOURCES = ["paper_0907_3390_amd/csrc/tvd_kernels.hip", "paper_0907_3390_amd/csrc/tvd_device.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_fp32_edge16_512blast_traffic.txt")
+KERNEL_SOURCES = ["paper_0907_3390_amd/csrc/tvd_stream.hpp", "paper_0907_3390_amd/csrc/tvd_block.hpp",
+                  "paper_0907_3390_amd/csrc/tvd_device.hpp"]
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 error; HBM GB/s % of peak"
 
 
@@ -76,6 +76,23 @@ def flops_per_block(n: int) -> int:
     M = n + 6
     pencil = 45 * M + 5 * (M - 1) + 60 * (M - 2) + 65 * (n + 1) + 15 * n
     return pencil * (M * M + n * M + n * n)
+
+
+def pencil_flops(n: int) -> int:
+    """Algorithmic FP32 work of one 1-D update of a pencil of n+6 cells with
+    n outputs (the same count as flops_per_block)."""
+    M = n + 6
+    return 45 * M + 5 * (M - 1) + 60 * (M - 2) + 65 * (n + 1) + 15 * n
+
+
+def flops_per_cell_stream(planes: int) -> float:
+    """Algorithmic FP32 work per cell-update of the streamed schedule on a
+    chain of `planes` planes of a 16 x 16 tile: the first two sweeps on 22
+    and 16 pencils of 16 outputs for each of planes + 6 planes (three ghost
+    planes at each chain end), the third sweep once per cell of each column
+    (45 + 5 + 60 + 65 + 15 = 190 flops per cell of an endless pencil,
+    planes + 6 cells passed through)."""
+    return (planes + 6) / planes * ((22 + 16) * pencil_flops(16) / 256.0 + 190.0)
 
 
 def kernel_source_hash() -> str:
@@ -103,48 +120,111 @@ def measured_traffic(variant):
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
     if variant is not None:
-        got = [int(x) for x in kv.get("variant", "0,0,0,0").split(",")]
-        want = [variant[k] for k in ("edge", "threads", "lds_pad", "split")]
-        if got[:2] != want[:2] or (got[3] & 2) != (want[3] & 2):
-            return None, f"counters were taken on variant {got}, not {want}"
+        want = f"{variant['chain_len']},{variant['second_sweep']}"
+        if kv.get("variant") != want:
+            return None, f"counters were taken on variant {kv.get('variant')}, not {want}"
     return float(kv["hbm_bytes_per_launch_mean"]), ("rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
                                                     + os.path.relpath(TRAFFIC_FILE, ROOT))
 
 
-def make_ic():
+def make_ic(N=N_GRID):
+    """The rough lognormal state (sigma_ln = 1, Gaussian velocities), FP32-rounded;
+    the FP64 runs start from the same values."""
     from paper_0907_3390_amd import workloads as wl
-    g = wl.lognormal(N_GRID, seed=SEED, sigma_ln=1.0, vel_sigma_rel=0.3, P0=1.0, gamma=GAMMA)
-    return g.astype(np.float32)  # FP32-rounded; the FP64 runs start from the same values
+    g = wl.lognormal(N, seed=SEED, sigma_ln=1.0, vel_sigma_rel=0.3, P0=1.0, gamma=GAMMA)
+    return g.astype(np.float32).astype(np.float64)
 
 
-def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=False):
-    """Warm up, then time `steps` steps twice: eagerly with HIP events around
-    every advance launch (for the kernel's average duration), and as replays
-    of a HIP graph holding one xyz/zyx pair (for the step rate)."""
+def make_blast(N=N_BLAST):
+    """The point blast on a lognormal background (sigma_ln = 0.5, gas at rest,
+    P = 1e-5, energy 1 in the central 2^3 cells), FP32-rounded."""
+    from paper_0907_3390_amd import workloads as wl
+    g = wl.sedov_lognormal(N, seed=SEED_BLAST, sigma_ln=0.5)
+    return g.astype(np.float32).astype(np.float64)
+
+
+def tune_stream(ctx, dev, candidates, reps=2):
+    """Time one xyz/zyx pair (fused speed and sums, as in the timed step) per
+    (chain length, second-sweep layout) candidate on the real state, after
+    an untimed pair, writing a scratch buffer; keep the fastest."""
+    import torch
+    from paper_0907_3390_amd import tvd
+    stream = torch.cuda.current_stream()
+    dev.dt.fill_(CFL / dev.bs.n_blocks)  # any small dt: the state is not kept
+    times = {}
+    for L, flags in candidates:
+        dev.set_chains(L)
+        dev.kernel = flags
+        state = dev.interior.clone()
+        for r in range(reps + 1):
+            if r == 1:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+            for o in (0, 1):
+                dev.advance(o, fuse_speed=o == 1, fuse_sums=True)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times[(L, flags)] = a.elapsed_time(b) / reps
+        dev.interior.copy_(state)
+        del state
+    (L, flags), ms = min(times.items(), key=lambda kv: kv[1])
+    dev.set_chains(L)
+    dev.kernel = flags
+    return {"chain_len": L, "second_sweep": "whole pencils" if flags else "half pencils",
+            "ms_per_pair": ms,
+            "candidates_ms_per_pair": {f"chain {k[0]}, {'whole' if k[1] else 'halves'}": v
+                                       for k, v in times.items()}}
+
+
+def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=False,
+            p_floor=0.0, sums=False, stream=False):
+    """Warm up, then time `steps` steps (an even number) twice: eagerly with
+    HIP events around every advance launch (for the kernel's average
+    duration), and as replays of a HIP graph holding one xyz/zyx pair (for
+    the step rate).  A step is the device time step on even steps, the
+    advance (gathering ghost cells from the neighbours' interiors, or after
+    a separate sibling fill), the fused signal speed on odd steps and, with
+    `sums`, the fused FP64 compensated conservation sums on every step."""
     import torch
     from paper_0907_3390_amd import layout, tvd
     from paper_0907_3390_amd.driver import DeviceBlocks
+    N = grid32.shape[3]
     # blocks numbered along a Morton curve: each XCD's contiguous share of the
     # blocks is a compact brick, so neighbours' ghost data meet in its L2
-    bs = layout.periodic_grid_blockset(N_GRID, n, curve="morton")
-    dev = DeviceBlocks(ctx, bs, dtype=dtype, gamma=GAMMA, cfl=CFL, kernel=kernel, gather=gather)
-    dev.upload(layout.grid_to_blocks(grid32.astype(np.float64), n, bs.perm))
+    bs = layout.periodic_grid_blockset(N, n, curve="morton")
+    dev = DeviceBlocks(ctx, bs, dtype=dtype, gamma=GAMMA, cfl=CFL, kernel=kernel, gather=gather,
+                       p_floor=p_floor, stream=stream)
+    dev.upload(layout.grid_to_blocks(grid32, n, bs.perm))
     info = {"blocks": bs.n_blocks, "edge": n}
-    if tune:
+    if sums:
+        # exact sums of the initial state (the reference for the drift)
+        dev.conservation_sums()
+        info["sums0"] = dev.sums.cpu().numpy().tolist()
+    if tune and stream:
+        col = N // n
+        lens = sorted({L for L in (col // 4, col // 2, col) if 2 <= L <= 64})
+        info["variant"] = tune_stream(ctx, dev, [(L, f) for L in lens
+                                                 for f in (tvd.TVD_KERNEL_AUTO,
+                                                           tvd.TVD_STREAM_WHOLE_B)])
+        log(f"bench: streamed advance tuned {info['variant']}")
+    elif tune:
         # pick the launch variant on the real data (scratch output), untimed
-        dev.dt.fill_(CFL / N_GRID / 4.0)
+        dev.signal_speed()
+        dev.set_dt_from_speed()
         scratch = dev.spare if gather else dev.interior.clone()
         src = dev.interior if gather else dev.ghosted
         if not gather:
             dev.fill_ghosts()
         idx, ms = ctx.tvd_autotune(dev.batch, dev.nbr if gather else None, src, scratch, GAMMA,
-                                   reps=3)
+                                   p_floor=p_floor, reps=3)
         info["variant"] = dict(zip(("index", "edge", "threads", "lds_pad", "split"),
                                    tvd.variants()[idx]))
         info["variant"]["tuned_ms_per_pair"] = ms
         log(f"bench: tuned variant {info['variant']}")
-    for _ in range(max(warmup, 2)):
-        dev.step()
+    ctx.tvd_read_flags()
+    for _ in range(warmup):
+        dev.step(sums=sums)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     adv_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -156,14 +236,14 @@ def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=Fal
         if not gather:
             dev.fill_ghosts()
         adv_ev[k][0].record(stream)
-        dev.advance(s % 2, fuse_speed=(s % 2 == 1))
+        dev.advance(s % 2, fuse_speed=(s % 2 == 1), fuse_sums=sums)
         adv_ev[k][1].record(stream)
         dev.step_index += 1
     torch.cuda.synchronize()
     info["adv_ms"] = [a.elapsed_time(b) for a, b in adv_ev]
     # graph-captured pair, replayed steps/2 times
     side = torch.cuda.Stream()
-    graph = dev.capture(2, stream=side)
+    graph = dev.capture(2, stream=side, sums=sums)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -176,6 +256,9 @@ def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=Fal
     info["wall_s"] = time.perf_counter() - t0
     info["total_ms"] = start.elapsed_time(stop)
     graph.close()
+    info["steps_run"] = dev.step_index
+    if sums:
+        info["sums"] = dev.sums.cpu().numpy().tolist()
     st, info["floored"], info["nonphysical"] = ctx.tvd_read_flags()
     return dev, info
 
@@ -432,6 +515,7 @@ def run_nested(ctx, ml, reps=4):
     sm = torch.zeros(1, dtype=torch.float64, device="cuda")
     u_in = torch.from_numpy(np.ascontiguousarray(ml.ghosted)).float().cuda().reshape(-1)
     d_dh = torch.from_numpy(np.ascontiguousarray(ml.dh)).cuda()
+    ctx.tvd_reserve(len(ml.dh))
     ctx.tvd_max_signal_speed(tvd.Batch(tvd.TVD_F32, len(ml.dh), 8, d_dh=d_dh), u_in,
                              tvd.TVD_LAYOUT_GHOSTED, GAMMA, sm)
     dt = CFL * (1.0 / ml.base) / float(sm.item())
@@ -634,43 +718,93 @@ def run_amr_fill(ctx, reps=20):
     return res
 
 
-def cpu_baseline(grid32, budget_s=15.0):
-    """The FP64 oracle (as it stands) on the host cores over a bounded sample
-    of the same workload: whole steps of the 256^3 grid as 32768 patches of
-    8^3 (periodic ghost fill in numpy, then the C advance), repeated until the
-    time budget is used; only the advance is timed, like the GPU's kernel."""
+def host_cpu():
+    """Model name and logical CPU count of the host, and the OpenMP thread
+    count the oracle is run with."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "omp_num_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+
+
+def native_oracle():
+    """Build the C oracle for this host's CPU (-O3 -march=native) into a
+    temporary directory and bind it; the arithmetic is the same C source
+    with FP contraction off.  Returns the compile flags used, or the shipped
+    build's if gcc is not usable here."""
+    import tempfile
+
     import oracle
-    g = grid32.astype(np.float64)
-    dh = 1.0 / N_GRID
-    steps, adv, threads, t_all = 0, 0.0, 1, time.perf_counter()
-    dt = None
-    while adv < budget_s and steps < 20:
-        if steps % 2 == 0:
-            dt = CFL * dh / oracle.max_signal_speed(g, GAMMA)
-        blocks = oracle.periodic_ghosted_blocks(g, 8)
-        c = oracle.Counts()
-        t = time.perf_counter()
-        out = oracle.advance_blocks(blocks, steps % 2, dt, dh, GAMMA, counts=c)
-        adv += time.perf_counter() - t
-        threads = c.threads
-        g = oracle.assemble_blocks(out, g.shape)
-        steps += 1
-    # one host thread (the paper compares one GPU with one CPU core): one step
-    # of a 4096-patch slice of the same state
-    blocks = oracle.periodic_ghosted_blocks(g, 8)[:4096]
-    oracle.set_threads(1)
+    out = os.path.join(tempfile.mkdtemp(prefix="oracle_native_"), "liboracle.so")
+    try:
+        oracle.build(out=out, native=True)
+        oracle.use_library(out)
+        return " ".join(oracle.CFLAGS_NATIVE)
+    except Exception as e:  # the shipped build stays in use
+        log(f"bench: native oracle build failed ({e}); using the shipped build")
+        return " ".join(oracle.CFLAGS)
+
+
+def sample_ghosted_blocks(grid, n, picks):
+    """Ghosted blocks (edge n + 6) of the periodic grid for the x-fastest
+    block indices `picks`, cut straight from the grid with periodic wrap."""
+    _, Nz, Ny, Nx = grid.shape
+    nbx, nby = Nx // n, Ny // n
+    out = np.empty((len(picks), 5, n + 6, n + 6, n + 6))
+    for i, b in enumerate(picks):
+        bx, by, bz = b % nbx, (b // nbx) % nby, b // (nbx * nby)
+        iz = np.arange(bz * n - 3, bz * n + n + 3) % Nz
+        iy = np.arange(by * n - 3, by * n + n + 3) % Ny
+        ix = np.arange(bx * n - 3, bx * n + n + 3) % Nx
+        out[i] = grid[(slice(None),) + np.ix_(iz, iy, ix)]
+    return out
+
+
+def cpu_baseline(grid, p_floor, budget_s=15.0, sample_blocks=16384):
+    """The FP64 oracle (as it stands, built for this host) on the host cores
+    over a bounded sample of the same workload: `sample_blocks` 8^3 patches
+    of the initial state with their ghost zones cut from the periodic grid,
+    advanced by one step (alternating xyz / zyx) at a time, repeated until
+    `budget_s` seconds of advance have run; then one step of 2048 of them on
+    one thread.  Only the advance is timed, like the GPU's kernel."""
+    import oracle
+    flags = native_oracle()
+    N = grid.shape[3]
+    dh = 1.0 / N
+    nb_all = (N // 8) ** 3
+    picks = np.sort(np.random.default_rng(SEED).choice(nb_all, size=min(sample_blocks, nb_all),
+                                                       replace=False))
+    blocks = sample_ghosted_blocks(grid.astype(np.float64), 8, picks)
+    dt = CFL * dh / oracle.max_signal_speed(grid.astype(np.float64), GAMMA, p_floor)
+    threads = host_cpu()["omp_num_threads"]
+    oracle.set_threads(threads)
+    steps = 0
     c = oracle.Counts()
-    t = time.perf_counter()
-    oracle.advance_blocks(blocks, 0, dt, dh, GAMMA, counts=c)
-    t1 = time.perf_counter() - t
-    oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
-    return {"value": steps * N_GRID ** 3 / adv, "unit": "cell-updates/s", "cores": threads,
+    while c.seconds < budget_s and steps < 50:
+        oracle.advance_blocks(blocks, steps % 2, dt, dh, GAMMA, p_floor, counts=c)
+        steps += 1
+    used, adv = c.threads, c.seconds
+    oracle.set_threads(1)
+    c1 = oracle.Counts()
+    oracle.advance_blocks(blocks[:2048], 0, dt, dh, GAMMA, p_floor, counts=c1)
+    t1 = c1.seconds
+    oracle.set_threads(threads)
+    cpu = host_cpu()
+    return {"value": steps * len(picks) * 512 / adv, "unit": "cell-updates/s", "cores": used,
             "kind": "oracle",
-            "sample": f"{steps} steps of the full 256^3 workload (32768 8^3 patches), FP64, "
-                      f"advance {adv:.1f} s timed of {time.perf_counter() - t_all:.1f} s "
-                      f"(ghost fill and CFL speed in numpy not timed)",
-            "single_thread": {"value": 4096 * 512 / t1, "unit": "cell-updates/s", "cores": c.threads,
-                              "sample": "one step of 4096 of the 32768 patches, FP64"}}
+            "sample": f"{len(picks)} of the {nb_all} 8^3 patches of the initial state (seeded "
+                      f"pick, ghost zones cut from the periodic grid), one FP64 step repeated "
+                      f"{steps} times, {adv:.1f} s inside the C advance timed (ghost cut, "
+                      f"marshalling and CFL speed not timed)",
+            "host": cpu, "oracle_cflags": flags,
+            "single_thread": {"value": 2048 * 512 / t1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": "one step of 2048 of the sampled patches, FP64"}}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=5):
@@ -694,181 +828,286 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
             "ms": ms}
 
 
+def whole_pairs(k: int, least: int) -> int:
+    """Steps come in xyz/zyx pairs sharing one dt: round up to a whole pair."""
+    return max(least, k + (k % 2))
+
+
+def l1_norms(a, b):
+    """Relative L1 per variable of a against reference b, both (5, ...):
+    rho and e on their own norm, momentum on the sum of rho c_s (and on its
+    own norm)."""
+    nrm = {}
+    for k, nm in enumerate(["rho", "m_x", "m_y", "m_z", "e"]):
+        nrm[nm] = float(np.abs(a[k] - b[k]).sum() / np.abs(b[k]).sum())
+    rho = b[0]
+    kin = 0.5 * (b[1] ** 2 + b[2] ** 2 + b[3] ** 2) / rho
+    cs = np.sqrt(GAMMA * np.maximum((GAMMA - 1) * (b[4] - kin), 0) / rho)
+    scale = (rho * cs).sum()
+    for k, nm in enumerate(["m_x", "m_y", "m_z"]):
+        nrm[nm + "_scale"] = float(np.abs(a[k + 1] - b[k + 1]).sum() / scale)
+    return nrm
+
+
+def download_grid(dev, shape):
+    """The device state as a (5, Nz, Ny, Nx) FP64 grid."""
+    from paper_0907_3390_amd import layout
+    return layout.blocks_to_grid(np.stack(dev.download()).astype(np.float64), shape, dev.bs.perm)
+
+
+def compare_fp32_fp64(ctx, g32, grid, steps, warmup, p_floor, sums, label):
+    """The plain FP64 per-patch kernel over the same steps from the same
+    FP32-rounded state, and the L1 error of the FP32 result g32 against it."""
+    import torch
+    from paper_0907_3390_amd import layout, tvd
+    N = grid.shape[3]
+    log(f"bench: {label}: FP64 plain, edge 8, {warmup}+{steps}+{steps} steps")
+    dev64, r64 = run_gpu(ctx, grid, 8, torch.float64, tvd.TVD_KERNEL_PLAIN, steps, warmup,
+                         p_floor=p_floor, sums=sums)
+    v64 = N ** 3 * steps / (r64["total_ms"] * 1e-3)
+    g64 = download_grid(dev64, (5, N, N, N))
+    del dev64
+    torch.cuda.empty_cache()
+    nrm = l1_norms(g32, g64)
+    nrm["after_steps"] = r64["steps_run"]
+    res = {"value": v64, "unit": "cell-updates/s", "ms_per_step": r64["total_ms"] / steps,
+           "avg_launch_ms": float(np.mean(r64["adv_ms"])), "blocks": r64["blocks"],
+           "block_edge": 8, "health": {"floored": r64["floored"],
+                                       "nonphysical": r64["nonphysical"]}}
+    log(f"bench: {label}: FP64 plain {v64 / 1e9:.3f} G cell-updates/s; relL1 {nrm}")
+    return res, nrm, g64
+
+
+def headline_record(r, cells, steps, n, label, workload, stream_planes=None):
+    """Throughput, roofline and health of one FP32 gathering-advance run
+    (per-block kernel, or streamed over chains of `stream_planes` planes)."""
+    value = cells * steps / (r["total_ms"] * 1e-3)
+    nb = r["blocks"]
+    # algorithmic bytes of one launch: the ghosted block in (gathered from the
+    # neighbours' interiors) and the interior out
+    bytes_launch = nb * ((n + 6) ** 3 + n ** 3) * 5 * 4
+    adv_avg_ms = float(np.mean(r["adv_ms"]))
+    achieved = bytes_launch / (adv_avg_ms * 1e-3) / 1e9
+    if stream_planes:
+        flops_launch = int(cells * flops_per_cell_stream(stream_planes))
+    else:
+        flops_launch = nb * flops_per_block(n)
+    tflops = flops_launch / (adv_avg_ms * 1e-3) / 1e12
+    rec = {"value": value, "unit": "cell-updates/s", "ms_per_step": r["total_ms"] / steps,
+           "workload": workload, "blocks": nb, "block_edge": n,
+           "advance_cell_updates_per_s": cells / (adv_avg_ms * 1e-3),
+           "avg_launch_ms": adv_avg_ms, "algorithmic_flops_per_launch": flops_launch,
+           "algorithmic_bytes_per_launch": bytes_launch,
+           "TFLOPs": tflops, "GBs": achieved,
+           "variant": r.get("variant"),
+           "health": {"floored": r["floored"], "nonphysical": r["nonphysical"]}}
+    log(f"bench: {label}: {value / 1e9:.2f} G cell-updates/s, advance {adv_avg_ms:.3f} ms "
+        f"({achieved:.0f} GB/s, {tflops:.1f} TFLOP/s)")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 512^3 headline run (for profiling)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparisons")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-variant tuner")
-    ap.add_argument("--no-amr-fill", action="store_true",
-                    help="skip the coarse-fine ghost-fill throughput")
-    ap.add_argument("--no-multilevel", action="store_true",
-                    help="skip the multi-level (18 152 patches) throughput")
-    ap.add_argument("--no-closing", action="store_true",
-                    help="skip the closing step (flux records, restriction, flux correction)")
-    ap.add_argument("--no-poisson", action="store_true",
-                    help="skip the red-black SOR Poisson solver on patch groups")
-    ap.add_argument("--no-uneven", action="store_true",
-                    help="skip the uneven-batch (4000 mixed boxes) throughput")
-    ap.add_argument("--edge", type=int, default=16, help="block edge of the FP32 batched run")
-    ap.add_argument("--no-gather", action="store_true",
-                    help="headline run with a separate ghost fill instead of the gathering advance")
+    ap.add_argument("--no-config2", action="store_true", help="skip the 256^3 lognormal runs")
+    ap.add_argument("--extras", action="store_true",
+                    help="also run the ghost fill, multi-level, closing, nested, Poisson, "
+                         "gravity and uneven-batch measurements")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    if args.steps % 2 or args.warmup % 2:
-        sys.exit("--steps and --warmup must be even (steps come in xyz/zyx pairs)")
+    steps = whole_pairs(args.steps, 2)
+    warmup = whole_pairs(args.warmup, 2)
+    if (steps, warmup) != (args.steps, args.warmup):
+        log(f"bench: steps/warmup {args.steps}/{args.warmup} rounded up to whole xyz/zyx pairs: "
+            f"{steps}/{warmup}")
 
     import torch
     from paper_0907_3390_amd import tvd
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log(f"bench: building the 256^3 initial state (seed {SEED})")
-    grid32 = make_ic()
     ctx = tvd.Context(0)
-    cells = N_GRID ** 3
+    t_start = time.perf_counter()
 
-    gather = not args.no_gather
-    log(f"bench: FP32 batched, edge {args.edge}, gather={gather}, {args.warmup}+{args.steps} steps")
-    dev32, r32 = run_gpu(ctx, grid32, args.edge, torch.float32, tvd.TVD_KERNEL_AUTO,
-                         args.steps, args.warmup, gather=gather, tune=not args.no_tune)
-    ms_step = r32["total_ms"] / args.steps
-    value = cells * args.steps / (r32["total_ms"] * 1e-3)
-    n = args.edge
-    nb = r32["blocks"]
-    # algorithmic bytes of one launch: the ghosted block in (gathered from the
-    # neighbours' interiors, or read from a ghosted copy) and the interior out
-    bytes_launch = nb * ((n + 6) ** 3 + n ** 3) * 5 * 4
-    adv_avg_ms = float(np.mean(r32["adv_ms"]))
-    achieved = bytes_launch / (adv_avg_ms * 1e-3) / 1e9
-    flops_launch = nb * flops_per_block(n)
-    tflops = flops_launch / (adv_avg_ms * 1e-3) / 1e12
-    traffic, traffic_note = (measured_traffic(r32.get("variant")) if (n == 16 and gather)
-                             else (None, "not profiled"))
+    # ---- headline: 512^3 point blast, FP32 patch groups, FP64 sums every step
+    log(f"bench: building the {N_BLAST}^3 point-blast state (seed {SEED_BLAST})")
+    grid5 = make_blast()
+    cells5 = N_BLAST ** 3
+    n = 16
+    wl5 = (f"{N_BLAST}^3 periodic grid = {(N_BLAST // 8) ** 3} patches of 8^3 run as "
+           f"{(N_BLAST // 16) ** 3} Morton-ordered 2^3 patch groups of 16^3; point blast (energy 1 "
+           f"in the central 2^3 cells) on a lognormal background sigma_ln=0.5 at rest, P=1e-5, "
+           f"gamma=5/3, CFL 0.5, p_floor 1e-10, seed {SEED_BLAST}")
+    log(f"bench: headline FP32, edge {n}, streamed advance, {warmup}+{steps}+{steps} steps, "
+        f"sums every step")
+    dev5, r5 = run_gpu(ctx, grid5, n, torch.float32, tvd.TVD_KERNEL_AUTO, steps, warmup,
+                       gather=True, tune=not args.no_tune, p_floor=P_FLOOR_BLAST, sums=True,
+                       stream=True)
+    planes5 = dev5.chain_len * n
+    head = headline_record(r5, cells5, steps, n, "512^3 blast FP32 streamed", wl5,
+                           stream_planes=planes5)
+    value = head["value"]
+    traffic, traffic_note = measured_traffic(r5.get("variant"))
+    # conservation drift of the fused FP64 sums after all steps run
+    s0, s1 = np.array(r5["sums0"]), np.array(r5["sums"])
+    drift = {nm: float(abs(s1[k] - s0[k]) / abs(s0[k]))
+             for k, nm in enumerate(["rho", "m_x", "m_y", "m_z", "e"]) if k in (0, 4)}
+    drift["momentum_over_mass"] = float(np.max(np.abs(s1[1:4] - s0[1:4])) / abs(s0[0]))
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "steps": steps, "warmup": warmup, "steps_requested": args.steps,
+        "warmup_requested": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "256^3 periodic grid = 32768 patches of 8^3 (run as 4096 "
-                               "2^3 patch groups of 16^3), lognormal rho sigma_ln=1, Gaussian "
-                               "v sigma=0.3 c_s, P=1, gamma=5/3, CFL 0.5, seed 2024"
-                               if n == 16 else
-                               "256^3 periodic grid = 32768 patches of 8^3, lognormal rho "
-                               "sigma_ln=1, Gaussian v sigma=0.3 c_s, P=1, gamma=5/3, CFL 0.5, "
-                               "seed 2024",
-                   "cells": cells, "blocks": nb, "block_edge": n, "precision": "fp32",
-                   "ghost_zones": "gathered inside the advance" if gather else "separate fill",
+        "config": {"workload": wl5, "cells": cells5, "blocks": head["blocks"], "block_edge": n,
+                   "precision": "fp32 state and arithmetic; fp64 dt, signal speed and "
+                                "compensated conservation sums",
+                   "ghost_zones": "gathered from the 26 neighbours inside the advance",
+                   "schedule": f"streamed: chains of {dev5.chain_len} blocks along the axis swept "
+                               f"last (z forward, x backward), 16 x 16 tiles, slabs of 8 planes",
+                   "step": "device dt (even steps), advance, fused signal speed (odd steps), "
+                           "fused FP64 compensated sums (every step)",
                    "block_order": "Morton curve"},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "traffic_source": traffic_note,
-                     "kernel": f"k_batched<float,{n}>" + (" gather" if gather else ""),
-                     "avg_launch_ms": adv_avg_ms,
-                     "algorithmic_flops_per_launch": flops_launch,
-                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS,
-                             "algorithmic_bytes_per_launch": bytes_launch}},
-        "advance_cell_updates_per_s": cells / (adv_avg_ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": head["TFLOPs"], "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": head["TFLOPs"] / FP32_PEAK_TFLOPS,
+                     "traffic": traffic, "traffic_source": traffic_note,
+                     "peak_note": "FP32 vector without packed FP32 (packed instructions are off "
+                                  "in this build); 157.3 TFLOP/s with packed FP32",
+                     "frac_of_packed_peak": head["TFLOPs"] / 157.3,
+                     "kernel": f"k_stream<float,{n}>",
+                     "avg_launch_ms": head["avg_launch_ms"],
+                     "algorithmic_flops_per_launch": head["algorithmic_flops_per_launch"],
+                     "algorithmic_flops_per_cell_update": flops_per_cell_stream(planes5),
+                     "flops_note": "the streamed schedule's own region-rule work (first two "
+                                   "sweeps on 22 + 16 pencils per plane and tile, third sweep "
+                                   "once per cell); the per-block schedule on 16^3 groups needs "
+                                   f"{flops_per_block(16) / 4096:.0f} flop per cell-update",
+                     "hbm": {"achieved": head["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": head["GBs"] / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"]}},
+        "advance_cell_updates_per_s": head["advance_cell_updates_per_s"],
         "timing": "steps replayed as a HIP graph of one xyz/zyx pair; advance duration from "
-                  "HIP events around eager launches of the same steps",
-        "variant": r32.get("variant"),
-        "health": {"floored": r32["floored"], "nonphysical": r32["nonphysical"]},
+                  "HIP events on the launch stream around eager launches of the same steps",
+        "variant": head["variant"], "health": head["health"],
+        "conservation_drift_after_run": drift,
     }
-    log(f"bench: FP32 {value / 1e9:.2f} G cell-updates/s, advance {adv_avg_ms:.3f} ms "
-        f"({achieved:.0f} GB/s, {tflops:.1f} TFLOP/s)")
+    g32 = download_grid(dev5, grid5.shape) if not args.headline_only else None
+    del dev5
+    torch.cuda.empty_cache()
+    # the per-block gathering advance on the same state and step, for comparison
+    if not args.headline_only:
+        log("bench: 512^3 blast FP32, per-block gathering advance for comparison")
+        dpb, rpb = run_gpu(ctx, grid5, n, torch.float32, tvd.TVD_KERNEL_AUTO, steps, warmup,
+                           gather=True, tune=not args.no_tune, p_floor=P_FLOOR_BLAST, sums=True)
+        pb = headline_record(rpb, cells5, steps, n, "512^3 blast FP32 per-block", wl5)
+        same = np.array_equal(download_grid(dpb, grid5.shape), g32)
+        pb["bitwise_equal_to_streamed"] = bool(same)
+        out["per_block_gather"] = pb
+        out["speedup_streamed_vs_per_block"] = value / pb["value"]
+        del dpb
+        torch.cuda.empty_cache()
     out["hbm_copy_measured"] = copy_bandwidth()
     out["roofline"]["hbm"]["frac_of_measured_copy"] = (
-        achieved / out["hbm_copy_measured"]["read_plus_write_GBs"])
+        head["GBs"] / out["hbm_copy_measured"]["read_plus_write_GBs"])
     log(f"bench: plain 1 GiB copy {out['hbm_copy_measured']['read_plus_write_GBs']:.0f} GB/s")
+    if not args.no_fp64 and not args.headline_only:
+        res64, nrm, g64 = compare_fp32_fp64(ctx, g32, grid5, steps, warmup, P_FLOOR_BLAST, True,
+                                            "512^3 blast")
+        del g64
+        out["fp64_plain"] = res64
+        out["speedup_fp32_batched_vs_fp64_plain"] = value / res64["value"]
+        out["l1_vs_fp64"] = nrm
+    del g32
+    torch.cuda.empty_cache()
 
-    if not args.no_fp64:
-        log(f"bench: FP64 plain, edge 8, {args.warmup}+{args.steps} steps")
-        s32 = np.stack(dev32.download()).astype(np.float64)
-        dev32_perm = dev32.bs.perm
-        del dev32
+    # ---- 256^3 rough lognormal grid: FP32 vs FP64 plain, FP64 batched, FP32 on patches
+    if not args.no_config2 and not args.headline_only:
+        grid2 = make_ic()
+        wl2 = ("256^3 periodic grid = 32768 patches of 8^3, lognormal rho sigma_ln=1, Gaussian v "
+               "sigma=0.3 c_s, P=1, gamma=5/3, CFL 0.5, seed 2024")
+        log("bench: 256^3 lognormal FP32, edge 16, streamed advance")
+        dev2, r2 = run_gpu(ctx, grid2, 16, torch.float32, tvd.TVD_KERNEL_AUTO, steps, warmup,
+                           gather=True, tune=not args.no_tune, sums=True, stream=True)
+        c2 = headline_record(r2, N_GRID ** 3, steps, 16, "256^3 lognormal FP32 streamed",
+                             wl2 + " (run as 4096 2^3 patch groups of 16^3)",
+                             stream_planes=dev2.chain_len * 16)
+        g2_32 = download_grid(dev2, grid2.shape)
+        del dev2
         torch.cuda.empty_cache()
-        dev64, r64 = run_gpu(ctx, grid32, 8, torch.float64, tvd.TVD_KERNEL_PLAIN, args.steps,
-                             args.warmup)
-        v64 = cells * args.steps / (r64["total_ms"] * 1e-3)
-        a64 = float(np.mean(r64["adv_ms"]))
-        from paper_0907_3390_amd import layout
-        s64 = np.stack(dev64.download())
-        g32 = layout.blocks_to_grid(s32, (5, N_GRID, N_GRID, N_GRID), dev32_perm)
-        g64 = layout.blocks_to_grid(s64, (5, N_GRID, N_GRID, N_GRID), dev64.bs.perm)
-        del dev64, s64
-        nrm = {}
-        for k, nm in enumerate(["rho", "m_x", "m_y", "m_z", "e"]):
-            d = np.abs(g32[k] - g64[k]).sum()
-            nrm[nm] = d / np.abs(g64[k]).sum()
-        rho = g64[0]
-        kin = 0.5 * (g64[1] ** 2 + g64[2] ** 2 + g64[3] ** 2) / rho
-        cs = np.sqrt(GAMMA * np.maximum((GAMMA - 1) * (g64[4] - kin), 0) / rho)
-        scale = (rho * cs).sum()
-        for k, nm in enumerate(["m_x", "m_y", "m_z"]):
-            nrm[nm + "_scale"] = np.abs(g32[k + 1] - g64[k + 1]).sum() / scale
-        out["fp64_plain"] = {"value": v64, "unit": "cell-updates/s", "ms_per_step": r64["total_ms"] / args.steps,
-                             "avg_launch_ms": a64, "blocks": r64["blocks"], "block_edge": 8}
-        out["speedup_fp32_batched_vs_fp64_plain"] = value / v64
-        out["l1_vs_fp64"] = {k: float(v) for k, v in nrm.items()}
-        out["l1_vs_fp64"]["after_steps"] = max(args.warmup, 2) + 2 * args.steps
-        log(f"bench: FP64 plain {v64 / 1e9:.3f} G cell-updates/s; relL1 {nrm}")
-        # the other two points of the comparison: the batched kernel in FP64
-        # (8^3 patches, gathering) and in FP32 on single 8^3 patches
+        log("bench: 256^3 lognormal FP32, per-block gathering advance")
+        dpb, rpb = run_gpu(ctx, grid2, 16, torch.float32, tvd.TVD_KERNEL_AUTO, steps, warmup,
+                           gather=True, tune=not args.no_tune, sums=True)
+        c2["per_block_gather"] = headline_record(rpb, N_GRID ** 3, steps, 16,
+                                                 "256^3 lognormal FP32 per-block", wl2)
+        c2["per_block_gather"]["bitwise_equal_to_streamed"] = bool(
+            np.array_equal(download_grid(dpb, grid2.shape), g2_32))
+        del dpb
         torch.cuda.empty_cache()
-        others = {}
-        for name, dtype, n in (("fp64_batched", torch.float64, 8), ("fp32_batched_edge8", torch.float32, 8)):
-            log(f"bench: {name}, edge {n}, {args.warmup}+{args.steps} steps")
-            dv, rr = run_gpu(ctx, grid32, n, dtype, tvd.TVD_KERNEL_AUTO, args.steps, args.warmup,
-                             gather=True, tune=not args.no_tune)
-            vv = cells * args.steps / (rr["total_ms"] * 1e-3)
-            others[name] = {"value": vv, "unit": "cell-updates/s",
-                            "ms_per_step": rr["total_ms"] / args.steps,
-                            "avg_launch_ms": float(np.mean(rr["adv_ms"])), "blocks": rr["blocks"],
-                            "block_edge": n, "variant": rr.get("variant")}
-            if dtype == torch.float64:
-                gb = layout.blocks_to_grid(np.stack(dv.download()), (5, N_GRID, N_GRID, N_GRID),
-                                           dv.bs.perm)
-                others[name]["max_rel_diff_vs_fp64_plain"] = float(
-                    max(np.abs(gb[k] - g64[k]).max() / np.abs(g64[k]).max() for k in range(5)))
-            del dv
-            torch.cuda.empty_cache()
-            log(f"bench: {name} {vv / 1e9:.3f} G cell-updates/s")
-        out.update(others)
-    if not args.no_amr_fill:
+        if not args.no_fp64:
+            res64, nrm, g64 = compare_fp32_fp64(ctx, g2_32, grid2, steps, warmup, 0.0, True,
+                                                "256^3 lognormal")
+            c2["fp64_plain"] = res64
+            c2["speedup_fp32_batched_vs_fp64_plain"] = c2["value"] / res64["value"]
+            c2["l1_vs_fp64"] = nrm
+            for name, dtype, e, strm in (("fp64_streamed_edge16", torch.float64, 16, True),
+                                         ("fp64_batched", torch.float64, 8, False),
+                                         ("fp32_batched_edge8", torch.float32, 8, False)):
+                log(f"bench: 256^3 lognormal {name}, edge {e}")
+                dv, rr = run_gpu(ctx, grid2, e, dtype, tvd.TVD_KERNEL_AUTO, steps, warmup,
+                                 gather=True, tune=not args.no_tune, sums=True, stream=strm)
+                c2[name] = {"value": N_GRID ** 3 * steps / (rr["total_ms"] * 1e-3),
+                            "unit": "cell-updates/s", "ms_per_step": rr["total_ms"] / steps,
+                            "avg_launch_ms": float(np.mean(rr["adv_ms"])),
+                            "blocks": rr["blocks"], "block_edge": e, "variant": rr.get("variant")}
+                if dtype == torch.float64:
+                    from paper_0907_3390_amd import layout
+                    gb = layout.blocks_to_grid(np.stack(dv.download()), g64.shape, dv.bs.perm)
+                    c2[name]["max_rel_diff_vs_fp64_plain"] = float(
+                        max(np.abs(gb[k] - g64[k]).max() / np.abs(g64[k]).max() for k in range(5)))
+                del dv
+                torch.cuda.empty_cache()
+                log(f"bench: {name} {c2[name]['value'] / 1e9:.3f} G cell-updates/s")
+            del g64
+        del g2_32
+        out["lognormal_256cube"] = c2
+        torch.cuda.empty_cache()
+
+    if args.extras and not args.headline_only:
+        grid2 = make_ic()
         log("bench: coarse-fine ghost fill")
-        torch.cuda.empty_cache()
         out["amr_ghost_fill"] = run_amr_fill(ctx)
-    if not args.no_multilevel or not args.no_closing:
         from paper_0907_3390_amd import workloads as wl
         log("bench: building the multi-level hierarchy")
         ml = wl.multilevel()
-    if not args.no_multilevel:
         log("bench: multi-level batch")
         torch.cuda.empty_cache()
         out["multilevel_batch"] = run_multilevel(ctx, ml)
-    if not args.no_closing:
         log("bench: closing step on the multi-level hierarchy")
         torch.cuda.empty_cache()
         out["closing_step"] = run_closing(ctx, ml)
         log("bench: nested sub-cycled step on the multi-level hierarchy")
         torch.cuda.empty_cache()
         out["nested_subcycled_step"] = run_nested(ctx, ml)
-    if not args.no_poisson:
         log("bench: Poisson SOR on patch groups")
         torch.cuda.empty_cache()
         out["poisson_sor"] = run_poisson(ctx)
-        out["gravity_operator"] = run_gravity(ctx, grid32)
-    if not args.no_uneven:
+        out["gravity_operator"] = run_gravity(ctx, grid2.astype(np.float32))
         log("bench: uneven batch of 4000 boxes")
         torch.cuda.empty_cache()
         out["uneven_batch"] = run_uneven(ctx)
-    if not args.no_cpu_baseline:
-        log("bench: FP64 oracle on the host cores (bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(grid32)
+    out["gpu_wall_s"] = time.perf_counter() - t_start
+
+    if not args.no_cpu_baseline and not args.headline_only:
+        log("bench: FP64 oracle on the host cores (bounded sample of the 512^3 blast)")
+        out["cpu_baseline"] = cpu_baseline(grid5, P_FLOOR_BLAST)
         cb = out["cpu_baseline"]
         log(f"bench: oracle {cb['value'] / 1e6:.2f} M cell-updates/s on {cb['cores']} threads, "
             f"{cb['single_thread']['value'] / 1e6:.2f} M on one")

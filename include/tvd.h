@@ -75,7 +75,10 @@ typedef struct tvd_ctx tvd_ctx;
 /*
  * A batch of blocks.  Every block b has an interior edge e_b (8 or 16), a
  * time step dt_b and a zone size dh_b.
- *   edge      uniform interior edge when d_edge == NULL.
+ *   edge      uniform interior edge when d_edge == NULL: 8 or 16; also 32
+ *             for tvd_patch_advance_stream, tvd_max_signal_speed,
+ *             tvd_dt_from_speed, tvd_conservation_sums and tvd_fill_ghosts
+ *             (the other entry points: TVD_ERR_INVALID_ARG).
  *   d_edge    [n_blocks] device int32 edges, or NULL.  When non-NULL the
  *             offsets below are required.
  *   d_in_off  [n_blocks] device int64: element offset of block b's ghosted
@@ -112,9 +115,17 @@ int tvd_destroy(tvd_ctx *ctx);
 const char *tvd_status_string(int status);
 /* Text of the last failing call on this context (empty if none). */
 const char *tvd_last_error(const tvd_ctx *ctx);
-/* Grow the workspace to hold per-block partials of n_blocks blocks.  Entry
- * points grow it on demand, but not while `stream` is being captured into a
- * graph: reserve the largest batch before capturing.  Synchronous. */
+/* Grow the workspace to hold per-block partials (and the persistent kernel's
+ * work plan) of n_blocks blocks; tvd_create reserves 1024.  This is the only
+ * call that allocates after tvd_create: the advance, signal-speed and sums
+ * entry points never allocate or synchronise, and return TVD_ERR_STATE when
+ * a batch needs more workspace than is reserved (fused d_smax / d_sums, the
+ * persistent kernel, tvd_max_signal_speed, tvd_conservation_sums).
+ * Synchronous (waits for the device before replacing the buffers).  Growing
+ * the workspace retires every graph captured earlier on this context: their
+ * tvd_graph_launch returns TVD_ERR_STATE.  TVD_ERR_STATE during a
+ * tvd_graph_begin / tvd_graph_end capture; no-op if n_blocks is already
+ * reserved. */
 int tvd_reserve(tvd_ctx *ctx, int n_blocks);
 
 /* ---- kernel variants (launch shape and LDS layout) ------------------------ */
@@ -171,8 +182,7 @@ int tvd_autotune(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
  *            With mixed edges a block whose d_edge entry is neither 8 nor
  *            16 is not advanced (the persistent kernel also counts it once
  *            as non-physical).  The persistent kernel uses workspace of
- *            n_blocks entries: reserve it (tvd_reserve) before capturing
- *            such an advance.
+ *            n_blocks entries (tvd_reserve; else TVD_ERR_STATE).
  *   d_smax   optional (NULL = skip): receives max over the output interior of
  *            c_s + max(|v_x|, |v_y|, |v_z|) in FP64 (Eq. CFL), fused.
  *   d_sums   optional (NULL = skip): receives the five sums over the output
@@ -205,10 +215,58 @@ int tvd_patch_advance_gather(tvd_ctx *ctx, const tvd_batch *batch, const int32_t
                              double *d_sums, void *stream);
 
 /*
+ * Chains of blocks for the streamed advance: chain c is the list
+ * d_blocks[d_start[c] .. d_start[c+1]) (device arrays), each block the
+ * neighbour of the one before at +1 along the axis that the step sweeps
+ * last (z for TVD_XYZ, x for TVD_ZYX: neighbour region 22 resp. 14 of
+ * d_nbr).  Every block should belong to exactly one chain; at most 64
+ * blocks per chain.
+ */
+typedef struct {
+    int32_t n_chains;
+    int32_t n_members;        /* entries of d_blocks                           */
+    const int32_t *d_start;   /* [n_chains + 1], d_start[0] = 0                 */
+    const int32_t *d_blocks;  /* [n_members]                                    */
+} tvd_chains;
+
+/* flags of tvd_patch_advance_stream besides TVD_KERNEL_AUTO */
+enum { TVD_STREAM_WHOLE_B = 16 };  /* second sweep in whole pencils (default: halves) */
+
+/*
+ * The same step as tvd_patch_advance_gather (interior blocks in, ghost
+ * zones gathered from the 26 neighbours named by d_nbr, interior blocks
+ * out; the same arithmetic per cell, so bit-identical results), organised
+ * for the MI355X: one workgroup per chain and 16 x 16 tile of the block
+ * face (1 tile for edge 16, 4 for edge 32) runs the first two sweeps of a
+ * slab of 8 planes at a time in LDS and carries the third sweep's 1-D
+ * update along the whole chain in registers.  This is the per-cell work of
+ * Sec. 3.1's solver with the third sweep's ghost-zone work of every block
+ * but the chain's ends removed; the region rule (three ghost planes on each
+ * side) applies to the chain as a whole.
+ *   batch    uniform edge 16 or 32 (d_edge NULL; else TVD_ERR_UNSUPPORTED),
+ *            TVD_F32 or TVD_F64.
+ *   chains   chains along z for TVD_XYZ, along x for TVD_ZYX.  A chain whose
+ *            blocks are not consecutive along that axis, or whose blocks
+ *            lack a neighbour of the same edge, or differ in dt or dh, or
+ *            has more than 64 blocks, is not advanced: its output is left
+ *            untouched and its cells are counted as non-physical.
+ *   flags    TVD_KERNEL_AUTO or TVD_STREAM_WHOLE_B.
+ *   d_smax, d_sums  as for tvd_patch_advance, over the chains' blocks; they
+ *            use n_blocks * (1 or 4) workspace entries (tvd_reserve; else
+ *            TVD_ERR_STATE).
+ * Asynchronous on stream; capture-safe.
+ */
+int tvd_patch_advance_stream(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
+                             const tvd_chains *chains, const void *d_u_in, void *d_u_out,
+                             int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                             double *d_smax, double *d_sums, void *stream);
+
+/*
  * Eq. (CFL) signal speed: d_smax[0] = max over the interior cells of all
  * blocks of c_s + max(|v_x|, |v_y|, |v_z|), with c_s from max(P, p_floor);
  * evaluated in FP64 from the stored values.  layout selects ghosted or
- * interior blocks (ghost cells are skipped).
+ * interior blocks (ghost cells are skipped).  Uses n_blocks entries of the
+ * workspace (tvd_reserve; else TVD_ERR_STATE).
  */
 int tvd_max_signal_speed(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u,
                          int32_t layout, double gamma, double p_floor,
@@ -225,7 +283,8 @@ int tvd_dt_from_speed(tvd_ctx *ctx, const tvd_batch *batch, const double *d_smax
 
 /*
  * Conservation sums: d_sums[k] = sum over blocks b and interior cells of
- * u_k * dh_b^3, k = 0..4, FP64, Neumaier-compensated, fixed order.
+ * u_k * dh_b^3, k = 0..4, FP64, Neumaier-compensated, fixed order.  Uses
+ * n_blocks entries of the workspace (tvd_reserve; else TVD_ERR_STATE).
  */
 int tvd_conservation_sums(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u,
                           int32_t layout, double *d_sums, void *stream);
@@ -472,7 +531,9 @@ typedef struct tvd_graph tvd_graph;
 int tvd_graph_begin(tvd_ctx *ctx, void *stream);
 /* Stop capturing and instantiate the graph; *out receives the handle. */
 int tvd_graph_end(tvd_ctx *ctx, void *stream, tvd_graph **out);
-/* Replay a recorded sequence on `stream` (asynchronous). */
+/* Replay a recorded sequence on `stream` (asynchronous).  TVD_ERR_STATE, with
+ * nothing launched, when tvd_reserve has replaced the context's workspace
+ * since the capture, or the context has been destroyed. */
 int tvd_graph_launch(tvd_graph *graph, void *stream);
 /* Free a recorded sequence (the caller ensures no replay is in flight). */
 int tvd_graph_destroy(tvd_graph *graph);

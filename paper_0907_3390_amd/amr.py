@@ -36,6 +36,7 @@ class TwoLevelDevice:
         z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
         nc, nf = L.coarse.n_blocks, L.fine.n_blocks
         self.nc, self.nf, self.n = nc, nf, n
+        ctx.tvd_reserve(max(nc, nf))
         self.c_int, self.c_gh, self.c_out = z(nc * 5 * 512), z(nc * 5 * 14 ** 3), z(nc * 5 * 512)
         self.c_half = z(nc * 5 * 512)
         m = n + 6
@@ -131,6 +132,7 @@ class NestedDevice:
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
         self.nb = [b.n_blocks for b in L.blocks]
+        ctx.tvd_reserve(max(self.nb))
         rs = layout.flux_record_size(8)
         self.u = [z(n * 5 * 512) for n in self.nb]
         self.u_new = [z(n * 5 * 512) for n in self.nb]

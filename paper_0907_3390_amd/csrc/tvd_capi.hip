@@ -12,11 +12,23 @@
 
 #include "tvd.h"
 #include "tvd_internal.hpp"
+#include "tvd_stream_params.hpp"
+
+#include <memory>
+
+// Generation of a context's workspace, shared with the graphs captured on
+// it: it changes whenever tvd_reserve replaces the workspace buffers (and
+// when the context is destroyed), so that a graph holding the old pointers
+// is refused instead of replayed into freed memory.
+using WsGeneration = std::shared_ptr<unsigned long long>;
+constexpr unsigned long long kWsGone = ~0ull;
 
 struct tvd_graph {
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  WsGeneration ws_gen;            // the capturing context's generation counter
+  unsigned long long gen = 0;     // its value when the capture ended
 };
 
 struct tvd_ctx {
@@ -27,6 +39,8 @@ struct tvd_ctx {
   double* ws_sums = nullptr;
   unsigned long long* counters = nullptr;
   int ws_blocks = 0;
+  WsGeneration ws_gen = std::make_shared<unsigned long long>(0ull);
+  bool capturing = false;  // between tvd_graph_begin and tvd_graph_end
   // work plan of the persistent launch: list [ws_blocks], count [2], next [8]
   int32_t* plan_list = nullptr;
   int32_t* plan_small = nullptr;  // count[2] then next[8] (as unsigned)
@@ -73,13 +87,12 @@ bool stream_capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
-// Grow the workspace to hold n blocks.  Not allowed while capturing.
-int reserve(tvd_ctx* ctx, int n, hipStream_t s) {
+// Grow the workspace to hold n blocks (tvd_create and tvd_reserve only: the
+// other entry points never allocate).  Replacing the buffers moves the
+// workspace generation on, which retires graphs captured before.
+int reserve(tvd_ctx* ctx, int n) {
   if (n <= ctx->ws_blocks) return TVD_OK;
-  if (stream_capturing(s))
-    return fail(ctx, TVD_ERR_STATE,
-                "workspace for %d blocks must be reserved before stream capture (have %d)", n,
-                ctx->ws_blocks);
+  ++*ctx->ws_gen;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
   (void)hipFree(ctx->ws_smax);
@@ -100,17 +113,28 @@ int reserve(tvd_ctx* ctx, int n, hipStream_t s) {
   return TVD_OK;
 }
 
+// The workspace must already hold n blocks: the hot entry points check, they
+// do not allocate.
+int need_workspace(tvd_ctx* ctx, int n) {
+  if (n <= ctx->ws_blocks) return TVD_OK;
+  return fail(ctx, TVD_ERR_STATE,
+              "the workspace holds %d blocks and this batch has %d: call tvd_reserve first",
+              ctx->ws_blocks, n);
+}
+
 size_t elem_size(int dtype) { return dtype == TVD_F32 ? 4 : 8; }
 
-// Host-side checks of a batch descriptor.
-int check_batch(tvd_ctx* ctx, const tvd_batch* b) {
+// Host-side checks of a batch descriptor.  Edge 32 only where the caller
+// serves it (the streamed advance and the per-cell reductions and fills).
+int check_batch(tvd_ctx* ctx, const tvd_batch* b, bool allow32 = false) {
   if (!b) return fail(ctx, TVD_ERR_INVALID_ARG, "batch is NULL");
   if (b->dtype != TVD_F32 && b->dtype != TVD_F64)
     return fail(ctx, TVD_ERR_INVALID_ARG, "dtype %d is neither TVD_F32 nor TVD_F64", b->dtype);
   if (b->n_blocks < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_blocks %d < 0", b->n_blocks);
   if (b->d_edge == nullptr) {
-    if (b->edge != 8 && b->edge != 16)
-      return fail(ctx, TVD_ERR_INVALID_ARG, "edge %d is not 8 or 16", b->edge);
+    if (b->edge != 8 && b->edge != 16 && !(allow32 && b->edge == 32))
+      return fail(ctx, TVD_ERR_INVALID_ARG, "edge %d is not 8 or 16%s", b->edge,
+                  allow32 ? " or 32" : "");
   } else if (b->d_in_off == nullptr || b->d_out_off == nullptr) {
     return fail(ctx, TVD_ERR_INVALID_ARG, "mixed edges (d_edge) need d_in_off and d_out_off");
   }
@@ -209,7 +233,7 @@ int tvd_create(tvd_ctx** out, int device) {
       hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&ctx->plan_small, 16 * sizeof(int32_t)) != hipSuccess ||
       hipMemset(ctx->plan_small, 0, 16 * sizeof(int32_t)) != hipSuccess ||
-      reserve(ctx, 1024, nullptr) != TVD_OK || hipDeviceSynchronize() != hipSuccess) {
+      reserve(ctx, 1024) != TVD_OK || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(ctx->counters);
     (void)hipFree(ctx->plan_small);
     (void)hipFree(ctx->plan_list);
@@ -224,6 +248,7 @@ int tvd_create(tvd_ctx** out, int device) {
 
 int tvd_destroy(tvd_ctx* ctx) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
+  *ctx->ws_gen = kWsGone;  // graphs captured on this context can no longer run
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
@@ -241,7 +266,10 @@ int tvd_reserve(tvd_ctx* ctx, int n_blocks) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   if (n_blocks < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_blocks %d < 0", n_blocks);
   DeviceGuard g(ctx->device);
-  return reserve(ctx, n_blocks, nullptr);
+  if (n_blocks <= ctx->ws_blocks) return TVD_OK;
+  if (ctx->capturing)
+    return fail(ctx, TVD_ERR_STATE, "tvd_reserve cannot run during a tvd_graph capture");
+  return reserve(ctx, n_blocks);
 }
 
 int tvd_variant_count(void) { return tvd::variant_count(); }
@@ -330,8 +358,15 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   const bool fuse = d_smax || d_sums;
   const bool persistent = flags == TVD_KERNEL_PERSISTENT ||
                           (batch->d_edge && flags == TVD_KERNEL_AUTO);
-  if ((fuse || persistent) && (st = reserve(ctx, batch->n_blocks, s))) return st;
+  if ((fuse || persistent) && (st = need_workspace(ctx, batch->n_blocks))) return st;
   tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
+  hipError_t e;
+  // partials start at zero: a block the kernel does not advance (a missing
+  // neighbour) then adds nothing, whatever an earlier call left there
+  if (d_smax) e = tvd::launch_zero_f64(kp.ws_smax, batch->n_blocks, s);
+  else e = hipSuccess;
+  if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(kp.ws_sums, 10 * (int64_t)batch->n_blocks, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
   kp.nbr = d_nbr;
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
   kp.flux = d_flux;
@@ -343,7 +378,6 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   auto variant = [&](int edge) {
     return d_flux ? default_variant(batch->dtype, edge) : chosen_variant(ctx, batch->dtype, edge);
   };
-  hipError_t e;
   if (flags == TVD_KERNEL_PLAIN) {
     e = tvd::launch_plain_f64(sweep_order, kp, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "plain kernel launch");
@@ -368,11 +402,11 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
     if (e != hipSuccess) return hip_fail(ctx, e, "batched kernel launch");
   }
   if (d_smax) {
-    e = tvd::launch_finalize_max(ctx->ws_smax, batch->n_blocks, d_smax, s);
+    e = tvd::launch_finalize_max(kp.ws_smax, batch->n_blocks, d_smax, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
   }
   if (d_sums) {
-    e = tvd::launch_finalize_sums(ctx->ws_sums, batch->n_blocks, d_sums, s);
+    e = tvd::launch_finalize_sums(kp.ws_sums, batch->n_blocks, d_sums, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
   }
   return TVD_OK;
@@ -397,6 +431,76 @@ int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
   if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
   return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
                       d_sums, stream, d_nbr);
+}
+
+int tvd_patch_advance_stream(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                             const tvd_chains* chains, const void* d_u_in, void* d_u_out,
+                             int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                             double* d_smax, double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch, true);
+  if (st) return st;
+  if ((st = check_gamma(ctx, gamma, p_floor))) return st;
+  if (sweep_order != TVD_XYZ && sweep_order != TVD_ZYX)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "sweep_order %d", sweep_order);
+  if (flags != TVD_KERNEL_AUTO && flags != TVD_STREAM_WHOLE_B)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "flags %d (TVD_KERNEL_AUTO or TVD_STREAM_WHOLE_B)",
+                flags);
+  if (batch->d_edge || (batch->edge != 16 && batch->edge != 32))
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "the streamed advance takes a uniform edge 16 or 32");
+  if (!chains) return fail(ctx, TVD_ERR_INVALID_ARG, "chains is NULL");
+  if (chains->n_chains < 0 || chains->n_members < 0 || chains->n_members > batch->n_blocks)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "%d chains of %d members for %d blocks",
+                chains->n_chains, chains->n_members, batch->n_blocks);
+  if (batch->n_blocks == 0 || chains->n_chains == 0) return TVD_OK;
+  if (!chains->d_start || !chains->d_blocks || !d_nbr)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL chain table or neighbour table");
+  if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
+  if (d_u_in == d_u_out) return fail(ctx, TVD_ERR_ALIAS, "d_u_in == d_u_out");
+  const int quads = batch->edge == 32 ? 4 : 1;
+  if (!batch->d_in_off && !batch->d_out_off) {
+    const size_t n = batch->edge;
+    const size_t len = (size_t)batch->n_blocks * 5 * n * n * n * elem_size(batch->dtype);
+    const char* a = (const char*)d_u_in;
+    const char* b = (const char*)d_u_out;
+    if (a < b + len && b < a + len) return fail(ctx, TVD_ERR_ALIAS, "input and output overlap");
+  }
+  const int64_t parts = (int64_t)batch->n_blocks * quads;
+  if ((d_smax || d_sums) && parts > 0x7fffffff)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "too many blocks for the fused diagnostics");
+  if ((d_smax || d_sums) && (st = need_workspace(ctx, (int)parts))) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, TVD_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
+  kp.nbr = d_nbr;
+  kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
+  tvd::StreamParams sp;
+  sp.start = chains->d_start;
+  sp.blocks = chains->d_blocks;
+  sp.n_chains = chains->n_chains;
+  sp.n_members = chains->n_members;
+  sp.quads = quads;
+  hipError_t e = hipSuccess;
+  // every per-tile partial starts at zero, so that blocks no valid chain
+  // covers add nothing to the fused maximum and sums
+  if (d_smax) e = tvd::launch_zero_f64(ctx->ws_smax, parts, s);
+  if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(ctx->ws_sums, 10 * parts, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
+  const bool splitb = flags != TVD_STREAM_WHOLE_B;
+  e = batch->dtype == TVD_F32
+          ? tvd::launch_stream_f32(sweep_order, batch->edge, splitb, kp, sp, s)
+          : tvd::launch_stream_f64(sweep_order, batch->edge, splitb, kp, sp, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "streamed kernel launch");
+  if (d_smax) {
+    e = tvd::launch_finalize_max(ctx->ws_smax, (int)parts, d_smax, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
+  }
+  if (d_sums) {
+    e = tvd::launch_finalize_sums(ctx->ws_sums, (int)parts, d_sums, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
+  }
+  return TVD_OK;
 }
 
 int tvd_patch_advance_flux(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in,
@@ -644,6 +748,7 @@ int tvd_graph_begin(tvd_ctx* ctx, void* stream) {
   DeviceGuard g(ctx->device);
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
+  ctx->capturing = true;
   return TVD_OK;
 }
 
@@ -654,6 +759,7 @@ int tvd_graph_end(tvd_ctx* ctx, void* stream, tvd_graph** out) {
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard g(ctx->device);
   hipGraph_t graph = nullptr;
+  ctx->capturing = false;
   hipError_t e = hipStreamEndCapture(s, &graph);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
   hipGraphExec_t exec = nullptr;
@@ -666,12 +772,16 @@ int tvd_graph_end(tvd_ctx* ctx, void* stream, tvd_graph** out) {
   gr->device = ctx->device;
   gr->graph = graph;
   gr->exec = exec;
+  gr->ws_gen = ctx->ws_gen;
+  gr->gen = *ctx->ws_gen;
   *out = gr;
   return TVD_OK;
 }
 
 int tvd_graph_launch(tvd_graph* graph, void* stream) {
   if (!graph) return TVD_ERR_INVALID_ARG;
+  // captured before tvd_reserve replaced the workspace, or its context is gone
+  if (*graph->ws_gen != graph->gen) return TVD_ERR_STATE;
   DeviceGuard g(graph->device);
   return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? TVD_OK : TVD_ERR_HIP;
 }
@@ -690,7 +800,7 @@ int tvd_graph_destroy(tvd_graph* graph) {
 int tvd_max_signal_speed(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, int32_t layout,
                          double gamma, double p_floor, double* d_smax, void* stream) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
-  int st = check_batch(ctx, batch);
+  int st = check_batch(ctx, batch, true);
   if (st) return st;
   if ((st = check_gamma(ctx, gamma, p_floor))) return st;
   if (layout != TVD_LAYOUT_GHOSTED && layout != TVD_LAYOUT_INTERIOR)
@@ -698,7 +808,7 @@ int tvd_max_signal_speed(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, 
   if (!d_u || !d_smax) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
-  if ((st = reserve(ctx, batch->n_blocks, s))) return st;
+  if ((st = need_workspace(ctx, batch->n_blocks))) return st;
   const tvd::KParams kp = make_params(ctx, batch, d_u, nullptr, gamma, p_floor);
   hipError_t e = hipSuccess;
   if (batch->n_blocks > 0) e = tvd::launch_signal_speed(batch->dtype, layout, kp, s);
@@ -711,7 +821,7 @@ int tvd_max_signal_speed(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, 
 int tvd_dt_from_speed(tvd_ctx* ctx, const tvd_batch* batch, const double* d_smax, double cfl,
                       double* d_dt_out, void* stream) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
-  int st = check_batch(ctx, batch);
+  int st = check_batch(ctx, batch, true);
   if (st) return st;
   if (!(cfl > 0.0) || !(cfl <= 1.0))
     return fail(ctx, TVD_ERR_INVALID_ARG, "cfl %g must lie in (0, 1]", cfl);
@@ -727,14 +837,14 @@ int tvd_dt_from_speed(tvd_ctx* ctx, const tvd_batch* batch, const double* d_smax
 int tvd_conservation_sums(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u, int32_t layout,
                           double* d_sums, void* stream) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
-  int st = check_batch(ctx, batch);
+  int st = check_batch(ctx, batch, true);
   if (st) return st;
   if (layout != TVD_LAYOUT_GHOSTED && layout != TVD_LAYOUT_INTERIOR)
     return fail(ctx, TVD_ERR_INVALID_ARG, "layout %d", layout);
   if (!d_u || !d_sums) return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
-  if ((st = reserve(ctx, batch->n_blocks, s))) return st;
+  if ((st = need_workspace(ctx, batch->n_blocks))) return st;
   const tvd::KParams kp = make_params(ctx, batch, d_u, nullptr, 1.0, 0.0);
   hipError_t e = hipSuccess;
   if (batch->n_blocks > 0) e = tvd::launch_cons_sums(batch->dtype, layout, kp, s);
@@ -768,7 +878,7 @@ int tvd_read_flags(tvd_ctx* ctx, int64_t* n_floored, int64_t* n_nonphysical, voi
 int tvd_fill_ghosts(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
                     const void* d_interior, void* d_ghosted, void* stream) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
-  int st = check_batch(ctx, batch);
+  int st = check_batch(ctx, batch, true);
   if (st) return st;
   if (batch->n_blocks == 0) return TVD_OK;
   if (!d_nbr || !d_interior || !d_ghosted)

@@ -108,6 +108,16 @@ hipError_t launch_sor(int dtype, int ngroups, const void* phi_in, const void* rh
                       const double* d_dh, double dh, double G, double omega, double tol,
                       int min_iter, int max_iter, int32_t* iters, double* resid, hipStream_t s);
 
+// The streamed advance over chains of blocks (tvd_stream.hpp): grid = one
+// workgroup per chain and 16 x 16 tile of a block face.
+struct StreamParams;
+hipError_t launch_stream_f32(int order, int edge, bool splitb, const KParams& kp,
+                             const StreamParams& sp, hipStream_t s);
+hipError_t launch_stream_f64(int order, int edge, bool splitb, const KParams& kp,
+                             const StreamParams& sp, hipStream_t s);
+// Zero n doubles (fill kernel, capture-safe).
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
+
 // Variants compiled into the library.
 int variant_count();
 Variant variant_at(int i);

@@ -1,0 +1,434 @@
+// The streamed advance: one step (sweep triple) of a chain of blocks that
+// follow each other along the axis swept last (z for the forward order xyz,
+// x for the backward order zyx).
+//
+// A workgroup of 256 threads owns a 16 x 16 tile of columns across the two
+// axes swept first (the whole face of a 16^3 block, a quadrant of a 32^3
+// block's face) and walks the chain plane by plane, in slabs of P planes:
+//   phase A: the first sweep of the slab's planes, every pencil gathered
+//            straight from HBM (the block's interior and its neighbours' for
+//            the ghost cells), the 16 tile cells of each written to LDS;
+//   phase B: the second sweep in LDS (the tile's 16 interior rows of each
+//            plane, ghost rows of the first sweep included as inputs);
+//   phase S: every thread pushes its column's cells of the slab through a
+//            register ring that carries the third sweep's 1-D update along
+//            the whole chain, and stores each finished cell to HBM.
+// The third sweep therefore runs once over the chain instead of once per
+// block with three ghost planes on each side: the region rule's redundant
+// work shrinks from (n+6)^2 + n(n+6) + n^2 pencils per n^2 columns to
+// (n+6) + n + n per column of the chain (plus three ghost planes at each
+// chain end), and no LDS holds more than one slab.  The arithmetic of every
+// cell is that of pencil_sweep, in the same order, so the results are
+// bit-identical to the per-block advance (the region rule is exact).
+//
+// Scheme: Schive, Tsai & Chiueh, GAMER, Sec. 2.2 (equations cited in
+// tvd_device.hpp); Sec. 3.1 for the one-block-per-thread-block design this
+// replaces; signal speed Eq. (CFL), Sec. 3.4.
+#pragma once
+
+#include "tvd_block.hpp"
+#include "tvd_stream_params.hpp"
+
+namespace tvd {
+
+constexpr int kStreamNT = 256;    // threads: one column of the 16 x 16 tile each
+constexpr int kTile = 16;         // tile edge across the first two sweep axes
+constexpr int kRows = kTile + 2 * kG;   // first-sweep rows of a plane (ghosts included)
+constexpr int kStreamMaxChain = 64;     // blocks per chain at most
+
+// Axes of the streamed advance: A (swept first), B (second), S (last,
+// streamed).  Order 0 (xyz): A = x, B = y, S = z; order 1 (zyx): A = z,
+// B = y, S = x.  Element strides of a block of edge E, and the neighbour
+// region index of offsets (ra, rb, rs).
+template <int ORDER, int E>
+struct StreamAxes {
+  static constexpr int A = ORDER == 0 ? 0 : 2;
+  static constexpr int B = 1;
+  static constexpr int S = ORDER == 0 ? 2 : 0;
+  static constexpr int sa = ORDER == 0 ? 1 : E * E;
+  static constexpr int sb = E;
+  static constexpr int ss = ORDER == 0 ? E * E : 1;
+  __device__ static constexpr int region(int ra, int rb, int rs) {
+    return ORDER == 0 ? (ra + 1) + 3 * (rb + 1) + 9 * (rs + 1)
+                      : (rs + 1) + 3 * (rb + 1) + 9 * (ra + 1);
+  }
+};
+
+// LDS of one slab: P planes of kRows x 16 cells per variable, rows of the
+// tile's 16 A-cells XOR-swizzled by (row + plane) and planes padded to a
+// pitch of 16 mod 32 words, so that the three phases' access patterns
+// spread over the banks.
+template <int P>
+struct SlabLayout {
+  static constexpr int PL = kTile * kRows + kTile;   // plane pitch (368)
+  static constexpr int VP = PL * P;                   // one variable
+  __device__ static inline int idx(int a, int r, int p) {
+    return (a ^ ((r + p) & (kTile - 1))) + kTile * r + PL * p;
+  }
+};
+
+template <typename T, int P>
+struct StreamLds {
+  T s[kNV * SlabLayout<P>::VP];
+  int64_t chain_off[kStreamMaxChain];  // interior offset of every chain block
+  int64_t nb9[9];                      // the slab's 3 x 3 neighbour offsets (ra, rb)
+  double red[kStreamNT / 64 * 2 * kNV];   // block-reduction scratch
+  int nbad;
+};
+
+// Phase A source: the first-sweep pencil of row r (b = b0 - 3 + r) of one
+// plane, cells a = a0 - 3 + j, j = 0 .. 21, gathered across the blocks at
+// A-offsets -1, 0, +1 (p[0..2] point at the pencil's row in each, at A
+// index 0).  For E = 16 the block of cell j is fixed; for E = 32 it depends
+// on the tile's quadrant (a0 = 0 or 16), a value uniform over the
+// workgroup.
+template <typename T, int E, int SA, int D>
+struct StreamPencilA {
+  const T* p[3];
+  int a0;
+  __device__ inline void load(int j, T u[kNV]) const {
+    constexpr int E3 = E * E * E;
+    const int a = a0 - kG + j;
+    const T* c;
+    if (E == kTile) {
+      c = j < kG ? p[0] + (j - kG + E) * SA : (j < kG + E ? p[1] + (j - kG) * SA : p[2] + (j - kG - E) * SA);
+    } else {
+      c = a < 0 ? p[0] + (a + E) * SA : (a < E ? p[1] + a * SA : p[2] + (a - E) * SA);
+    }
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = c[gcomp<D>(k) * E3];
+  }
+};
+
+// Phase A sink: the 16 tile cells of a row into the slab.
+template <typename T, int P, int D>
+struct StreamSinkA {
+  T* s;
+  int r, p;
+  __device__ inline void store(int i, const T u[kNV]) const {
+    const int o = SlabLayout<P>::idx(i, r, p);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * SlabLayout<P>::VP + o] = u[k];
+  }
+};
+
+// Phase B: the second-sweep pencil at tile column a of plane p, in place
+// (reads rows 0 .. 21, writes rows 3 .. 18).
+template <typename T, int P, int D>
+struct StreamPencilB {
+  T* s;
+  int a, p;
+  __device__ inline void load(int j, T u[kNV]) const {
+    const int o = SlabLayout<P>::idx(a, j, p);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) u[k] = s[gcomp<D>(k) * SlabLayout<P>::VP + o];
+  }
+  __device__ inline void store(int i, const T u[kNV]) const {
+    const int o = SlabLayout<P>::idx(a, i + kG, p);
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) s[gcomp<D>(k) * SlabLayout<P>::VP + o] = u[k];
+  }
+};
+
+// The third sweep of one column, carried along the chain: the rolling
+// windows of pencil_sweep (cell states, midpoint fluxes, the previous
+// interface fluxes) kept across slabs.  step<J4>() takes the next cell
+// (chain step j with j mod 4 = J4) and returns the finished cell j - 6 in
+// `out`; the first six steps of a chain return nothing meaningful (their
+// results are dropped by the caller).  The arithmetic per cell is that of
+// pencil_sweep, operation for operation.
+template <typename T>
+struct StreamRing {
+  T q[4][kNV];
+  T FRh[4][kNV];
+  T FLh[4][kNV];
+  T FRp[kNV], Gp[kNV], Hp[kNV];
+
+  __device__ inline void reset() {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      FRp[k] = Gp[k] = Hp[k] = T(0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) q[r][k] = FRh[r][k] = FLh[r][k] = T(0);
+    }
+  }
+
+  template <int J4>
+  __device__ inline void step(const T u[kNV], const Coef<T>& cf, T out[kNV]) {
+    constexpr int a = J4, b = (J4 + 1) & 3, c = (J4 + 2) & 3, d = (J4 + 3) & 3;
+    T* qj = q[J4];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) qj[k] = u[k];
+    T FR[kNV], FL[kNV];
+    split_flux(qj, cf, FR, FL);
+    // first-order upwind flux at j-1/2, Eq. (MidpointValue) for cell j-1
+    // and its midpoint fluxes
+    T G[kNV], h[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      G[k] = FRp[k] - FL[k];
+      h[k] = Num<T>::fma(-cf.hlam, G[k] - Gp[k], q[d][k]);
+      Gp[k] = G[k];
+      FRp[k] = FR[k];
+    }
+    split_flux(h, cf, FRh[d], FLh[d]);
+    // second-order flux at interface (j-3)+1/2 from the midpoint fluxes of
+    // cells j-4 .. j-1, then Eq. (FullstepValue) for cell j-3
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      const T R = FRh[b][k] + vanleer(FRh[b][k] - FRh[a][k], FRh[c][k] - FRh[b][k]);
+      const T L = FLh[c][k] + vanleer(FLh[c][k] - FLh[d][k], FLh[b][k] - FLh[c][k]);
+      const T H = R - L;
+      out[k] = Num<T>::fma(-cf.lam, H - Hp[k], q[b][k]);
+      Hp[k] = H;
+    }
+  }
+};
+
+// Compile-time loop: f(std::integral_constant<int, I>{}) for I = B .. E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// One step of a chain on one tile (workgroup), see the top of this file.
+//
+// Chain planes are numbered g = -3 .. C*E+2 along the streamed axis: the
+// three ghost planes before the first block (its S- neighbour), the blocks'
+// planes, and three ghost planes after the last block (its S+ neighbour).
+// Consuming plane g finishes cell g - 3 of every column.
+template <typename T, int E, int ORDER, int P, bool SPLITB>
+struct StreamChain {
+  using AX = StreamAxes<ORDER, E>;
+  using SL = SlabLayout<P>;
+  static constexpr int E3 = E * E * E;
+  // 16-byte output runs along x in the backward order (x is the streamed
+  // axis there, so a thread's finished cells are consecutive in memory)
+  static constexpr int RUN = ORDER == 1 ? 16 / (int)sizeof(T) : 1;
+
+  const KParams& kp;
+  const StreamParams& sp;
+  StreamLds<T, P>& sm;
+  int tid, quad, a0, b0, chain0, C;
+  Coef<T> cf;
+  double dh;
+  StreamRing<T> ring;
+  CellDiag dg;
+  T run[RUN][kNV];
+
+  // Phase A and B of the slab planes pl in [lo, hi), plane pl being plane
+  // s_lo + pl of block `cb` (rs = 0) or of its neighbour at S-offset rs (the
+  // chain's ghost planes).  Chain ends use the same code with fewer planes,
+  // so that one copy of each phase serves every slab.
+  __device__ __forceinline__ void planes_ab(int cb, int rs, int s_lo, int lo, int hi) {
+    if (tid < 9) {
+      const int ra = tid % 3 - 1, rb = tid / 3 - 1;
+      const int nb = kp.nbr[27 * (int64_t)cb + AX::region(ra, rb, rs)];
+      sm.nb9[tid] = kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * E3;
+    }
+    __syncthreads();
+    const T* __restrict__ uin = reinterpret_cast<const T*>(kp.uin);
+    // phase A: 22 rows per plane, spread evenly over the four waves
+    {
+      constexpr int npen = kRows * P;
+      constexpr int per = (npen + 3) / 4;
+      const int l = tid & 63, p = (tid >> 6) * per + l;
+      const int r = p % kRows, pl = p / kRows;
+      if (l < per && p < npen && pl >= lo && pl < hi) {
+        const int b = b0 - kG + r;
+        const int rb = b < 0 ? -1 : (b >= E ? 1 : 0);
+        const int64_t row = (int64_t)(b - rb * E) * AX::sb + (int64_t)(s_lo + pl) * AX::ss;
+        StreamPencilA<T, E, AX::sa, AX::A> src;
+        src.a0 = a0;
+#pragma unroll
+        for (int ra = 0; ra < 3; ++ra) src.p[ra] = uin + sm.nb9[ra + 3 * (rb + 1)] + row;
+        const StreamSinkA<T, P, AX::A> dst{sm.s, r, pl};
+        pencil_sweep<T, kTile>(src, dst, cf);
+      }
+    }
+    __syncthreads();
+    // phase B: the tile's 16 columns per plane, in place
+    if constexpr (SPLITB) {
+      const int p = tid >> 1, off = (tid & 1) * (kTile / 2);
+      const int pl = p / kTile;
+      const bool act = pl >= lo && pl < hi;   // 2 * 16 * P = 256 half pencils
+      const Shifted<StreamPencilB<T, P, AX::B>> acc{{sm.s, p % kTile, pl}, off};
+      Held<T, kTile / 2> held;
+      if (act) pencil_sweep<T, kTile / 2>(acc, held, cf);
+      __syncthreads();
+      if (act) held.flush(acc);
+    } else {
+      constexpr int npen = kTile * P;
+      constexpr int per = (npen + 3) / 4;
+      const int l = tid & 63, p = (tid >> 6) * per + l;
+      const int pl = p / kTile;
+      if (l < per && p < npen && pl >= lo && pl < hi) {
+        const StreamPencilB<T, P, AX::B> acc{sm.s, p % kTile, pl};
+        pencil_sweep<T, kTile>(acc, acc, cf);
+      }
+    }
+    __syncthreads();
+  }
+
+  // Store finished cell `cell` (0 .. C*E-1 along the chain) of this
+  // thread's column and account for it in the diagnostics; with runs, the
+  // cell waits in registers until its run is complete.
+  template <int RPOS>
+  __device__ __forceinline__ void emit(int cell, const T out[kNV]) {
+    T ug[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) ug[gcomp<AX::S>(k)] = out[k];
+    diag_cell<T>(dg, ug, kp.diag, kp.gamma, kp.pfloor);
+    const int kk = cell / E, sl = cell % E;
+    const int al = tid & (kTile - 1), bl = tid / kTile;
+    T* base = reinterpret_cast<T*>(kp.uout) + sm.chain_off[kk] + (int64_t)(a0 + al) * AX::sa +
+              (int64_t)(b0 + bl) * AX::sb;
+    if constexpr (RUN == 1) {
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) base[(int64_t)k * E3 + (int64_t)sl * AX::ss] = ug[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) run[RPOS][k] = ug[k];
+      if constexpr (RPOS == RUN - 1) {
+        // x = sl - RUN + 1 .. sl, 16-byte aligned
+#pragma unroll
+        for (int k = 0; k < kNV; ++k) {
+          T* c = base + (int64_t)k * E3 + (sl - RUN + 1);
+          if constexpr (sizeof(T) == 4)
+            *reinterpret_cast<float4*>(c) = make_float4(run[0][k], run[1][k], run[2][k], run[3][k]);
+          else
+            *reinterpret_cast<double2*>(c) = make_double2(run[0][k], run[1][k]);
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void publish(int kk) {
+    const int b = sp.blocks[chain0 + kk];
+    diag_publish<kStreamNT>(dg, b * sp.quads + quad, dh, kp, sm.red, tid);
+    diag_init(dg);
+  }
+
+  // Phase S over the slab planes pl in [lo, hi): plane pl is chain plane
+  // g = g0 + pl, chain step g + 3, ring position (3 + pl) mod 4 (g0 is a
+  // multiple of 4 minus 0 for the blocks' planes and the closing ghost
+  // planes, -8 for the opening ghost planes, which sit at pl = 5 .. 7).
+  // `emit_from` is the first plane whose finished cell is kept; `pub_at`
+  // the plane after which the previous block's diagnostics are complete
+  // (-1: none).
+  __device__ __forceinline__ void planes_s(int g0, int lo, int hi, int emit_from, int pub_at) {
+    const int al = tid & (kTile - 1), bl = tid / kTile;
+    static_for<0, P>([&](auto I) {
+      constexpr int pl = decltype(I)::value;
+      constexpr int j4 = (3 + pl) & 3;
+      if (pl >= lo && pl < hi) {
+        const int o = SL::idx(al, bl + kG, pl);
+        T u[kNV], out[kNV];
+#pragma unroll
+        for (int k = 0; k < kNV; ++k) u[k] = sm.s[gcomp<AX::S>(k) * SL::VP + o];
+        ring.template step<j4>(u, cf, out);
+        // finished cell g - 3, at position (pl - 3) mod RUN of its 16-byte run
+        constexpr int rpos = ((pl - kG) % RUN + RUN) % RUN;
+        if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out);
+        if (pl == pub_at) publish((g0 + pl - kG) / E);
+      }
+    });
+    __syncthreads();
+  }
+
+  __device__ __forceinline__ void run_chain() {
+    static_assert(P == 8, "ring positions and run alignment assume slabs of 8 planes");
+    ring.reset();
+    diag_init(dg);
+    // One loop over the chain's slabs, so that each phase exists once in the
+    // code: slab 0 holds the three ghost planes before the chain (the last
+    // planes of the head's S- neighbour) in slab planes 5 .. 7, chain steps
+    // 0 .. 2, nothing finished; slabs 1 .. C*E/P hold the blocks' planes; the
+    // last slab holds the three ghost planes after the chain (the first
+    // planes of the tail's S+ neighbour), which finish the last block.
+    const int nslab = C * (E / P) + 2;
+    for (int t = 0; t < nslab; ++t) {
+      int cb, rs, s_lo, lo, hi, g0, emit_from, pub_at;
+      if (t == 0) {
+        cb = sp.blocks[chain0];
+        rs = -1, s_lo = E - P, lo = P - kG, hi = P, g0 = -P, emit_from = P, pub_at = -1;
+      } else if (t == nslab - 1) {
+        cb = sp.blocks[chain0 + C - 1];
+        rs = 1, s_lo = 0, lo = 0, hi = kG, g0 = C * E, emit_from = 0, pub_at = kG - 1;
+      } else {
+        const int kk = (t - 1) / (E / P), m = (t - 1) % (E / P);
+        cb = sp.blocks[chain0 + kk];
+        rs = 0, s_lo = m * P, lo = 0, hi = P, g0 = kk * E + m * P;
+        // the chain's first three planes finish nothing (cells -3 .. -1); the
+        // third plane of every later block finishes the previous block
+        emit_from = (kk == 0 && m == 0) ? kG : 0;
+        pub_at = (kk > 0 && m == 0) ? kG - 1 : -1;
+      }
+      planes_ab(cb, rs, s_lo, lo, hi);
+      planes_s(g0, lo, hi, emit_from, pub_at);
+    }
+  }
+};
+
+template <typename T, int E, int ORDER, int P, bool SPLITB>
+__global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_stream(
+    KParams kp, StreamParams sp) {
+  using AX = StreamAxes<ORDER, E>;
+  __shared__ StreamLds<T, P> sm;
+  const int tid = threadIdx.x;
+  const int item = xcd_block(blockIdx.x, gridDim.x);
+  const int chain = item / sp.quads, quad = item % sp.quads;
+  const int c0 = sp.start[chain];
+  const int C = sp.start[chain + 1] - c0;
+  constexpr int RUN = StreamChain<T, E, ORDER, P, SPLITB>::RUN;
+  // Validate the chain before touching anything: at most kStreamMaxChain
+  // blocks of edge E, each the S+ neighbour of the one before, every
+  // neighbour of every block present with edge E, one dt and dh.  A chain
+  // that fails is not advanced (its cells are counted as non-physical and
+  // its output is left untouched).
+  const bool shape_ok = C >= 1 && C <= kStreamMaxChain && c0 >= 0 && c0 + C <= sp.n_members;
+  if (tid == 0) sm.nbad = shape_ok ? 0 : 1;
+  __syncthreads();
+  if (sm.nbad == 0) {
+    const int head = sp.blocks[c0];
+    const bool head_ok = head >= 0 && head < kp.nblocks;
+    for (int i = tid; i < C; i += kStreamNT) {
+      const int b = sp.blocks[c0 + i];
+      bool ok = head_ok && b >= 0 && b < kp.nblocks && block_edge(kp, b) == E;
+      if (ok) {
+        sm.chain_off[i] = kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * E * E * E;
+        ok = sm.chain_off[i] % RUN == 0;  // 16-byte output runs stay aligned
+        if (i + 1 < C) ok = kp.nbr[27 * (int64_t)b + AX::region(0, 0, 1)] == sp.blocks[c0 + i + 1];
+        if (kp.d_dt) ok = ok && kp.d_dt[b] == kp.d_dt[head];
+        if (kp.d_dh) ok = ok && kp.d_dh[b] == kp.d_dh[head];
+      }
+      if (!ok) atomicAdd(&sm.nbad, 1);
+    }
+    for (int w = tid; w < 27 * C; w += kStreamNT) {
+      const int b = sp.blocks[c0 + w / 27];
+      if (b < 0 || b >= kp.nblocks) continue;  // counted above
+      const int nb = kp.nbr[27 * (int64_t)b + w % 27];
+      if (!(nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == E)) atomicAdd(&sm.nbad, 1);
+    }
+  }
+  __syncthreads();
+  if (sm.nbad) {
+    if (tid == 0 && shape_ok)
+      atomicAdd(&kp.counters[1], (unsigned long long)C * (E * E * E / sp.quads));
+    return;  // uniform over the workgroup
+  }
+  StreamChain<T, E, ORDER, P, SPLITB> ch{kp, sp, sm};
+  ch.tid = tid;
+  ch.quad = quad;
+  ch.a0 = kTile * (quad & 1);
+  ch.b0 = kTile * (quad >> 1);
+  ch.chain0 = c0;
+  ch.C = C;
+  ch.cf = make_coef<T>(kp, sp.blocks[c0], ch.dh);
+  ch.run_chain();
+}
+
+}  // namespace tvd

@@ -16,8 +16,16 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import tvd
+from . import layout, tvd
 from .layout import BlockSet
+
+
+def default_chain_len(tiles: int, slots: int = 1024) -> int:
+    """Chain length of the streamed advance for `tiles` block-face tiles: as
+    long as possible (each chain repeats the first two sweeps on six ghost
+    planes) while leaving about `slots` chains (two workgroups on each of the
+    256 compute units, twice over) to spread over the chip; 4 to 64 blocks."""
+    return int(min(64, max(4, tiles // slots)))
 
 
 class DeviceBlocks:
@@ -25,7 +33,8 @@ class DeviceBlocks:
 
     def __init__(self, ctx: tvd.Context, bs: BlockSet, dtype=torch.float32,
                  device="cuda:0", gamma: float = 5.0 / 3.0, p_floor: float = 0.0,
-                 cfl: float = 0.5, kernel: int = tvd.TVD_KERNEL_AUTO, gather: bool = False):
+                 cfl: float = 0.5, kernel: int = tvd.TVD_KERNEL_AUTO, gather: bool = False,
+                 stream: bool = False, chain_len: int | None = None):
         self.ctx = ctx
         self.bs = bs
         self.dtype = dtype
@@ -34,7 +43,9 @@ class DeviceBlocks:
         self.p_floor = p_floor
         self.cfl = cfl
         self.kernel = kernel
-        self.gather = gather
+        self.stream = stream
+        self.gather = gather or stream
+        gather = self.gather
         dev = self.device
         self.interior = torch.zeros(bs.out_total, dtype=dtype, device=dev)
         if gather:
@@ -60,8 +71,26 @@ class DeviceBlocks:
             self.batch = tvd.Batch(code, bs.n_blocks, 0, d_edge=self.edges, d_in_off=self.in_off,
                                    d_out_off=self.out_off, d_dt=self.dt, d_dh=self.dh)
             self.batch_const = self.batch
-        ctx.tvd_reserve(bs.n_blocks)
+        quads = 1
+        if stream:
+            # chains along z for the forward step, along x for the backward one
+            if uniform not in (16, 32):
+                raise ValueError("the streamed advance takes a uniform block edge of 16 or 32")
+            quads = (uniform // 16) ** 2
+            self.set_chains(default_chain_len(bs.n_blocks * quads) if chain_len is None
+                            else chain_len)
+        ctx.tvd_reserve(bs.n_blocks * quads)
         self.step_index = 0
+
+    def set_chains(self, chain_len: int):
+        """Chains of at most chain_len blocks for the streamed advance: along
+        z for the forward step, along x for the backward one."""
+        self.chain_len = chain_len
+        self.chains = {}
+        for order, axis in ((tvd.TVD_XYZ, 2), (tvd.TVD_ZYX, 0)):
+            st, bl = layout.stream_chains(self.bs.nbr, axis, chain_len)
+            self.chains[order] = tvd.Chains(torch.from_numpy(st).to(self.device),
+                                            torch.from_numpy(bl).to(self.device))
 
     # -- data movement (host <-> device), not part of a step ----------------
     def upload(self, blocks):
@@ -85,7 +114,12 @@ class DeviceBlocks:
     def advance(self, order: int, fuse_speed: bool = False, fuse_sums: bool = False):
         smax = self.smax if fuse_speed else None
         sums = self.sums if fuse_sums else None
-        if self.gather:
+        if self.stream:
+            self.ctx.tvd_patch_advance_stream(self.batch, self.nbr, self.chains[order],
+                                              self.interior, self.spare, order, self.gamma,
+                                              self.p_floor, self.kernel, smax=smax, sums=sums)
+            self.interior, self.spare = self.spare, self.interior
+        elif self.gather:
             self.ctx.tvd_patch_advance_gather(self.batch, self.nbr, self.interior, self.spare,
                                               order, self.gamma, self.p_floor, self.kernel,
                                               smax=smax, sums=sums)

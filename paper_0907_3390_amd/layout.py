@@ -524,3 +524,72 @@ class NestedLevels:
         """{level l: (restrict_rows, face_rows, pass_count)} of every pair
         (l, l+1)."""
         return closing_tables(self.patches, self.Nc // PATCH, self.locate)
+
+
+# ---------------------------------------------------------------------------
+# chains of blocks for the streamed advance
+# ---------------------------------------------------------------------------
+
+# neighbour region of the block at +1 along x, y, z
+PLUS_REGION = {0: 2 + 3 * 1 + 9 * 1, 1: 1 + 3 * 2 + 9 * 1, 2: 1 + 3 * 1 + 9 * 2}
+MINUS_REGION = {0: 0 + 3 * 1 + 9 * 1, 1: 1 + 3 * 0 + 9 * 1, 2: 1 + 3 * 1 + 9 * 0}
+
+
+def stream_chains(nbr: np.ndarray, axis: int, max_len: int, members=None):
+    """Cut the lines of blocks along `axis` (0 x, 1 y, 2 z; block b's
+    successor is nbr[b][+axis]) into chains of at most `max_len` consecutive
+    blocks, as even in length as the line allows.  A line is a cycle on a
+    periodic grid (it starts at its lowest block number) or a path from a
+    block without a predecessor.  `members`: the blocks to chain (default:
+    all); a successor outside them ends a path.  Chains are ordered by their
+    first block's number, so consecutive chains lie close together when the
+    blocks are numbered along a space-filling curve.  Returns (start, blocks)
+    int32 arrays: chain c is blocks[start[c]:start[c+1]]."""
+    nbr = np.asarray(nbr)
+    nb = nbr.shape[0]
+    if max_len < 1:
+        raise ValueError("max_len must be >= 1")
+    inset = np.zeros(nb, dtype=bool)
+    inset[np.arange(nb) if members is None else np.asarray(members, dtype=np.int64)] = True
+    succ = nbr[:, PLUS_REGION[axis]].astype(np.int64)
+    pred = nbr[:, MINUS_REGION[axis]].astype(np.int64)
+    ok_s = (succ >= 0) & (succ < nb)
+    ok_p = (pred >= 0) & (pred < nb)
+    has_pred = np.zeros(nb, dtype=bool)
+    has_pred[ok_p] = inset[pred[ok_p]]
+    has_pred &= inset
+    seen = ~inset
+    lines = []
+
+    def walk(b):
+        line = []
+        while 0 <= b < nb and not seen[b]:
+            seen[b] = True
+            line.append(b)
+            b = succ[b] if ok_s[b] else -1
+        return line
+
+    # paths first (from blocks without a predecessor in the set), then cycles
+    for b in np.nonzero(inset & ~has_pred)[0]:
+        if not seen[b]:
+            lines.append(walk(int(b)))
+    for b in np.nonzero(~seen)[0]:
+        if not seen[b]:
+            line = walk(int(b))
+            k = int(np.argmin(line))
+            lines.append(line[k:] + line[:k])
+    chains = []
+    for line in lines:
+        n = len(line)
+        pieces = -(-n // max_len)
+        q, r = divmod(n, pieces)
+        o = 0
+        for i in range(pieces):
+            m = q + (1 if i < r else 0)
+            chains.append(line[o:o + m])
+            o += m
+    chains.sort(key=lambda c: c[0])
+    start = np.zeros(len(chains) + 1, dtype=np.int32)
+    start[1:] = np.cumsum([len(c) for c in chains])
+    blocks = np.array([b for c in chains for b in c], dtype=np.int32)
+    return start, blocks

@@ -33,6 +33,7 @@ TVD_KERNEL_AUTO = 0
 TVD_KERNEL_BATCHED = 1
 TVD_KERNEL_PLAIN = 2
 TVD_KERNEL_PERSISTENT = 3
+TVD_STREAM_WHOLE_B = 16
 
 EXPORTS = [
     "tvd_create", "tvd_destroy", "tvd_status_string", "tvd_last_error", "tvd_reserve",
@@ -42,6 +43,7 @@ EXPORTS = [
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
     "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
     "tvd_close_level", "tvd_poisson_sor", "tvd_gravity", "tvd_lerp",
+    "tvd_patch_advance_stream",
 ]
 
 
@@ -49,6 +51,11 @@ class TvdError(RuntimeError):
     def __init__(self, status: int, text: str):
         super().__init__(f"libtvd status {status}: {text}")
         self.status = status
+
+
+class tvd_chains(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int32), ("n_members", ctypes.c_int32),
+                ("d_start", ctypes.c_void_p), ("d_blocks", ctypes.c_void_p)]
 
 
 class tvd_batch(ctypes.Structure):
@@ -84,6 +91,8 @@ def load(path: str = LIB_PATH):
         "tvd_patch_advance": (ctypes.c_int, [vp, bp, vp, vp, i32, dbl, dbl, i32, vp, vp, vp]),
         "tvd_patch_advance_gather": (ctypes.c_int, [vp, bp, vp, vp, vp, i32, dbl, dbl, i32, vp,
                                                     vp, vp]),
+        "tvd_patch_advance_stream": (ctypes.c_int, [vp, bp, vp, ctypes.POINTER(tvd_chains), vp,
+                                                    vp, i32, dbl, dbl, i32, vp, vp, vp]),
         "tvd_max_signal_speed": (ctypes.c_int, [vp, bp, vp, i32, dbl, dbl, vp, vp]),
         "tvd_dt_from_speed": (ctypes.c_int, [vp, bp, vp, dbl, vp, vp]),
         "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
@@ -154,6 +163,19 @@ class Batch:
         return ctypes.byref(self.c)
 
 
+class Chains:
+    """A tvd_chains descriptor over two int32 device tensors (start, blocks)."""
+
+    def __init__(self, start, blocks):
+        self.start, self.blocks = start, blocks
+        self.c = tvd_chains(int(start.numel()) - 1, int(blocks.numel()), _ptr(start),
+                            _ptr(blocks))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
 class Context:
     """Owns a tvd_ctx; methods carry the C entry points' names and arguments."""
 
@@ -203,6 +225,16 @@ class Context:
         st = self.lib.tvd_patch_advance_gather(self.h, batch.ref, _ptr(nbr), _ptr(u_in),
                                                _ptr(u_out), sweep_order, gamma, p_floor, flags,
                                                _ptr(smax), _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_patch_advance_stream(self, batch: Batch, nbr, chains: "Chains", u_in, u_out,
+                                 sweep_order: int, gamma: float, p_floor: float = 0.0,
+                                 flags: int = TVD_KERNEL_AUTO, smax=None, sums=None,
+                                 stream=None, check: bool = True):
+        st = self.lib.tvd_patch_advance_stream(self.h, batch.ref, _ptr(nbr), chains.ref,
+                                               _ptr(u_in), _ptr(u_out), sweep_order, gamma,
+                                               p_floor, flags, _ptr(smax), _ptr(sums),
+                                               _stream(stream))
         return self._check(st) if check else st
 
     def tvd_patch_advance_flux(self, batch: Batch, u_in, u_out, flux, flux_off, sweep_order: int,
@@ -323,6 +355,9 @@ class Graph:
 
     def tvd_graph_launch(self, stream=None):
         st = self.lib.tvd_graph_launch(self.h, _stream(stream))
+        if st == TVD_ERR_STATE:
+            raise TvdError(st, "graph retired: the workspace was replaced by tvd_reserve or "
+                               "the context destroyed after the capture")
         if st != TVD_OK:
             raise TvdError(st, "tvd_graph_launch failed")
 

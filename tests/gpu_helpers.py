@@ -32,19 +32,42 @@ def norms(a, b, gamma=GAMMA):
     scale = np.sum(rho * cs)
     out = {}
     names = ["rho", "m_x", "m_y", "m_z", "e"]
+    mscale = max(float(np.max(rho * cs)), 1e-300)
     for k, nm in enumerate(names):
         d = np.abs(a[k] - b[k])
         own = np.sum(np.abs(b[k]))
+        own_max = max(np.abs(b[k]).max(), 1e-300)
         out[nm] = {
             "relL1": d.sum() / (own if k in (0, 4) else max(scale, 1e-300)),
             "relL1_own": d.sum() / max(own, 1e-300),
-            "relLinf": d.max() / max(np.abs(b[k]).max(), 1e-300),
+            # elementwise: the largest difference against the variable's
+            # largest magnitude (momentum: against the largest rho c_s)
+            "relLinf": d.max() / (own_max if k in (0, 4) else max(mscale, own_max)),
+            "relLinf_own": d.max() / own_max,
         }
     return out
 
 
 def worst(nrm, key="relL1"):
     return max(v[key] for v in nrm.values())
+
+
+# Parity bounds (relative L1, relative Linf per variable).  FP64: the same
+# arithmetic in another order, differences at round-off (1e-16 per
+# operation).  FP32: each step rounds O(100) operations per cell at 6e-8, a
+# per-cell relative error of about 1e-6 after ten steps; the largest cell is
+# allowed 100x that on smooth data and 1000x on rough data, where limiter
+# switches and shocks amplify round-off differences locally.
+FP64 = (1e-12, 1e-12)
+FP32_SMOOTH = (1e-5, 1e-4)
+FP32_ROUGH = (1e-5, 1e-3)
+
+
+def check(nrm, bounds):
+    """Assert both norms of every variable within (L1, Linf) bounds."""
+    l1, linf = bounds
+    assert worst(nrm, "relL1") <= l1, {k: v["relL1"] for k, v in nrm.items()}
+    assert worst(nrm, "relLinf") <= linf, {k: v["relLinf"] for k, v in nrm.items()}
 
 
 def oracle_periodic(grid, steps, n=8, cfl=0.5, gamma=GAMMA, p_floor=0.0):

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from oracle import ghosts
-from gpu_helpers import GAMMA, norms, note, worst
+from gpu_helpers import FP64, check, GAMMA, norms, note, worst
 from paper_0907_3390_amd import layout, tvd, workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -94,7 +94,7 @@ def test_fill_then_step_fp64(ctx):
     got = out.cpu().numpy().reshape(fine_bs.n_blocks, 5, n, n, n)
     nrm = norms(got.transpose(1, 0, 2, 3, 4).reshape(5, -1), want.transpose(1, 0, 2, 3, 4).reshape(5, -1))
     note(str({k: f"{v['relL1']:.2e}" for k, v in nrm.items()}))
-    assert worst(nrm) <= 1e-12
+    check(nrm, FP64)
 
 
 def test_fill_flags_a_missing_coarse_patch(ctx):

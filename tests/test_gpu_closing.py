@@ -23,7 +23,7 @@ import torch
 
 import oracle
 from oracle import closing
-from gpu_helpers import GAMMA, note
+from gpu_helpers import FP64, GAMMA, check, norms, note
 from paper_0907_3390_amd import layout, tvd, workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -44,6 +44,16 @@ def _rel_l1(got, want):
     for k in range(5):
         d = sum(float(np.abs(g[:, :, k] - w[:, :, k]).sum()) for g, w in zip(got, want))
         s = sum(float(np.abs(w[:, :, k]).sum()) for w in want)
+        worst = max(worst, d / s)
+    return worst
+
+
+def _rel_linf(got, want):
+    """Worst over the five variables of max |got - want| / max |want|."""
+    worst = 0.0
+    for k in range(5):
+        d = max(float(np.abs(g[:, :, k] - w[:, :, k]).max()) for g, w in zip(got, want))
+        s = max(float(np.abs(w[:, :, k]).max()) for w in want)
         worst = max(worst, d / s)
     return worst
 
@@ -111,8 +121,10 @@ def test_flux_records_match_oracle(ctx, dtype, n, flags, order):
     got_out, got_rec = _advance_flux(ctx, dtype, list(blocks), [n] * len(blocks), order, flags, dt, dh)
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     err = _rel_l1(got_rec, want_rec)
-    note(f"  record relL1 {err:.2e}")
+    einf = _rel_linf(got_rec, want_rec)
+    note(f"  record relL1 {err:.2e}, relLinf {einf:.2e}")
     assert err <= tol
+    assert einf <= (1e-12 if dtype == torch.float64 else 1e-4)
     assert not any(np.isnan(r).any() for r in got_rec)
     # neighbouring blocks report the same bits on the face they share
     nb = N // n
@@ -321,6 +333,9 @@ def test_two_level_step(ctx, dtype, n, order):
     note(f"  coarse relL1 {err_c:.2e}, fine relL1 {err_f:.2e}")
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert err_c <= tol and err_f <= tol
+    bounds = FP64 if dtype == torch.float64 else (1e-5, 1e-4)
+    check(norms(cg, want_c), bounds)
+    check(norms(fg[:, mask], want_f[:, mask]), bounds)
     before = closing.leaf_sums(coarse, fine, L.refined)
     after = closing.leaf_sums(cg, fg, L.refined)
     scale = closing.leaf_sums(np.abs(coarse), np.abs(fine), L.refined)

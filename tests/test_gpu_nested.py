@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from oracle import closing, ghosts
-from gpu_helpers import GAMMA, note
+from gpu_helpers import FP64, GAMMA, check, norms, note
 from paper_0907_3390_amd import amr, tvd, workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -84,6 +84,9 @@ def test_nested_driver_matches_oracle(ctx, dtype):
             err = np.abs(g[:, k] - w[:, k]).sum() / scale
             note(f"  level {lev} var {k}: relL1 {err:.1e}")
             assert err <= tol, (lev, k, err)
+        check(norms(g.transpose(1, 0, 2, 3, 4).reshape(5, -1),
+                    w.transpose(1, 0, 2, 3, 4).reshape(5, -1)),
+              FP64 if dtype == torch.float64 else (1e-5, 1e-4))
 
 
 def test_nested_driver_conserves_over_steps(ctx):

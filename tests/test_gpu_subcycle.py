@@ -9,7 +9,7 @@ import pytest
 import torch
 
 from oracle import closing
-from gpu_helpers import GAMMA, note
+from gpu_helpers import FP64, GAMMA, check, norms, note
 from paper_0907_3390_amd import amr, tvd, workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -62,6 +62,10 @@ def test_two_level_driver_matches_oracle(ctx, dtype, n, subcycle):
     note(f"  coarse relL1 {err_c:.1e}, fine {err_f:.1e}")
     tol = 1e-12 if dtype == torch.float64 else 1e-5
     assert err_c <= tol and err_f <= tol
+    bounds = FP64 if dtype == torch.float64 else (1e-5, 1e-4)
+    check(norms(got_c, want_c), bounds)
+    check(norms(got_f.transpose(1, 0, 2, 3, 4).reshape(5, -1),
+                want_fb.transpose(1, 0, 2, 3, 4).reshape(5, -1)), bounds)
 
 
 @pytest.mark.parametrize("subcycle", [False, True])

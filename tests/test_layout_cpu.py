@@ -201,3 +201,35 @@ def test_nested_levels_masks_round_trip():
     L = layout.NestedLevels(32, [r0, r1])
     back = layout.NestedLevels.refined_from_patches(32, L.patches)
     assert len(back) == 2 and all(np.array_equal(a, b) for a, b in zip(back, [r0, r1]))
+
+
+def test_stream_chains_cover_and_follow_the_axis():
+    """Chains for the streamed advance: every block exactly once, each block
+    the +axis neighbour of the one before, lengths as even as the line
+    allows (at most max_len), on periodic grids numbered linearly and along
+    the Morton curve, and on independent periodic boxes (lines that are
+    cycles of one block)."""
+    from paper_0907_3390_amd.driver import default_chain_len
+    cases = [layout.periodic_grid_blockset(96, 16), layout.periodic_grid_blockset(64, 16, curve="morton"),
+             layout.boxes_blockset([32, 32, 16], lambda L: L, [1 / 32, 1 / 32, 1 / 16])]
+    for bs in cases:
+        for axis in (0, 1, 2):
+            for L in (1, 2, 3, 4, 64):
+                st, bl = layout.stream_chains(bs.nbr, axis, L)
+                assert st[0] == 0 and st[-1] == bs.n_blocks
+                assert sorted(bl.tolist()) == list(range(bs.n_blocks))
+                lens = np.diff(st)
+                assert lens.min() >= 1 and lens.max() <= L
+                for c in range(len(lens)):
+                    ch = bl[st[c]:st[c + 1]]
+                    for a, b in zip(ch[:-1], ch[1:]):
+                        assert bs.nbr[a, layout.PLUS_REGION[axis]] == b
+    # a periodic line of 6 blocks cut at most 4 long: two chains of 3
+    bs = layout.periodic_grid_blockset((16, 16, 96), 16)
+    st, bl = layout.stream_chains(bs.nbr, 0, 4)
+    assert np.diff(st).tolist() == [3, 3]
+    # a subset: the successor outside the set ends a path
+    st, bl = layout.stream_chains(bs.nbr, 0, 8, members=[1, 2, 3])
+    assert bl.tolist() == [1, 2, 3] and st.tolist() == [0, 3]
+    assert default_chain_len(32768) == 32 and default_chain_len(4096) == 4
+    assert default_chain_len(10 ** 7) == 64
