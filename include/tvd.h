@@ -262,6 +262,28 @@ int tvd_patch_advance_stream(tvd_ctx *ctx, const tvd_batch *batch, const int32_t
                              double *d_smax, double *d_sums, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as tvd_patch_advance_stream, with the same arguments and the same
+ * results bit for bit, but the per-tile partials of the fused signal speed
+ * and sums live in a static device array of the library (one per device,
+ * 5.8 MB, held until the process ends) instead of the context's workspace.
+ * It calls no hipMalloc, hipFree or allocating routine and needs no
+ * tvd_reserve.
+ *   Limit: with d_smax or d_sums, n_blocks * (1 for edge 16, 4 for edge 32)
+ *            must not exceed 65536 (else TVD_ERR_STATE, nothing launched).
+ *   Sharing: every call on a device uses that device's one array; calls
+ *            that overlap in time on one device (other streams, other
+ *            contexts, other host threads) race and give wrong diagnostics.
+ *            The partials are cleared by each call before its kernel runs.
+ */
+int tvd_patch_advance_stream_noalloc(tvd_ctx *ctx, const tvd_batch *batch,
+                                     const int32_t *d_nbr, const tvd_chains *chains,
+                                     const void *d_u_in, void *d_u_out, int32_t sweep_order,
+                                     double gamma, double p_floor, int32_t flags,
+                                     double *d_smax, double *d_sums, void *stream);
+
+/*
  * Eq. (CFL) signal speed: d_smax[0] = max over the interior cells of all
  * blocks of c_s + max(|v_x|, |v_y|, |v_z|), with c_s from max(P, p_floor);
  * evaluated in FP64 from the stored values.  layout selects ghosted or

@@ -15,6 +15,17 @@
 #include "tvd_stream_params.hpp"
 
 #include <memory>
+#include <mutex>
+
+// Scratch of the allocation-free streamed advance
+// (tvd_patch_advance_stream_noalloc): per-tile partials of the fused signal
+// speed ([kScratchParts] doubles) followed by those of the compensated sums
+// ([kScratchParts][10]), 5.8 MB.  Each device that loads the library holds
+// its own copy until the process ends.  In host code `scratch` names a host
+// stand-in, never the device memory: kernels and fills get the address that
+// hipGetSymbolAddress returned for the current device (scratch_address).
+constexpr int64_t kScratchParts = 65536;
+static __device__ __align__(256) double scratch[11 * kScratchParts];
 
 // Generation of a context's workspace, shared with the graphs captured on
 // it: it changes whenever tvd_reserve replaces the workspace buffers (and
@@ -47,6 +58,8 @@ struct tvd_ctx {
   int cus = 256;                  // compute units (one persistent workgroup each)
   // tuned variants, per dtype (index 0: FP32, 1: FP64) and edge (0: 8, 1: 16)
   int tuned[2][2] = {{-1, -1}, {-1, -1}};
+  // device address of this device's static scratch array
+  double* scratch = nullptr;
 };
 
 namespace {
@@ -80,6 +93,23 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+// Device address of the static scratch array on `device`, looked up once per
+// device (with that device current) and kept for the life of the process.
+double* scratch_address(int device) {
+  static std::mutex mu;
+  static double* addr[64] = {};
+  static bool done[64] = {};
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    addr[device] = static_cast<double*>(p);
+    done[device] = true;
+  }
+  return addr[device];
+}
 
 bool stream_capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -233,7 +263,8 @@ int tvd_create(tvd_ctx** out, int device) {
       hipMemset(ctx->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
       hipMalloc(&ctx->plan_small, 16 * sizeof(int32_t)) != hipSuccess ||
       hipMemset(ctx->plan_small, 0, 16 * sizeof(int32_t)) != hipSuccess ||
-      reserve(ctx, 1024) != TVD_OK || hipDeviceSynchronize() != hipSuccess) {
+      reserve(ctx, 1024) != TVD_OK || (ctx->scratch = scratch_address(device)) == nullptr ||
+      hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(ctx->counters);
     (void)hipFree(ctx->plan_small);
     (void)hipFree(ctx->plan_list);
@@ -414,29 +445,17 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
-                      int32_t sweep_order, double gamma, double p_floor, int32_t flags,
-                      double* d_smax, double* d_sums, void* stream) {
-  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
-                      d_sums, stream, nullptr);
-}
-
-int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
-                             const void* d_u_in, void* d_u_out, int32_t sweep_order,
-                             double gamma, double p_floor, int32_t flags, double* d_smax,
-                             double* d_sums, void* stream) {
-  if (!ctx) return TVD_ERR_INVALID_ARG;
-  if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
-  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
-                      d_sums, stream, d_nbr);
-}
-
-int tvd_patch_advance_stream(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
-                             const tvd_chains* chains, const void* d_u_in, void* d_u_out,
-                             int32_t sweep_order, double gamma, double p_floor, int32_t flags,
-                             double* d_smax, double* d_sums, void* stream) {
+// Shared body of tvd_patch_advance_stream (partials in the context's
+// workspace) and tvd_patch_advance_stream_noalloc (partials in the static
+// scratch array): ws_smax [cap] and ws_sums [10 * cap] hold the per-tile
+// partials of the fused signal speed and sums.
+int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                const tvd_chains* chains, const void* d_u_in, void* d_u_out, int32_t sweep_order,
+                double gamma, double p_floor, int32_t flags, double* d_smax, double* d_sums,
+                void* stream, double* ws_smax, double* ws_sums, int64_t cap,
+                const char* cap_hint) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   int st = check_batch(ctx, batch, true);
   if (st) return st;
@@ -468,13 +487,17 @@ int tvd_patch_advance_stream(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
   const int64_t parts = (int64_t)batch->n_blocks * quads;
   if ((d_smax || d_sums) && parts > 0x7fffffff)
     return fail(ctx, TVD_ERR_INVALID_ARG, "too many blocks for the fused diagnostics");
-  if ((d_smax || d_sums) && (st = need_workspace(ctx, (int)parts))) return st;
+  if ((d_smax || d_sums) && parts > cap)
+    return fail(ctx, TVD_ERR_STATE, "the fused diagnostics need %lld partials and %s holds %lld",
+                (long long)parts, cap_hint, (long long)cap);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, TVD_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t s = (hipStream_t)stream;
   tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
   kp.nbr = d_nbr;
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
+  kp.ws_smax = ws_smax;
+  kp.ws_sums = ws_sums;
   tvd::StreamParams sp;
   sp.start = chains->d_start;
   sp.blocks = chains->d_blocks;
@@ -484,8 +507,8 @@ int tvd_patch_advance_stream(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
   hipError_t e = hipSuccess;
   // every per-tile partial starts at zero, so that blocks no valid chain
   // covers add nothing to the fused maximum and sums
-  if (d_smax) e = tvd::launch_zero_f64(ctx->ws_smax, parts, s);
-  if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(ctx->ws_sums, 10 * parts, s);
+  if (d_smax) e = tvd::launch_zero_f64(ws_smax, parts, s);
+  if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(ws_sums, 10 * parts, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
   const bool splitb = flags != TVD_STREAM_WHOLE_B;
   e = batch->dtype == TVD_F32
@@ -493,14 +516,59 @@ int tvd_patch_advance_stream(tvd_ctx* ctx, const tvd_batch* batch, const int32_t
           : tvd::launch_stream_f64(sweep_order, batch->edge, splitb, kp, sp, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "streamed kernel launch");
   if (d_smax) {
-    e = tvd::launch_finalize_max(ctx->ws_smax, (int)parts, d_smax, s);
+    e = tvd::launch_finalize_max(ws_smax, (int)parts, d_smax, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
   }
   if (d_sums) {
-    e = tvd::launch_finalize_sums(ctx->ws_sums, (int)parts, d_sums, s);
+    e = tvd::launch_finalize_sums(ws_sums, (int)parts, d_sums, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "finalize launch");
   }
   return TVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvd_patch_advance(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void* d_u_out,
+                      int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                      double* d_smax, double* d_sums, void* stream) {
+  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
+                      d_sums, stream, nullptr);
+}
+
+int tvd_patch_advance_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                             const void* d_u_in, void* d_u_out, int32_t sweep_order,
+                             double gamma, double p_floor, int32_t flags, double* d_smax,
+                             double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
+  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
+                      d_sums, stream, d_nbr);
+}
+
+int tvd_patch_advance_stream(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                             const tvd_chains* chains, const void* d_u_in, void* d_u_out,
+                             int32_t sweep_order, double gamma, double p_floor, int32_t flags,
+                             double* d_smax, double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  return stream_impl(ctx, batch, d_nbr, chains, d_u_in, d_u_out, sweep_order, gamma, p_floor,
+                     flags, d_smax, d_sums, stream, ctx->ws_smax, ctx->ws_sums, ctx->ws_blocks,
+                     "the workspace (tvd_reserve)");
+}
+
+int tvd_patch_advance_stream_noalloc(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                                     const tvd_chains* chains, const void* d_u_in,
+                                     void* d_u_out, int32_t sweep_order, double gamma,
+                                     double p_floor, int32_t flags, double* d_smax,
+                                     double* d_sums, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!ctx->scratch)
+    return fail(ctx, TVD_ERR_STATE, "the scratch array of device %d was not resolved",
+                ctx->device);
+  return stream_impl(ctx, batch, d_nbr, chains, d_u_in, d_u_out, sweep_order, gamma, p_floor,
+                     flags, d_smax, d_sums, stream, ctx->scratch,
+                     ctx->scratch + kScratchParts, kScratchParts, "the static scratch array");
 }
 
 int tvd_patch_advance_flux(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in,

@@ -43,7 +43,7 @@ EXPORTS = [
     "tvd_autotune", "tvd_graph_begin", "tvd_graph_end", "tvd_graph_launch", "tvd_graph_destroy",
     "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
     "tvd_close_level", "tvd_poisson_sor", "tvd_gravity", "tvd_lerp",
-    "tvd_patch_advance_stream",
+    "tvd_patch_advance_stream", "tvd_patch_advance_stream_noalloc",
 ]
 
 
@@ -93,6 +93,9 @@ def load(path: str = LIB_PATH):
                                                     vp, vp]),
         "tvd_patch_advance_stream": (ctypes.c_int, [vp, bp, vp, ctypes.POINTER(tvd_chains), vp,
                                                     vp, i32, dbl, dbl, i32, vp, vp, vp]),
+        "tvd_patch_advance_stream_noalloc": (ctypes.c_int, [vp, bp, vp,
+                                                            ctypes.POINTER(tvd_chains), vp, vp,
+                                                            i32, dbl, dbl, i32, vp, vp, vp]),
         "tvd_max_signal_speed": (ctypes.c_int, [vp, bp, vp, i32, dbl, dbl, vp, vp]),
         "tvd_dt_from_speed": (ctypes.c_int, [vp, bp, vp, dbl, vp, vp]),
         "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
@@ -235,6 +238,16 @@ class Context:
                                                _ptr(u_in), _ptr(u_out), sweep_order, gamma,
                                                p_floor, flags, _ptr(smax), _ptr(sums),
                                                _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_patch_advance_stream_noalloc(self, batch: Batch, nbr, chains: "Chains", u_in, u_out,
+                                         sweep_order: int, gamma: float, p_floor: float = 0.0,
+                                         flags: int = TVD_KERNEL_AUTO, smax=None, sums=None,
+                                         stream=None, check: bool = True):
+        st = self.lib.tvd_patch_advance_stream_noalloc(self.h, batch.ref, _ptr(nbr), chains.ref,
+                                                       _ptr(u_in), _ptr(u_out), sweep_order,
+                                                       gamma, p_floor, flags, _ptr(smax),
+                                                       _ptr(sums), _stream(stream))
         return self._check(st) if check else st
 
     def tvd_patch_advance_flux(self, batch: Batch, u_in, u_out, flux, flux_off, sweep_order: int,
