@@ -3,7 +3,8 @@
 * Pressure floor (the reading P* = max(P, p_floor) in the fluxes, the sound
   speed and the signal speed, the stored energy untouched): a cold,
   supersonic lognormal state whose pressures lie around the floor, so that
-  at least 10 % of the cells are floored, in FP64 (<= 1e-12 relative L1 and
+  at least 10 % of the initial cells are floored and the floor changes the
+  result well beyond the parity bounds, in FP64 (<= 1e-12 relative L1 and
   Linf) and FP32 (the rough-data bounds), with every kernel.
 * gamma = 1 (pressureless gas: P = 0, c_s = 0, c = |v_d|) with a third of
   the cells at rest, where the freezing speed is exactly 0 and the split
@@ -14,7 +15,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import FP32_ROUGH, FP64, check, norms, note, oracle_periodic
+from gpu_helpers import FP32_ROUGH, FP64, check, norms, note, oracle_periodic, worst
 from paper_0907_3390_amd import layout, tvd, workloads as wl
 from paper_0907_3390_amd.driver import DeviceBlocks
 
@@ -72,25 +73,34 @@ def floored_fraction(u, p_floor, gamma=5.0 / 3.0):
 
 @pytest.mark.parametrize("mode", list(MODES))
 def test_pressure_floor_parity(ctx, mode):
-    """A cold supersonic state with p_floor 1e-4: >= 10 % of the cells are
-    floored in the initial and in the final state; the GPU matches the
-    oracle (which applies the same floor) after 4 steps and reports floored
-    cells."""
+    """A cold supersonic state with p_floor 1e-4: about half of the initial
+    cells are floored (>= 10 % required).  The supersonic flow shocks and
+    heats the gas, so few cells stay below the floor after the first step;
+    the floor's effect on the result is therefore required instead: the
+    oracle without the floor differs from the oracle with it by at least 10x
+    the parity bound (relative L1), so a device that skipped the floor would
+    fail.  The GPU matches the oracle with the floor after 4 steps and
+    reports floored cells."""
     dtype = MODES[mode][0]
     note(f"pressure floor parity, {mode}")
     pf = 1e-4
     g = cold_supersonic(32, seed=41, p_floor=pf)
     if dtype == torch.float32:
         g = g.astype(np.float32).astype(np.float64)
-    assert floored_fraction(g, pf) >= 0.1
+    frac0 = floored_fraction(g, pf)
+    assert frac0 >= 0.1
     want, _ = oracle_periodic(g, 4, p_floor=pf)
-    frac = floored_fraction(want, pf)
+    free, _ = oracle_periodic(g, 4, p_floor=0.0)
+    bounds = FP64 if dtype == torch.float64 else FP32_ROUGH
+    effect = worst(norms(free, want))
+    assert effect >= 10 * bounds[0], effect
     got, floored, bad = run_mode(ctx, g, 4, mode, p_floor=pf)
     nrm = norms(got, want)
-    note(f"  floored fraction {frac:.2f}, device floored count {floored}, " +
+    note(f"  initial floored fraction {frac0:.2f}, floor effect {effect:.1e}, device floored "
+         f"count {floored}, " +
          str({k: (f"{v['relL1']:.1e}", f"{v['relLinf']:.1e}") for k, v in nrm.items()}))
-    assert frac >= 0.1 and floored > 0 and bad == 0
-    check(nrm, FP64 if dtype == torch.float64 else FP32_ROUGH)
+    assert floored > 0 and bad == 0
+    check(nrm, bounds)
 
 
 @pytest.mark.parametrize("mode", list(MODES))
