@@ -927,20 +927,23 @@ hipError_t launch_flux_correct(int dtype, const KParams& ck, const KParams& fk, 
   return hipGetLastError();
 }
 
+// grid-stride: any n up to the entry point's limit with a grid that stays
+// far below the 2^32 work-item limit of a launch
 __global__ void k_lerp_f32(int64_t n, const float* a, const float* b, float* out, float w) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[i] = a[i] + w * (b[i] - a[i]);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = a[i] + w * (b[i] - a[i]);
 }
 
 __global__ void k_lerp_f64(int64_t n, const double* a, const double* b, double* out, double w) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[i] = a[i] + w * (b[i] - a[i]);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = a[i] + w * (b[i] - a[i]);
 }
 
 hipError_t launch_lerp(int dtype, int64_t n, const void* a, const void* b, void* out, double w,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const int64_t want = (n + 255) / 256;
+  const dim3 grid((unsigned)(want < (1 << 20) ? want : (1 << 20))), block(256);
   if (dtype == 1)
     hipLaunchKernelGGL(k_lerp_f32, grid, block, 0, s, n, static_cast<const float*>(a),
                        static_cast<const float*>(b), static_cast<float*>(out), (float)w);
