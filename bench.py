@@ -178,7 +178,7 @@ def tune_stream(ctx, dev, candidates, reps=2):
 
 
 def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=False,
-            p_floor=0.0, sums=False, stream=False):
+            p_floor=0.0, sums=False, stream=False, chain_len=None):
     """Warm up, then time `steps` steps (an even number) twice: eagerly with
     HIP events around every advance launch (for the kernel's average
     duration), and as replays of a HIP graph holding one xyz/zyx pair (for
@@ -194,13 +194,16 @@ def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=Fal
     # blocks is a compact brick, so neighbours' ghost data meet in its L2
     bs = layout.periodic_grid_blockset(N, n, curve="morton")
     dev = DeviceBlocks(ctx, bs, dtype=dtype, gamma=GAMMA, cfl=CFL, kernel=kernel, gather=gather,
-                       p_floor=p_floor, stream=stream)
+                       p_floor=p_floor, stream=stream, chain_len=chain_len)
     dev.upload(layout.grid_to_blocks(grid32, n, bs.perm))
     info = {"blocks": bs.n_blocks, "edge": n}
     if sums:
         # exact sums of the initial state (the reference for the drift)
         dev.conservation_sums()
         info["sums0"] = dev.sums.cpu().numpy().tolist()
+    if stream and not tune:
+        info["variant"] = {"chain_len": dev.chain_len,
+                           "second_sweep": "whole pencils" if kernel else "half pencils"}
     if tune and stream:
         col = N // n
         lens = sorted({L for L in (col // 4, col // 2, col) if 2 <= L <= 64})
@@ -718,6 +721,90 @@ def run_amr_fill(ctx, reps=20):
     return res
 
 
+def run_host_pipeline_bench(ctx, grid32, reps=3):
+    """The host-resident advance (tvd_patch_advance_host) of the 256^3 level
+    as 4096 patch groups of 16^3 held in host memory, FP32.
+
+    table1: one launch of 1024 groups (the paper's GPU solver call of N_s x
+    N_g groups) with N_s = 1, 2, 4, 8 streams: per group, the copy down, the
+    advance and the copy up as each stream sees them, the GPU's span, and
+    the transfer time as a share of the advance time (exposed: span minus
+    advance); the preparation and closing steps are not in these figures, as
+    in the paper's hydrodynamic timing table.
+    level: the whole level in four launches of N_s = 4 x N_g = 256 groups,
+    with the host's preparation and closing steps overlapped with the GPU
+    (Sec. 3.5) or not: wall time and host-inclusive cell-updates/s."""
+    import torch
+    from paper_0907_3390_amd import layout, tvd
+    n, N = 16, grid32.shape[3]
+    bs = layout.periodic_grid_blockset(N, n, curve="morton")
+    u = bs.pack_interior(layout.grid_to_blocks(grid32, n, bs.perm)).astype(np.float32)
+    out = np.empty_like(u)
+    batch = tvd.Batch(tvd.TVD_F32, bs.n_blocks, n, dt=0.2 / N, dh=1.0 / N)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    res = {"workload": f"{N}^3 lognormal level as {bs.n_blocks} patch groups of 16^3 in host "
+                       f"memory (pageable), FP32", "host_threads": threads,
+           "staging": "page-locked host staging (torch pin_memory), device staging per stream"}
+
+    def run(ns, ng, concurrent, nblocks):
+        streams = [torch.cuda.Stream() for _ in range(ns)]
+        pipe = tvd.HostPipeline(streams, ng, threads, concurrent)
+        hb, db = pipe.stage_bytes(tvd.TVD_F32, n)
+        pipe.attach(torch.empty(hb, dtype=torch.uint8, pin_memory=True),
+                    torch.empty(db, dtype=torch.uint8, device="cuda"))
+        b = tvd.Batch(tvd.TVD_F32, nblocks, n, dt=0.2 / N, dh=1.0 / N)
+        nbr = np.ascontiguousarray(bs.nbr[:nblocks]) if nblocks < bs.n_blocks else bs.nbr
+        if nblocks < bs.n_blocks:
+            # the first nblocks groups with their neighbours folded into the
+            # subset (a copy pattern of the same size; the values are not kept)
+            nbr = np.ascontiguousarray(nbr % nblocks).astype(np.int32)
+        best = None
+        for _ in range(reps + 1):
+            _, t = ctx.tvd_patch_advance_host(b, nbr, u, out, pipe, 0, GAMMA, 0.0, times=True)
+            if best is None or t["wall"] < best["wall"]:
+                best = t
+        return best
+
+    table = {}
+    per_launch = 1024
+    for ns in (1, 2, 4, 8):
+        t = run(ns, per_launch // ns, False, per_launch)
+        g = per_launch
+        table[f"N_s={ns}"] = {
+            "N_g": per_launch // ns,
+            "copy_down_us_per_group": 1e3 * t["copy_down"] / g,
+            "advance_us_per_group": 1e3 * t["advance"] / g,
+            "copy_up_us_per_group": 1e3 * t["copy_up"] / g,
+            "gpu_span_us_per_group": 1e3 * t["gpu_span"] / g,
+            "transfer_share_of_advance": (t["copy_down"] + t["copy_up"]) / t["advance"],
+            "exposed_transfer_share_of_advance": (t["gpu_span"] - t["advance"]) / t["advance"],
+            "host_prepare_ms": t["host_prepare"], "host_close_ms": t["host_close"]}
+        log(f"bench: host pipeline N_s={ns}: span {t['gpu_span']:.2f} ms, advance "
+            f"{t['advance']:.2f} ms, down {t['copy_down']:.2f} ms, up {t['copy_up']:.2f} ms")
+    res["table1"] = table
+    res["table1_bytes"] = {"down_per_group": 5 * 22 ** 3 * 4, "up_per_group": 5 * 16 ** 3 * 4}
+    level = {}
+    for concurrent in (False, True):
+        t = run(4, 256, concurrent, bs.n_blocks)
+        level["concurrent" if concurrent else "sequential"] = {
+            "wall_ms": t["wall"], "cell_updates_per_s": N ** 3 / (t["wall"] * 1e-3),
+            "host_prepare_ms": t["host_prepare"], "host_close_ms": t["host_close"],
+            "copy_down_ms": t["copy_down"], "advance_ms": t["advance"], "copy_up_ms": t["copy_up"],
+            "gpu_span_ms": t["gpu_span"]}
+        log(f"bench: host pipeline level, concurrent={concurrent}: {t['wall']:.1f} ms")
+    level["overlap_saving"] = 1.0 - level["concurrent"]["wall_ms"] / level["sequential"]["wall_ms"]
+    res["level_N_s4_N_g256"] = level
+    res["paper_context"] = {
+        "note": "the paper's hydrodynamic solver per patch group (Tesla T10 / 8800 GTX, PCIe "
+                "gen 1-2), context only",
+        "kernel_us_per_group": {"GraCCA": 252, "NCHC": 144, "CQSE": 150},
+        "copy_down_us_per_group": {"GraCCA": 71, "NCHC": 51, "CQSE": 44},
+        "copy_up_us_per_group": {"GraCCA": 46, "NCHC": 64, "CQSE": 29},
+        "transfer_share_one_stream": {"GraCCA": 0.464, "NCHC": 0.799, "CQSE": 0.487},
+        "transfer_share_four_streams": {"NCHC": 0.229, "CQSE": 0.180}}
+    return res
+
+
 def host_cpu():
     """Model name and logical CPU count of the host, and the OpenMP thread
     count the oracle is run with."""
@@ -917,6 +1004,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-variant tuner")
     ap.add_argument("--no-config2", action="store_true", help="skip the 256^3 lognormal runs")
+    ap.add_argument("--chain-len", type=int, default=None,
+                    help="with --no-tune: chain length of the streamed headline run")
+    ap.add_argument("--whole-b", action="store_true",
+                    help="with --no-tune: second sweep in whole pencils in the headline run")
     ap.add_argument("--extras", action="store_true",
                     help="also run the ghost fill, multi-level, closing, nested, Poisson, "
                          "gravity and uneven-batch measurements")
@@ -948,9 +1039,10 @@ def main():
            f"gamma=5/3, CFL 0.5, p_floor 1e-10, seed {SEED_BLAST}")
     log(f"bench: headline FP32, edge {n}, streamed advance, {warmup}+{steps}+{steps} steps, "
         f"sums every step")
-    dev5, r5 = run_gpu(ctx, grid5, n, torch.float32, tvd.TVD_KERNEL_AUTO, steps, warmup,
-                       gather=True, tune=not args.no_tune, p_floor=P_FLOOR_BLAST, sums=True,
-                       stream=True)
+    dev5, r5 = run_gpu(ctx, grid5, n, torch.float32,
+                       tvd.TVD_STREAM_WHOLE_B if args.whole_b else tvd.TVD_KERNEL_AUTO, steps,
+                       warmup, gather=True, tune=not args.no_tune, p_floor=P_FLOOR_BLAST,
+                       sums=True, stream=True, chain_len=args.chain_len)
     planes5 = dev5.chain_len * n
     head = headline_record(r5, cells5, steps, n, "512^3 blast FP32 streamed", wl5,
                            stream_planes=planes5)
@@ -1014,6 +1106,8 @@ def main():
         out["speedup_streamed_vs_per_block"] = value / pb["value"]
         del dpb
         torch.cuda.empty_cache()
+    # a plain copy of known size: the peak measured on this machine, and the
+    # calibration of the HBM counters when this run is profiled
     out["hbm_copy_measured"] = copy_bandwidth()
     out["roofline"]["hbm"]["frac_of_measured_copy"] = (
         head["GBs"] / out["hbm_copy_measured"]["read_plus_write_GBs"])
@@ -1076,6 +1170,8 @@ def main():
                 torch.cuda.empty_cache()
                 log(f"bench: {name} {c2[name]['value'] / 1e9:.3f} G cell-updates/s")
             del g64
+        log("bench: host-resident pipeline (N_s streams) on the 256^3 level")
+        c2["host_pipeline"] = run_host_pipeline_bench(ctx, grid2)
         del g2_32
         out["lognormal_256cube"] = c2
         torch.cuda.empty_cache()

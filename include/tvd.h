@@ -283,6 +283,79 @@ int tvd_patch_advance_stream_noalloc(tvd_ctx *ctx, const tvd_batch *batch,
                                      double gamma, double p_floor, int32_t flags,
                                      double *d_smax, double *d_sums, void *stream);
 
+/* ---- host-resident advance (Sec. 3.1 stream objects, Sec. 3.5) ---------- */
+
+/*
+ * How tvd_patch_advance_host moves a host-resident level through the GPU.
+ * A launch takes n_streams * groups_per_stream blocks (the paper's N_s x
+ * N_g patch groups); stream s carries one copy down, one advance and one
+ * copy up of groups_per_stream of them, so that one stream's copies overlap
+ * another stream's advance.
+ *   n_streams          N_s, 1 .. 16.
+ *   groups_per_stream  N_g >= 1 (N_s * N_g <= 2^20).
+ *   host_threads       threads of the host's preparation and closing steps,
+ *                      1 .. 256.
+ *   concurrent         1: the host prepares launch k+1 and closes launch k-1
+ *                      while the GPU works on launch k (Sec. 3.5); 0: the
+ *                      host waits for each launch before the next.
+ *   streams            [n_streams] hipStream_t (void*), created by the caller
+ *                      (default priority).
+ *   h_stage            page-locked host memory (hipHostMalloc) of at least
+ *                      the h_stage_bytes of tvd_pipeline_stage_bytes: two
+ *                      launches of ghosted blocks, then two of interiors.
+ *                      Pageable memory works but its copies do not overlap.
+ *   d_stage            device memory of at least d_stage_bytes: per stream,
+ *                      N_g ghosted blocks, then N_g interiors.
+ * The staging buffers are the caller's and are overwritten by every call.
+ */
+typedef struct {
+    int32_t n_streams;
+    int32_t groups_per_stream;
+    int32_t host_threads;
+    int32_t concurrent;
+    void *const *streams;
+    void *h_stage;
+    void *d_stage;
+} tvd_host_pipeline;
+
+/* Staging sizes in bytes for a pipeline of blocks of `edge` (8 or 16) and
+ * `dtype`.  TVD_ERR_INVALID_ARG for sizes outside the limits above. */
+int tvd_pipeline_stage_bytes(int32_t dtype, int32_t edge, const tvd_host_pipeline *pipe,
+                             int64_t *h_stage_bytes, int64_t *d_stage_bytes);
+
+/*
+ * One step (one triple) of a level whose blocks live in host memory, as in
+ * the paper's GPU solver (Sec. 3.1: preparation step, copy down, kernel, copy
+ * up, closing step, with N_s stream objects; Sec. 3.5: the host's steps
+ * overlapped with the GPU's).
+ *   batch     dense, uniform edge (FP32: 8 or 16; FP64: 8), scalar dt and dh;
+ *             no device arrays (else TVD_ERR_UNSUPPORTED).
+ *   h_nbr     host int32 [n_blocks][27]: the block covering each of the 27
+ *             regions around block b (region (rx+1) + 3(ry+1) + 9(rz+1)),
+ *             every entry in [0, n_blocks) (checked; else
+ *             TVD_ERR_INVALID_ARG).
+ *   h_u_in    host: n_blocks interior blocks (5 cubes of edge^3 each);
+ *   h_u_out   host: the advanced interiors, same layout; must not overlap
+ *             h_u_in or h_stage (TVD_ERR_ALIAS).
+ *   times     NULL, or double[7] receiving in ms: the call's wall time, the
+ *             host's preparation and closing time, the durations of the
+ *             copies down, the advances and the copies up summed over
+ *             streams and launches (each measured on its stream), and the
+ *             GPU's span from the first copy down to the end of the last
+ *             copy up.
+ * The preparation step copies each ghosted block from the interiors of the
+ * block and its neighbours (sibling ghost zones), the closing step copies
+ * each result back; the advance is the batched kernel of
+ * tvd_patch_advance.  The results equal, bit for bit, tvd_fill_ghosts then
+ * tvd_patch_advance on the device.  Synchronous: returns when h_u_out holds
+ * every block.  Creates and destroys its HIP events; not capture-safe
+ * (TVD_ERR_STATE while capturing).  Health counters as for
+ * tvd_patch_advance.
+ */
+int tvd_patch_advance_host(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *h_nbr,
+                           const void *h_u_in, void *h_u_out, const tvd_host_pipeline *pipe,
+                           int32_t sweep_order, double gamma, double p_floor, double *times);
+
 /*
  * Eq. (CFL) signal speed: d_smax[0] = max over the interior cells of all
  * blocks of c_s + max(|v_x|, |v_y|, |v_z|), with c_s from max(P, p_floor);

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "_lib", "libtvd.so")
 SOURCES = ["tvd_k_stream_f32.hip", "tvd_k_batched_f32_e16.hip", "tvd_k_stream_f64.hip",
            "tvd_kernels.hip", "tvd_k_batched_f32_e8.hip", "tvd_k_batched_f64_e8.hip",
-           "tvd_k_fused.hip", "tvd_capi.hip"]
+           "tvd_k_fused.hip", "tvd_pipeline.hip", "tvd_capi.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 

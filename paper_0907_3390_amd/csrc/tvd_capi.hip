@@ -571,6 +571,98 @@ int tvd_patch_advance_stream_noalloc(tvd_ctx* ctx, const tvd_batch* batch, const
                      ctx->scratch + kScratchParts, kScratchParts, "the static scratch array");
 }
 
+int tvd_pipeline_stage_bytes(int32_t dtype, int32_t edge, const tvd_host_pipeline* pipe,
+                             int64_t* h_stage_bytes, int64_t* d_stage_bytes) {
+  if (!pipe || (dtype != TVD_F32 && dtype != TVD_F64) || (edge != 8 && edge != 16))
+    return TVD_ERR_INVALID_ARG;
+  if (pipe->n_streams < 1 || pipe->n_streams > 16 || pipe->groups_per_stream < 1 ||
+      (int64_t)pipe->n_streams * pipe->groups_per_stream > (1 << 20))
+    return TVD_ERR_INVALID_ARG;
+  const int64_t es = dtype == TVD_F32 ? 4 : 8;
+  const int64_t g = 5 * (int64_t)(edge + 6) * (edge + 6) * (edge + 6) * es;
+  const int64_t i = 5 * (int64_t)edge * edge * edge * es;
+  const int64_t per_launch = (int64_t)pipe->n_streams * pipe->groups_per_stream;
+  if (h_stage_bytes) *h_stage_bytes = 2 * per_launch * (g + i);
+  if (d_stage_bytes) *d_stage_bytes = per_launch * (g + i);
+  return TVD_OK;
+}
+
+int tvd_patch_advance_host(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* h_nbr,
+                           const void* h_u_in, void* h_u_out, const tvd_host_pipeline* pipe,
+                           int32_t sweep_order, double gamma, double p_floor, double* times) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch);
+  if (st) return st;
+  if ((st = check_gamma(ctx, gamma, p_floor))) return st;
+  if (sweep_order != TVD_XYZ && sweep_order != TVD_ZYX)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "sweep_order %d", sweep_order);
+  if (batch->d_edge || batch->d_in_off || batch->d_out_off || batch->d_dt || batch->d_dh)
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "the host-resident advance takes a dense batch of uniform edge with scalar dt "
+                "and dh (no device arrays)");
+  if (batch->dtype == TVD_F64 && batch->edge != 8)
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "FP64 blocks of edge %d (the batched kernel holds "
+                "FP64 blocks of edge 8)", batch->edge);
+  if (!pipe) return fail(ctx, TVD_ERR_INVALID_ARG, "pipe is NULL");
+  int64_t hb = 0, db = 0;
+  if (tvd_pipeline_stage_bytes(batch->dtype, batch->edge, pipe, &hb, &db) != TVD_OK)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "n_streams %d (1..16), groups_per_stream %d (>= 1)",
+                pipe->n_streams, pipe->groups_per_stream);
+  if (pipe->host_threads < 1 || pipe->host_threads > 256)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "host_threads %d (1..256)", pipe->host_threads);
+  if (pipe->concurrent != 0 && pipe->concurrent != 1)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "concurrent %d is neither 0 nor 1", pipe->concurrent);
+  if (batch->n_blocks == 0) {
+    if (times)
+      for (int k = 0; k < 7; ++k) times[k] = 0.0;
+    return TVD_OK;
+  }
+  if (!h_nbr || !h_u_in || !h_u_out || !pipe->streams || !pipe->h_stage || !pipe->d_stage)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  // host memory can be checked here, unlike the device arrays of a batch
+  const int64_t nb = batch->n_blocks;
+  for (int64_t k = 0; k < 27 * nb; ++k)
+    if (h_nbr[k] < 0 || h_nbr[k] >= nb)
+      return fail(ctx, TVD_ERR_INVALID_ARG, "h_nbr[%lld][%lld] = %d is not a block",
+                  (long long)(k / 27), (long long)(k % 27), h_nbr[k]);
+  const size_t len = (size_t)nb * 5 * batch->edge * batch->edge * batch->edge *
+                     elem_size(batch->dtype);
+  {
+    const char* a = (const char*)h_u_in;
+    const char* b = (const char*)h_u_out;
+    if (a < b + len && b < a + len) return fail(ctx, TVD_ERR_ALIAS, "h_u_in and h_u_out overlap");
+    const char* c = (const char*)pipe->h_stage;
+    if ((c < a + len && a < c + hb) || (c < b + len && b < c + hb))
+      return fail(ctx, TVD_ERR_ALIAS, "h_stage overlaps h_u_in or h_u_out");
+  }
+  if (ctx->capturing) return fail(ctx, TVD_ERR_STATE, "the host-resident advance cannot be captured");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, TVD_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  for (int s = 0; s < pipe->n_streams; ++s)
+    if (stream_capturing((hipStream_t)pipe->streams[s]))
+      return fail(ctx, TVD_ERR_STATE, "stream %d is capturing", s);
+  tvd::HostPipe hp;
+  hp.dtype = batch->dtype;
+  hp.edge = batch->edge;
+  hp.order = sweep_order;
+  hp.n_blocks = nb;
+  hp.h_nbr = h_nbr;
+  hp.h_in = h_u_in;
+  hp.h_out = h_u_out;
+  hp.ns = pipe->n_streams;
+  hp.ng = pipe->groups_per_stream;
+  hp.threads = pipe->host_threads;
+  hp.concurrent = pipe->concurrent == 1;
+  hp.h_stage = pipe->h_stage;
+  hp.d_stage = pipe->d_stage;
+  hp.streams = reinterpret_cast<const hipStream_t*>(pipe->streams);
+  hp.variant = chosen_variant(ctx, batch->dtype, batch->edge);
+  hp.kp = make_params(ctx, batch, nullptr, nullptr, gamma, p_floor);
+  const hipError_t e = tvd::run_host_pipeline(hp, times);
+  if (e != hipSuccess) return hip_fail(ctx, e, "host-resident pipeline");
+  return TVD_OK;
+}
+
 int tvd_patch_advance_flux(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in,
                            void* d_u_out, void* d_flux, const int64_t* d_flux_off,
                            double flux_weight, int32_t accumulate, int32_t sweep_order,

@@ -118,6 +118,30 @@ hipError_t launch_stream_f64(int order, int edge, bool splitb, const KParams& kp
 // Zero n doubles (fill kernel, capture-safe).
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 
+// The host-resident advance (tvd_pipeline.hip): n_blocks interior blocks of
+// uniform edge in host memory (h_in, h_out), neighbour table h_nbr
+// [n_blocks][27], advanced in launches of ns x ng blocks on the ns streams.
+// kp carries dt, dh, gamma, p_floor and the health counters.
+struct HostPipe {
+  int dtype, edge, order;
+  int64_t n_blocks;
+  const int32_t* h_nbr;
+  const void* h_in;
+  void* h_out;
+  int ns, ng, threads;
+  bool concurrent;
+  void* h_stage;   // page-locked: 2 x ns x ng ghosted blocks, then 2 x ns x ng interiors
+  void* d_stage;   // per stream: ng ghosted blocks, then ng interiors
+  const hipStream_t* streams;
+  Variant variant;
+  KParams kp;
+};
+// Runs the whole pipeline and returns when h_out holds every result;
+// times (optional): wall, host preparation, host closing, the summed
+// durations of the copies down, the advances and the copies up, and the
+// GPU's span from the first copy down to the last copy up (ms).
+hipError_t run_host_pipeline(const HostPipe& hp, double times[7]);
+
 // Variants compiled into the library.
 int variant_count();
 Variant variant_at(int i);

@@ -44,6 +44,7 @@ EXPORTS = [
     "tvd_fill_ghosts_amr", "tvd_patch_advance_flux", "tvd_restrict", "tvd_flux_correct",
     "tvd_close_level", "tvd_poisson_sor", "tvd_gravity", "tvd_lerp",
     "tvd_patch_advance_stream", "tvd_patch_advance_stream_noalloc",
+    "tvd_pipeline_stage_bytes", "tvd_patch_advance_host",
 ]
 
 
@@ -56,6 +57,13 @@ class TvdError(RuntimeError):
 class tvd_chains(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int32), ("n_members", ctypes.c_int32),
                 ("d_start", ctypes.c_void_p), ("d_blocks", ctypes.c_void_p)]
+
+
+class tvd_host_pipeline(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("groups_per_stream", ctypes.c_int32),
+                ("host_threads", ctypes.c_int32), ("concurrent", ctypes.c_int32),
+                ("streams", ctypes.POINTER(ctypes.c_void_p)), ("h_stage", ctypes.c_void_p),
+                ("d_stage", ctypes.c_void_p)]
 
 
 class tvd_batch(ctypes.Structure):
@@ -96,6 +104,11 @@ def load(path: str = LIB_PATH):
         "tvd_patch_advance_stream_noalloc": (ctypes.c_int, [vp, bp, vp,
                                                             ctypes.POINTER(tvd_chains), vp, vp,
                                                             i32, dbl, dbl, i32, vp, vp, vp]),
+        "tvd_pipeline_stage_bytes": (ctypes.c_int, [i32, i32, ctypes.POINTER(tvd_host_pipeline),
+                                                    i64p, i64p]),
+        "tvd_patch_advance_host": (ctypes.c_int, [vp, bp, vp, vp, vp,
+                                                  ctypes.POINTER(tvd_host_pipeline), i32, dbl, dbl,
+                                                  ctypes.POINTER(ctypes.c_double)]),
         "tvd_max_signal_speed": (ctypes.c_int, [vp, bp, vp, i32, dbl, dbl, vp, vp]),
         "tvd_dt_from_speed": (ctypes.c_int, [vp, bp, vp, dbl, vp, vp]),
         "tvd_conservation_sums": (ctypes.c_int, [vp, bp, vp, i32, vp, vp]),
@@ -179,6 +192,50 @@ class Chains:
         return ctypes.byref(self.c)
 
 
+class HostPipeline:
+    """A tvd_host_pipeline over caller-created streams and staging buffers
+    (torch tensors: page-locked host memory and device memory), kept alive
+    here."""
+
+    def __init__(self, streams, groups_per_stream: int, host_threads: int, concurrent: bool,
+                 h_stage=None, d_stage=None):
+        self.streams = list(streams)
+        self._sp = (ctypes.c_void_p * len(self.streams))(
+            *[ctypes.c_void_p(st.cuda_stream) for st in self.streams])
+        self.h_stage, self.d_stage = h_stage, d_stage
+        self.c = tvd_host_pipeline(len(self.streams), groups_per_stream, host_threads,
+                                   1 if concurrent else 0,
+                                   ctypes.cast(self._sp, ctypes.POINTER(ctypes.c_void_p)),
+                                   _host_ptr(h_stage), _ptr(d_stage))
+
+    def stage_bytes(self, dtype: int, edge: int):
+        """(host, device) staging bytes this pipeline needs for (dtype, edge)."""
+        hb, db = ctypes.c_int64(), ctypes.c_int64()
+        st = load().tvd_pipeline_stage_bytes(dtype, edge, ctypes.byref(self.c), ctypes.byref(hb),
+                                             ctypes.byref(db))
+        if st != TVD_OK:
+            raise TvdError(st, "tvd_pipeline_stage_bytes: " + status_string(st))
+        return hb.value, db.value
+
+    def attach(self, h_stage, d_stage):
+        self.h_stage, self.d_stage = h_stage, d_stage
+        self.c.h_stage = _host_ptr(h_stage)
+        self.c.d_stage = _ptr(d_stage)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _host_ptr(a):
+    """Host address of a CPU torch tensor or numpy array (or None)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
+
+
 class Context:
     """Owns a tvd_ctx; methods carry the C entry points' names and arguments."""
 
@@ -249,6 +306,23 @@ class Context:
                                                        gamma, p_floor, flags, _ptr(smax),
                                                        _ptr(sums), _stream(stream))
         return self._check(st) if check else st
+
+    def tvd_patch_advance_host(self, batch: Batch, nbr, u_in, u_out, pipe: HostPipeline,
+                               sweep_order: int, gamma: float, p_floor: float = 0.0,
+                               times: bool = False, check: bool = True):
+        """Host arrays nbr (int32 [n][27]), u_in and u_out (numpy or CPU
+        tensors).  Returns (status, times) with times a dict of ms or None."""
+        t = (ctypes.c_double * 7)() if times else None
+        st = self.lib.tvd_patch_advance_host(self.h, batch.ref, _host_ptr(nbr), _host_ptr(u_in),
+                                             _host_ptr(u_out), pipe.ref, sweep_order, gamma,
+                                             p_floor, t)
+        if check:
+            self._check(st)
+        if t is None:
+            return st, None
+        keys = ("wall", "host_prepare", "host_close", "copy_down", "advance", "copy_up",
+                "gpu_span")
+        return st, {k: float(t[i]) for i, k in enumerate(keys)}
 
     def tvd_patch_advance_flux(self, batch: Batch, u_in, u_out, flux, flux_off, sweep_order: int,
                                gamma: float, p_floor: float = 0.0, flags: int = TVD_KERNEL_AUTO,
