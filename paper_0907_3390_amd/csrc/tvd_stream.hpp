@@ -224,6 +224,12 @@ struct StreamChain {
   // chain's ghost planes).  Chain ends use the same code with fewer planes,
   // so that one copy of each phase serves every slab.
   __device__ __forceinline__ void planes_ab(int cb, int rs, int s_lo, int lo, int hi) {
+    // An opaque copy of the thread index: the per-lane LDS and HBM addresses
+    // derived from it are recomputed in every slab instead of being hoisted
+    // out of the slab loop, where the compiler keeps dozens of them alive
+    // across all phases and spills them to scratch memory.
+    int tid = this->tid;
+    asm volatile("" : "+v"(tid));
     if (tid < 9) {
       const int ra = tid % 3 - 1, rb = tid / 3 - 1;
       const int nb = kp.nbr[27 * (int64_t)cb + AX::region(ra, rb, rs)];
@@ -231,12 +237,18 @@ struct StreamChain {
     }
     __syncthreads();
     const T* __restrict__ uin = reinterpret_cast<const T*>(kp.uin);
-    // phase A: 22 rows per plane, spread evenly over the four waves
+    // phase A: 22 rows per plane, spread evenly over the four waves.  Along
+    // x (forward step) each lane walks one contiguous row, so consecutive
+    // lanes take consecutive rows; along z (backward step) the lanes of a row
+    // take consecutive planes, i.e. consecutive x, so that one load
+    // instruction reads whole 32-byte pieces of x-rows instead of one value
+    // from each of 44 rows.
     {
       constexpr int npen = kRows * P;
       constexpr int per = (npen + 3) / 4;
       const int l = tid & 63, p = (tid >> 6) * per + l;
-      const int r = p % kRows, pl = p / kRows;
+      const int r = ORDER == 0 ? p % kRows : p / P;
+      const int pl = ORDER == 0 ? p / kRows : p % P;
       if (l < per && p < npen && pl >= lo && pl < hi) {
         const int b = b0 - kG + r;
         const int rb = b < 0 ? -1 : (b >= E ? 1 : 0);
@@ -320,6 +332,8 @@ struct StreamChain {
   // the plane after which the previous block's diagnostics are complete
   // (-1: none).
   __device__ __forceinline__ void planes_s(int g0, int lo, int hi, int emit_from, int pub_at) {
+    int tid = this->tid;  // opaque, as in planes_ab
+    asm volatile("" : "+v"(tid));
     const int al = tid & (kTile - 1), bl = tid / kTile;
     static_for<0, P>([&](auto I) {
       constexpr int pl = decltype(I)::value;
