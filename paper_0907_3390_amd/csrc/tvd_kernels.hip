@@ -165,40 +165,20 @@ __global__ __launch_bounds__(kFinNT) void k_finalize_max(const double* ws, int n
 }
 
 // The partials are n records of 10 doubles (sum, compensation of each
-// variable).  Thread t takes the doubles t, t + 1024, t + 2048, ... of the
-// flat array, so that every load instruction of a wave reads 512 contiguous
-// bytes: a sum part goes into the thread's compensated sum of its variable,
-// a compensation part into that sum's compensation (the two halves of
-// csum_merge).  Fixed assignment and fixed tree: deterministic.
+// variable).  Thread t merges the records t, t + 1024, t + 2048, ... in
+// that order, so that the lanes of a wave read consecutive records
+// (coalesced), then the fixed tree of block_csum: deterministic.
 __global__ __launch_bounds__(kFinNT) void k_finalize_sums(const double* ws, int n, double* out) {
   __shared__ CSum red[kFinNT / 64 * kNV];
   CSum a[kNV];
   for (int k = 0; k < kNV; ++k) a[k] = CSum{0.0, 0.0};
-  const int64_t total = (int64_t)n * 2 * kNV;
-  constexpr int U = 4;
-  int64_t i = threadIdx.x;
-  for (; i + (U - 1) * kFinNT < total; i += U * kFinNT) {
-    double v[U];
+  for (int b = threadIdx.x; b < n; b += kFinNT) {
+    const double2* r = reinterpret_cast<const double2*>(ws + (size_t)b * 2 * kNV);
+    double2 v[kNV];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = ws[i + u * kFinNT];
+    for (int k = 0; k < kNV; ++k) v[k] = r[k];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = (int)((i + u * kFinNT) % (2 * kNV));
-#pragma unroll
-      for (int k = 0; k < kNV; ++k) {
-        if (c == 2 * k) csum_add(a[k], v[u]);
-        else if (c == 2 * k + 1) a[k].c += v[u];
-      }
-    }
-  }
-  for (; i < total; i += kFinNT) {
-    const int c = (int)(i % (2 * kNV));
-    const double v = ws[i];
-#pragma unroll
-    for (int k = 0; k < kNV; ++k) {
-      if (c == 2 * k) csum_add(a[k], v);
-      else if (c == 2 * k + 1) a[k].c += v;
-    }
+    for (int k = 0; k < kNV; ++k) a[k] = csum_merge(a[k], CSum{v[k].x, v[k].y});
   }
   block_csum<kFinNT>(a, red, threadIdx.x);
   if (threadIdx.x == 0)

@@ -318,20 +318,21 @@ struct StreamChain {
     }
   }
 
-  __device__ __forceinline__ void publish(int kk) {
-    const int b = sp.blocks[chain0 + kk];
+  // The chain's diagnostics, once all its cells are finished, into the
+  // partial record of its first block (the records of the other blocks of
+  // the chain stay zero): one block reduction per chain instead of one per
+  // block.
+  __device__ __forceinline__ void publish() {
+    const int b = sp.blocks[chain0];
     diag_publish<kStreamNT>(dg, b * sp.quads + quad, dh, kp, sm.red, tid);
-    diag_init(dg);
   }
 
   // Phase S over the slab planes pl in [lo, hi): plane pl is chain plane
   // g = g0 + pl, chain step g + 3, ring position (3 + pl) mod 4 (g0 is a
   // multiple of 4 minus 0 for the blocks' planes and the closing ghost
   // planes, -8 for the opening ghost planes, which sit at pl = 5 .. 7).
-  // `emit_from` is the first plane whose finished cell is kept; `pub_at`
-  // the plane after which the previous block's diagnostics are complete
-  // (-1: none).
-  __device__ __forceinline__ void planes_s(int g0, int lo, int hi, int emit_from, int pub_at) {
+  // `emit_from` is the first plane whose finished cell is kept.
+  __device__ __forceinline__ void planes_s(int g0, int lo, int hi, int emit_from) {
     int tid = this->tid;  // opaque, as in planes_ab
     asm volatile("" : "+v"(tid));
     const int al = tid & (kTile - 1), bl = tid / kTile;
@@ -347,7 +348,6 @@ struct StreamChain {
         // finished cell g - 3, at position (pl - 3) mod RUN of its 16-byte run
         constexpr int rpos = ((pl - kG) % RUN + RUN) % RUN;
         if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out);
-        if (pl == pub_at) publish((g0 + pl - kG) / E);
       }
     });
     __syncthreads();
@@ -365,25 +365,24 @@ struct StreamChain {
     // planes of the tail's S+ neighbour), which finish the last block.
     const int nslab = C * (E / P) + 2;
     for (int t = 0; t < nslab; ++t) {
-      int cb, rs, s_lo, lo, hi, g0, emit_from, pub_at;
+      int cb, rs, s_lo, lo, hi, g0, emit_from;
       if (t == 0) {
         cb = sp.blocks[chain0];
-        rs = -1, s_lo = E - P, lo = P - kG, hi = P, g0 = -P, emit_from = P, pub_at = -1;
+        rs = -1, s_lo = E - P, lo = P - kG, hi = P, g0 = -P, emit_from = P;
       } else if (t == nslab - 1) {
         cb = sp.blocks[chain0 + C - 1];
-        rs = 1, s_lo = 0, lo = 0, hi = kG, g0 = C * E, emit_from = 0, pub_at = kG - 1;
+        rs = 1, s_lo = 0, lo = 0, hi = kG, g0 = C * E, emit_from = 0;
       } else {
         const int kk = (t - 1) / (E / P), m = (t - 1) % (E / P);
         cb = sp.blocks[chain0 + kk];
         rs = 0, s_lo = m * P, lo = 0, hi = P, g0 = kk * E + m * P;
-        // the chain's first three planes finish nothing (cells -3 .. -1); the
-        // third plane of every later block finishes the previous block
+        // the chain's first three planes finish nothing (cells -3 .. -1)
         emit_from = (kk == 0 && m == 0) ? kG : 0;
-        pub_at = (kk > 0 && m == 0) ? kG - 1 : -1;
       }
       planes_ab(cb, rs, s_lo, lo, hi);
-      planes_s(g0, lo, hi, emit_from, pub_at);
+      planes_s(g0, lo, hi, emit_from);
     }
+    publish();
   }
 };
 
