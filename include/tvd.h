@@ -245,11 +245,16 @@ enum { TVD_STREAM_WHOLE_B = 16 };  /* second sweep in whole pencils (default: ha
  * side) applies to the chain as a whole.
  *   batch    uniform edge 16 or 32 (d_edge NULL; else TVD_ERR_UNSUPPORTED),
  *            TVD_F32 or TVD_F64.
+ *   d_u_in, d_u_out  16-byte aligned (else TVD_ERR_INVALID_ARG); block
+ *            offsets (d_out_off, or the dense layout) must be multiples of
+ *            16 bytes, since rows are read and written 16 bytes at a time.
  *   chains   chains along z for TVD_XYZ, along x for TVD_ZYX.  A chain whose
  *            blocks are not consecutive along that axis, or whose blocks
  *            lack a neighbour of the same edge, or differ in dt or dh, or
- *            has more than 64 blocks, is not advanced: its output is left
- *            untouched and its cells are counted as non-physical.
+ *            has more than 64 blocks, or whose blocks or neighbours sit at
+ *            offsets that are not multiples of 16 bytes, is not advanced:
+ *            its output is left untouched and its cells are counted as
+ *            non-physical.
  *   flags    TVD_KERNEL_AUTO or TVD_STREAM_WHOLE_B.
  *   d_smax, d_sums  as for tvd_patch_advance, over the chains' blocks; they
  *            use n_blocks * (1 or 4) workspace entries (tvd_reserve; else

@@ -476,6 +476,8 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
     return fail(ctx, TVD_ERR_INVALID_ARG, "NULL chain table or neighbour table");
   if (!d_u_in || !d_u_out) return fail(ctx, TVD_ERR_INVALID_ARG, "state pointer is NULL");
   if (d_u_in == d_u_out) return fail(ctx, TVD_ERR_ALIAS, "d_u_in == d_u_out");
+  if ((reinterpret_cast<uintptr_t>(d_u_in) | reinterpret_cast<uintptr_t>(d_u_out)) & 15)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "the state pointers must be 16-byte aligned");
   const int quads = batch->edge == 32 ? 4 : 1;
   if (!batch->d_in_off && !batch->d_out_off) {
     const size_t n = batch->edge;

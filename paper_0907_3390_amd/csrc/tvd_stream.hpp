@@ -86,8 +86,28 @@ template <typename T, int E, int SA, int D>
 struct StreamPencilA {
   const T* p[3];
   int a0;
+  // Along x (forward step, SA = 1) the tile's 16 interior cells of a row are
+  // read four at a time with 16-byte loads (FP32), which cuts the first
+  // sweep's load instructions and L1 requests; the ghost cells, 12-byte
+  // pieces of the neighbours' rows, stay single loads.
+  static constexpr bool kVec = SA == 1 && sizeof(T) == 4;
+  mutable float4 buf[kNV];
   __device__ inline void load(int j, T u[kNV]) const {
     constexpr int E3 = E * E * E;
+    if constexpr (kVec) {
+      if (j >= kG && j < kG + kTile) {
+        const int q = (j - kG) & 3;
+        if (q == 0) {
+          const float4* c = reinterpret_cast<const float4*>(p[1] + a0 + (j - kG));
+#pragma unroll
+          for (int k = 0; k < kNV; ++k) buf[k] = c[gcomp<D>(k) * (E3 / 4)];
+        }
+#pragma unroll
+        for (int k = 0; k < kNV; ++k)
+          u[k] = q == 0 ? buf[k].x : (q == 1 ? buf[k].y : (q == 2 ? buf[k].z : buf[k].w));
+        return;
+      }
+    }
     const int a = a0 - kG + j;
     const T* c;
     if (E == kTile) {
@@ -396,7 +416,7 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
   const int chain = item / sp.quads, quad = item % sp.quads;
   const int c0 = sp.start[chain];
   const int C = sp.start[chain + 1] - c0;
-  constexpr int RUN = StreamChain<T, E, ORDER, P, SPLITB>::RUN;
+  constexpr int kAlign = 16 / (int)sizeof(T);  // elements in 16 bytes
   // Validate the chain before touching anything: at most kStreamMaxChain
   // blocks of edge E, each the S+ neighbour of the one before, every
   // neighbour of every block present with edge E, one dt and dh.  A chain
@@ -413,7 +433,8 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
       bool ok = head_ok && b >= 0 && b < kp.nblocks && block_edge(kp, b) == E;
       if (ok) {
         sm.chain_off[i] = kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * E * E * E;
-        ok = sm.chain_off[i] % RUN == 0;  // 16-byte output runs stay aligned
+        // 16-byte loads of rows and 16-byte output runs stay aligned
+        ok = sm.chain_off[i] % kAlign == 0;
         if (i + 1 < C) ok = kp.nbr[27 * (int64_t)b + AX::region(0, 0, 1)] == sp.blocks[c0 + i + 1];
         if (kp.d_dt) ok = ok && kp.d_dt[b] == kp.d_dt[head];
         if (kp.d_dh) ok = ok && kp.d_dh[b] == kp.d_dh[head];
@@ -424,7 +445,9 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
       const int b = sp.blocks[c0 + w / 27];
       if (b < 0 || b >= kp.nblocks) continue;  // counted above
       const int nb = kp.nbr[27 * (int64_t)b + w % 27];
-      if (!(nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == E)) atomicAdd(&sm.nbad, 1);
+      if (!(nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == E &&
+            (kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * E * E * E) % kAlign == 0))
+        atomicAdd(&sm.nbad, 1);
     }
   }
   __syncthreads();

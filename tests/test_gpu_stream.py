@@ -182,7 +182,7 @@ def test_bad_chains_are_flagged_not_advanced(ctx):
 
 def test_stream_argument_errors(ctx):
     """Host-side checks: edges other than 16/32, mixed edges, bad flags,
-    aliasing, a too-small workspace."""
+    aliasing, misaligned state pointers, a too-small workspace."""
     note("stream argument errors")
     bs = layout.periodic_grid_blockset(32, 16)
     dev = DeviceBlocks(ctx, bs, dtype=torch.float32, stream=True)
@@ -198,6 +198,12 @@ def test_stream_argument_errors(ctx):
     with pytest.raises(tvd.TvdError) as e:
         ctx.tvd_patch_advance_stream(dev.batch, dev.nbr, ch, u, u, 0, GAMMA)
     assert e.value.status == tvd.TVD_ERR_ALIAS
+    # rows are read and written 16 bytes at a time: a state pointer off by one
+    # element is refused before any launch
+    shifted = torch.zeros(bs.out_total + 4, dtype=torch.float32, device="cuda")[1:1 + bs.out_total]
+    with pytest.raises(tvd.TvdError) as e:
+        ctx.tvd_patch_advance_stream(dev.batch, dev.nbr, ch, shifted, o, 0, GAMMA)
+    assert e.value.status == tvd.TVD_ERR_INVALID_ARG and "aligned" in str(e.value)
     big = layout.periodic_grid_blockset(256, 16)   # 4096 blocks, more than reserved so far
     c2 = tvd.Context(0)
     try:
