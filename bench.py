@@ -104,12 +104,12 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(variant):
-    """HBM bytes per launch of the advance from the committed rocprofv3 counter
-    summary, only if it was taken on the current kernel sources and on a
-    launch variant with the same HBM access pattern: the block edge, the
-    workgroup size and whether the third sweep runs in half pencils (split
-    bit 1) fix which addresses are read and written; the LDS padding and the
-    second sweep's split only move work inside the workgroup."""
+    """HBM bytes per launch of the headline kernel (mean over the forward and
+    backward launches) from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources and on the launch variant the
+    run uses: the summary holds one `traffic[chain length,second sweep]`
+    entry per variant profiled (the chain length and the second sweep's
+    split change which addresses are read and written)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary"
     kv = {}
@@ -119,12 +119,13 @@ def measured_traffic(variant):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
-    if variant is not None:
-        want = f"{variant['chain_len']},{variant['second_sweep']}"
-        if kv.get("variant") != want:
-            return None, f"counters were taken on variant {kv.get('variant')}, not {want}"
-    return float(kv["hbm_bytes_per_launch_mean"]), ("rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
-                                                    + os.path.relpath(TRAFFIC_FILE, ROOT))
+    if variant is None:
+        return None, "no launch variant recorded"
+    key = f"traffic[{variant['chain_len']},{variant['second_sweep']}]"
+    if key not in kv:
+        return None, f"no counters for variant {key[8:-1]} in the summary"
+    return float(kv[key]), ("rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, "
+                            + os.path.relpath(TRAFFIC_FILE, ROOT))
 
 
 def make_ic(N=N_GRID):
@@ -1008,6 +1009,8 @@ def main():
                     help="with --no-tune: chain length of the streamed headline run")
     ap.add_argument("--whole-b", action="store_true",
                     help="with --no-tune: second sweep in whole pencils in the headline run")
+    ap.add_argument("--per-block", action="store_true",
+                    help="with --headline-only: also time the per-block advance (profiling)")
     ap.add_argument("--extras", action="store_true",
                     help="also run the ghost fill, multi-level, closing, nested, Poisson, "
                          "gravity and uneven-batch measurements")
@@ -1095,13 +1098,14 @@ def main():
     del dev5
     torch.cuda.empty_cache()
     # the per-block gathering advance on the same state and step, for comparison
-    if not args.headline_only:
+    if not args.headline_only or args.per_block:
         log("bench: 512^3 blast FP32, per-block gathering advance for comparison")
         dpb, rpb = run_gpu(ctx, grid5, n, torch.float32, tvd.TVD_KERNEL_AUTO, steps, warmup,
                            gather=True, tune=not args.no_tune, p_floor=P_FLOOR_BLAST, sums=True)
         pb = headline_record(rpb, cells5, steps, n, "512^3 blast FP32 per-block", wl5)
-        same = np.array_equal(download_grid(dpb, grid5.shape), g32)
-        pb["bitwise_equal_to_streamed"] = bool(same)
+        if g32 is not None:
+            same = np.array_equal(download_grid(dpb, grid5.shape), g32)
+            pb["bitwise_equal_to_streamed"] = bool(same)
         out["per_block_gather"] = pb
         out["speedup_streamed_vs_per_block"] = value / pb["value"]
         del dpb
