@@ -485,11 +485,12 @@ def run_closing(ctx, ml, reps=10):
     return res
 
 
-def run_nested(ctx, ml, reps=4):
+def run_nested(ctx, ml, reps=4, n=8):
     """The multi-level hierarchy advanced with every level sub-cycled (FP32,
-    8^3 patches): one root step is one step of level 0, two of level 1, four
-    of level 2 and eight of level 3, each level closed with the next finer
-    one after each of its steps (amr.NestedDevice).  Timed with HIP events
+    as 8^3 patches or, n = 16, as 2^3 patch groups): one root step is one
+    step of level 0, two of level 1, four of level 2 and eight of level 3,
+    each level closed with the next finer one after each of its steps
+    (amr.NestedDevice).  Timed with HIP events
     over `reps` root steps run eagerly, and as replays of a HIP graph of two
     root steps (xyz, zyx).  Also reports the drift of the leaf totals over
     the timed steps (host sums of the downloaded state)."""
@@ -497,25 +498,24 @@ def run_nested(ctx, ml, reps=4):
     from paper_0907_3390_amd import amr, layout, tvd
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
     top = len(refined)
-    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32)
+    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
-    per = [np.zeros((n, 5, 8, 8, 8), dtype=np.float32) for n in dev.nb]
+    per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
+    # per-cell leaf mask: a patch's cells are leaves unless it is refined
+    leaf = [np.ones((k, 1, n, n, n), dtype=bool) for k in dev.nb]
     for i, (l, px, py, pz) in enumerate(ml.patches):
-        per[l][L.locate(l, px, py, pz)[0]] = interior[i]
+        b, (ox, oy, oz) = L.locate(l, px, py, pz)
+        per[l][b, :, oz:oz + 8, oy:oy + 8, ox:ox + 8] = interior[i]
+        if l < top and refined[l][pz, py, px]:
+            leaf[l][b, :, oz:oz + 8, oy:oy + 8, ox:ox + 8] = False
     dev.upload(per)
-    leaf = [np.ones(n, dtype=bool) for n in dev.nb]
-    for l in range(top):
-        for (lev, px, py, pz) in L.patches:
-            if lev == l and refined[l][pz, py, px]:
-                leaf[l][L.locate(l, px, py, pz)[0]] = False
 
-    def leaf_sums(blocks):
-        return sum(blocks[l][leaf[l]].astype(np.float64).sum(axis=(0, 2, 3, 4)) * 8.0 ** -l
+    def leaf_sums(blocks, f=lambda a: a):
+        return sum((f(blocks[l].astype(np.float64)) * leaf[l]).sum(axis=(0, 2, 3, 4)) * 8.0 ** -l
                    for l in range(len(blocks)))
     before = leaf_sums(per)
-    scale = sum(np.abs(per[l][leaf[l]]).astype(np.float64).sum(axis=(0, 2, 3, 4)) * 8.0 ** -l
-                for l in range(len(per)))
+    scale = leaf_sums(per, np.abs)
     sm = torch.zeros(1, dtype=torch.float64, device="cuda")
     u_in = torch.from_numpy(np.ascontiguousarray(ml.ghosted)).float().cuda().reshape(-1)
     d_dh = torch.from_numpy(np.ascontiguousarray(ml.dh)).cuda()
@@ -555,18 +555,19 @@ def run_nested(ctx, ml, reps=4):
         g.close()
     after = leaf_sums(dev.download())
     steps = 2 + reps + 2 + 2 * (reps // 2)
-    updates = sum((1 << l) * n * 512 for l, n in enumerate(dev.nb))
+    updates = sum((1 << l) * k * n ** 3 for l, k in enumerate(dev.nb))
     # the gas starts at rest: momentum is measured against mass times the
     # largest signal speed
     scale[1:4] = scale[0] * float(sm.item())
     drift = float(np.max(np.abs(after - before) / scale))
-    res = {"workload": "multi-level hierarchy (128^3 base, levels 1-3, 18 152 patches of 8^3), "
+    held = "18 152 patches of 8^3" if n == 8 else "2269 patch groups of 16^3"
+    res = {"workload": f"multi-level hierarchy (128^3 base, levels 1-3, {held}), "
                        "FP32, every level sub-cycled, every pair closed",
-           "patches_per_level": dev.nb, "cell_updates_per_root_step": updates,
+           "blocks_per_level": dev.nb, "block_edge": n, "cell_updates_per_root_step": updates,
            "root_step_ms_eager": ms_eager, "root_step_ms_graph": ms_graph,
            "value": updates / (ms_graph * 1e-3), "unit": "cell-updates/s",
            "root_steps_run": steps, "leaf_total_drift": drift}
-    log(f"bench: nested sub-cycled step: {ms_eager:.3f} ms eager, {ms_graph:.3f} ms as graph replay "
+    log(f"bench: nested sub-cycled step ({n}^3 blocks): {ms_eager:.3f} ms eager, {ms_graph:.3f} ms as graph replay "
         f"per root step ({updates / 1e6:.1f} M cell-updates), {res['value'] / 1e9:.2f} G "
         f"cell-updates/s; leaf totals drift {drift:.1e} over {steps} root steps")
     return res
@@ -1195,7 +1196,8 @@ def main():
         out["closing_step"] = run_closing(ctx, ml)
         log("bench: nested sub-cycled step on the multi-level hierarchy")
         torch.cuda.empty_cache()
-        out["nested_subcycled_step"] = run_nested(ctx, ml)
+        out["nested_subcycled_step"] = run_nested(ctx, ml, n=16)
+        out["nested_subcycled_step"]["patches_8cube"] = run_nested(ctx, ml, n=8)
         log("bench: Poisson SOR on patch groups")
         torch.cuda.empty_cache()
         out["poisson_sor"] = run_poisson(ctx)

@@ -425,21 +425,25 @@ int tvd_fill_ghosts(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
  *     tvd_fill_ghosts, r = 13 being b itself), the cell is copied from that
  *     block's interior in d_fine_interior (the fine batch's out offsets);
  *   - otherwise, per variable, with f the cell's fine index relative to the
- *     corner of b's parent (f = 2 * d_corigin[3*b + axis] + cell - 3 along
- *     each axis), c = floor(f / 2) the coarse cell and d = -1/4 (f even) or
+ *     corner of the central coarse block (f = 2 * d_corigin[3*b + axis] +
+ *     cell - 3 along each axis), c = floor(f / 2) the coarse cell and
+ *     d = -1/4 (f even) or
  *     +1/4 (f odd): u_c + dx s_x + dy s_y + dz s_z, summed in that order,
  *     s_axis = minmod(u_{c+1} - u_c, u_c - u_{c-1}) along the axis, minmod
  *     being 0 unless both differences are positive or both negative, else
  *     the one of smaller magnitude (the second on a tie).
- * The coarse level is a batch of 8^3 patches (uniform edge 8, interiors in
- * d_coarse_interior at its out offsets, same dtype).  d_cnbr[27*b + r] names
- * the coarse patch at offset r around b's parent (r = 13: the parent), and
+ * The coarse level is a batch of blocks of uniform edge 8 (patches) or 16
+ * (2^3 patch groups), interiors in d_coarse_interior at its out offsets,
+ * same dtype.  d_cnbr[27*b + r] names the coarse block at offset r around
+ * the central coarse block, the one holding b's parent patch (r = 13), and
  * d_corigin[3*b + 0..2] (x, y, z) is b's lower corner, in coarse cells,
- * relative to the parent's: 0 or 4 for 8^3 fine patches, 0 for 16^3 groups.
- * A cell whose coarse stencil leaves those 27 patches, or names a coarse
- * index outside [0, coarse n_blocks), is left untouched and counted as
- * non-physical.  Proper nesting (every parent has its 26 neighbours) makes
- * every entry valid.  Asynchronous on stream.
+ * relative to the central block's: 0 or 4 for 8^3 fine patches under 8^3
+ * coarse patches, 0 for 16^3 fine groups under 8^3 patches, 0 or 8 for
+ * 16^3 fine groups under 16^3 groups.  A cell whose coarse stencil leaves
+ * those 27 blocks, or names a coarse index outside [0, coarse n_blocks), is
+ * left untouched and counted as non-physical.  Proper nesting (every
+ * refined patch has its 26 neighbours) makes every needed entry valid.
+ * Asynchronous on stream.
  */
 int tvd_fill_ghosts_amr(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nbr,
                         const void *d_fine_interior, void *d_fine_ghosted,

@@ -103,8 +103,9 @@ class TwoLevelDevice:
 
 
 class NestedDevice:
-    """A periodic hierarchy of 8^3 patches on any number of levels
-    (layout.NestedLevels) advanced on the device, every level sub-cycled.
+    """A periodic hierarchy on any number of levels (layout.NestedLevels),
+    held as 8^3 patches or as 2^3 patch groups of 16^3 (n = 16; Sec. 3.1),
+    advanced on the device, every level sub-cycled.
 
     One root step of dt (Sec. 2.1, a level's update: advance, let the finer
     level catch up, correct with it):
@@ -125,19 +126,24 @@ class NestedDevice:
     a time-interpolated state."""
 
     def __init__(self, ctx: tvd.Context, Nc: int, refined, dtype=torch.float64,
-                 gamma: float = GAMMA):
+                 gamma: float = GAMMA, n: int = 8):
+        if n == 16 and dtype != torch.float32:
+            raise ValueError("patch groups (n = 16) advance in FP32: the flux-recording FP64 "
+                             "advance holds blocks of edge 8 only")
         self.ctx, self.dtype, self.gamma = ctx, dtype, gamma
-        self.L = L = layout.NestedLevels(Nc, refined)
+        self.L = L = layout.NestedLevels(Nc, refined, n)
+        self.n = n
         self.code = tvd.dtype_code(dtype)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
         self.nb = [b.n_blocks for b in L.blocks]
         ctx.tvd_reserve(max(self.nb))
-        rs = layout.flux_record_size(8)
-        self.u = [z(n * 5 * 512) for n in self.nb]
-        self.u_new = [z(n * 5 * 512) for n in self.nb]
-        self.u_gh = [z(n * 5 * 14 ** 3) for n in self.nb]
-        self.u_half = [z(n * 5 * 512) for n in self.nb[:-1]]
+        rs = layout.flux_record_size(n)
+        self.cells = n ** 3
+        self.u = [z(k * 5 * n ** 3) for k in self.nb]
+        self.u_new = [z(k * 5 * n ** 3) for k in self.nb]
+        self.u_gh = [z(k * 5 * (n + 6) ** 3) for k in self.nb]
+        self.u_half = [z(k * 5 * n ** 3) for k in self.nb[:-1]]
         # level 0 takes one step per root step, the others two
         self.rec = [[z(n * rs)] if lev == 0 else [z(n * rs), z(n * rs)]
                     for lev, n in enumerate(self.nb)]
@@ -151,17 +157,18 @@ class NestedDevice:
             self.rows[lev] = (dev(rr), dev(gr), dev(gs))
 
     def upload(self, states):
-        """Per level the patch interiors (B_l, 5, 8, 8, 8) in NestedLevels
+        """Per level the block interiors (B_l, 5, n, n, n) in NestedLevels
         order."""
         for buf, s in zip(self.u, states):
             buf.copy_(torch.from_numpy(np.ascontiguousarray(s)).reshape(-1))
 
     def download(self):
-        """Per level the patch interiors (B_l, 5, 8, 8, 8), FP64 numpy."""
-        return [b.double().cpu().numpy().reshape(n, 5, 8, 8, 8) for b, n in zip(self.u, self.nb)]
+        """Per level the block interiors (B_l, 5, n, n, n), FP64 numpy."""
+        n = self.n
+        return [b.double().cpu().numpy().reshape(k, 5, n, n, n) for b, k in zip(self.u, self.nb)]
 
     def _batch(self, lev, dt):
-        return tvd.Batch(self.code, self.nb[lev], 8, dt=dt, dh=1.0 / (self.L.Nc << lev))
+        return tvd.Batch(self.code, self.nb[lev], self.n, dt=dt, dh=1.0 / (self.L.Nc << lev))
 
     def _close(self, lev, dt):
         rr, gr, gs = self.rows[lev]
@@ -173,8 +180,8 @@ class NestedDevice:
         """Level lev takes two steps of dt/2 inside level lev-1's step of dt,
         whose old state is u[lev-1] and whose advanced one u_new[lev-1]."""
         ctx, h = self.ctx, 0.5 * dt
-        ctx.tvd_lerp(self.code, self.nb[lev - 1] * 5 * 512, self.u[lev - 1], self.u_new[lev - 1],
-                     self.u_half[lev - 1], 0.5)
+        ctx.tvd_lerp(self.code, self.nb[lev - 1] * 5 * self.cells, self.u[lev - 1],
+                     self.u_new[lev - 1], self.u_half[lev - 1], 0.5)
         fb, cb = self._batch(lev, h), self._batch(lev - 1, h)
         for k in (0, 1):
             o = order if k == 0 else 1 - order
@@ -188,7 +195,7 @@ class NestedDevice:
                 self._subcycle(lev + 1, h, o)
                 self._close(lev, h)
             self.u[lev], self.u_new[lev] = self.u_new[lev], self.u[lev]
-        ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(8), self.rec[lev][0],
+        ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(self.n), self.rec[lev][0],
                      self.rec[lev][1], self.rec_mean[lev], 0.5)
 
     def step(self, dt: float, order: int):

@@ -1065,8 +1065,9 @@ int tvd_fill_ghosts_amr(tvd_ctx* ctx, const tvd_batch* fine, const int32_t* d_nb
   if ((st = check_batch(ctx, coarse))) return st;
   if (coarse->dtype != fine->dtype)
     return fail(ctx, TVD_ERR_INVALID_ARG, "coarse and fine batches differ in dtype");
-  if (coarse->d_edge || coarse->edge != 8)
-    return fail(ctx, TVD_ERR_UNSUPPORTED, "coarse blocks must be 8^3 patches (uniform edge 8)");
+  if (coarse->d_edge || (coarse->edge != 8 && coarse->edge != 16))
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "coarse blocks must have a uniform edge of 8 (patches) or 16 (patch groups)");
   if (fine->n_blocks == 0) return TVD_OK;
   if (!d_nbr || !d_fine_interior || !d_fine_ghosted || !d_coarse_interior || !d_cnbr ||
       !d_corigin)
@@ -1078,8 +1079,8 @@ int tvd_fill_ghosts_amr(tvd_ctx* ctx, const tvd_batch* fine, const int32_t* d_nb
                                       const_cast<void*>(d_fine_interior), 1.0, 0.0);
   const int max_edge = fine->d_edge ? 16 : fine->edge;
   hipError_t e = tvd::launch_fill_ghosts_amr(fine->dtype, kp, d_nbr, max_edge, d_coarse_interior,
-                                             coarse->d_out_off, coarse->n_blocks, d_cnbr,
-                                             d_corigin, (hipStream_t)stream);
+                                             coarse->d_out_off, coarse->n_blocks, coarse->edge,
+                                             d_cnbr, d_corigin, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "coarse-fine ghost fill launch");
   return TVD_OK;
 }

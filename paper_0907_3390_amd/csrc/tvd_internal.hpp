@@ -76,11 +76,11 @@ hipError_t launch_dt_from_speed(const KParams& kp, const double* smax, double cf
                                 double* dt_out, hipStream_t s);
 hipError_t launch_fill_ghosts(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
                               hipStream_t s);
-// Sibling copy, else Min-Mod limited interpolation from coarse 8^3 patches
-// (cin at coarse offsets coff, or dense); cnbr [27 per fine block], corigin
-// [3 per fine block].
+// Sibling copy, else Min-Mod limited interpolation from the coarse level's
+// blocks of edge cedge (8 or 16; cin at coarse offsets coff, or dense); cnbr
+// [27 per fine block], corigin [3 per fine block].
 hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
-                                  const void* cin, const int64_t* coff, int ncoarse,
+                                  const void* cin, const int64_t* coff, int ncoarse, int cedge,
                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 // Closing step of a level pair: ck is the coarse level (interior blocks read

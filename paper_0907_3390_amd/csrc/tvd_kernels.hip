@@ -256,19 +256,23 @@ struct CoarseNbhd {
   const int64_t* coff;  // coarse out offsets (or null: dense)
   const int32_t* cnbr;  // 27 entries of this fine block
   int ncoarse;
+  int cs;               // log2 of the coarse block edge: 3 (8^3 patches) or 4 (16^3 groups)
   // Branch-free, so that the seven reads of a cell's stencil issue together:
-  // a cell outside the 27 patches or a missing patch reads block 0 instead
-  // (ncoarse >= 1 is checked by the caller) and reports false.
+  // a cell outside the 27 coarse blocks or a missing block reads block 0
+  // instead (ncoarse >= 1 is checked by the caller) and reports false.
+  // (ix, iy, iz): coarse cell relative to the corner of the central block.
   __device__ inline bool get(int ix, int iy, int iz, T u[kNV]) const {
-    const int qx = ix >> 3, qy = iy >> 3, qz = iz >> 3;
+    const int qx = ix >> cs, qy = iy >> cs, qz = iz >> cs;
     const bool in = qx >= -1 && qx <= 1 && qy >= -1 && qy <= 1 && qz >= -1 && qz <= 1;
     const int cb = cnbr[in ? (qx + 1) + 3 * (qy + 1) + 9 * (qz + 1) : 13];
     const bool ok = in && cb >= 0 && cb < ncoarse;
-    const int cs = ok ? cb : 0;
-    const T* c = cin + (coff ? coff[cs] : (int64_t)cs * kNV * 512) + (ix & 7) + 8 * (iy & 7) +
-                 64 * (iz & 7);
+    const int cs_b = ok ? cb : 0;
+    const int ce = 1 << cs, cm = ce - 1;
+    const int64_t c3 = (int64_t)ce * ce * ce;
+    const T* c = cin + (coff ? coff[cs_b] : (int64_t)cs_b * kNV * c3) + (ix & cm) +
+                 ce * (iy & cm) + ce * ce * (iz & cm);
 #pragma unroll
-    for (int k = 0; k < kNV; ++k) u[k] = c[k * 512];
+    for (int k = 0; k < kNV; ++k) u[k] = c[k * c3];
     return ok;
   }
 };
@@ -284,20 +288,20 @@ constexpr int kFillCPT = 4;
 template <typename T>
 __device__ __forceinline__ void fill_interp(const KParams& kp, int b, int x, int y, int z,
                                             T* d, int64_t m3, int cell, const T* cin,
-                                            const int64_t* coff, int ncoarse,
+                                            const int64_t* coff, int ncoarse, int cshift,
                                             const int32_t* cnbr, const int32_t* corigin) {
   if (ncoarse <= 0) {
     atomicAdd(&kp.counters[1], 1ull);
     return;
   }
-  // fine index relative to the parent's corner, in fine cells
+  // fine index relative to the central coarse block's corner, in fine cells
   const int fx = 2 * corigin[3 * b + 0] + x - kG;
   const int fy = 2 * corigin[3 * b + 1] + y - kG;
   const int fz = 2 * corigin[3 * b + 2] + z - kG;
   const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;  // floor
   const T q = T(0.25);
   const T dx = (fx & 1) ? q : -q, dy = (fy & 1) ? q : -q, dz = (fz & 1) ? q : -q;
-  const CoarseNbhd<T> cn{cin, coff, cnbr + 27 * (int64_t)b, ncoarse};
+  const CoarseNbhd<T> cn{cin, coff, cnbr + 27 * (int64_t)b, ncoarse, cshift};
   // all seven stencil reads first (no short-circuit between them)
   T u[kNV], xp[kNV], xm[kNV], yp[kNV], ym[kNV], zp[kNV], zm[kNV], out[kNV];
   bool ok = cn.get(cx, cy, cz, u);
@@ -331,7 +335,7 @@ template <typename T>
 __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const int32_t* nbr,
                                                             int chunks, const T* cin,
                                                             const int64_t* coff, int ncoarse,
-                                                            const int32_t* cnbr,
+                                                            int cshift, const int32_t* cnbr,
                                                             const int32_t* corigin) {
   const int b = blockIdx.x / chunks;
   const int chunk = blockIdx.x % chunks;
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
     if (kind[i] != 2) continue;
     const int cell = (chunk * kFillCPT + i) * kFillNT + threadIdx.x;
     const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
-    fill_interp<T>(kp, b, x, y, z, d, m3, cell, cin, coff, ncoarse, cnbr, corigin);
+    fill_interp<T>(kp, b, x, y, z, d, m3, cell, cin, coff, ncoarse, cshift, cnbr, corigin);
   }
 }
 
@@ -868,17 +872,18 @@ hipError_t launch_fill_ghosts(int dtype, const KParams& kp, const int32_t* nbr, 
 }
 
 hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
-                                  const void* cin, const int64_t* coff, int ncoarse,
+                                  const void* cin, const int64_t* coff, int ncoarse, int cedge,
                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s) {
+  const int cshift = cedge == 16 ? 4 : 3;
   const int m = max_edge + 2 * kG;
   const int chunks = (m * m * m + kFillNT * kFillCPT - 1) / (kFillNT * kFillCPT);
   const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
   if (dtype == 1)
     hipLaunchKernelGGL((k_fill_ghosts_amr<float>), grid, block, 0, s, kp, nbr, chunks,
-                       static_cast<const float*>(cin), coff, ncoarse, cnbr, corigin);
+                       static_cast<const float*>(cin), coff, ncoarse, cshift, cnbr, corigin);
   else
     hipLaunchKernelGGL((k_fill_ghosts_amr<double>), grid, block, 0, s, kp, nbr, chunks,
-                       static_cast<const double*>(cin), coff, ncoarse, cnbr, corigin);
+                       static_cast<const double*>(cin), coff, ncoarse, cshift, cnbr, corigin);
   return hipGetLastError();
 }
 

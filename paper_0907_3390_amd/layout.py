@@ -431,13 +431,24 @@ class NestedLevels:
     and corigin[l] [B, 3] for the coarse-fine ghost fill (the level-(l-1)
     patches around each patch's parent, and the patch's corner in coarse
     cells inside its parent, x first).  patches and locate describe the
-    octree for closing_tables."""
+    octree for closing_tables.
 
-    def __init__(self, Nc: int, refined):
+    With n = 16 every level is held as 2^3 patch groups of 16^3 cells
+    instead (Sec. 3.1): level 0 as the (Nc/16)^3 groups of the root grid, x
+    fastest, and level l >= 1 as one group per refined patch of level l-1
+    (its eight children), in the order of the refined patches.  blocks,
+    origins, cnbr and corigin then describe the groups: cnbr names the 27
+    level-(l-1) groups around the group holding the parent patch, corigin
+    is the group's corner in coarse cells inside that group (0 or 8), and
+    locate returns a patch's group and its cell offset in it."""
+
+    def __init__(self, Nc: int, refined, n: int = PATCH):
         npc = Nc // PATCH
         if Nc % PATCH:
             raise ValueError("Nc must be a multiple of 8")
-        self.Nc = Nc
+        if n not in (PATCH, 2 * PATCH) or (n == 2 * PATCH and Nc % n):
+            raise ValueError("blocks are 8^3 patches or 16^3 patch groups (then Nc % 16 == 0)")
+        self.Nc, self.n = Nc, n
         self.refined = [np.asarray(r, dtype=bool) for r in refined]
         self.n_levels = len(self.refined) + 1
         index = {(px, py, pz): px + npc * (py + npc * pz)
@@ -499,9 +510,58 @@ class NestedLevels:
             self.cnbr.append(cnbr)
             self.corigin.append(corigin)
         self.patches = [(lev, px, py, pz) for lev, cl in enumerate(coords) for px, py, pz in cl]
+        if n == 2 * PATCH:
+            self._groups(coords)
+
+    def _groups(self, coords):
+        """Replace the per-patch tables by those of 2^3 patch groups."""
+        Nc, n = self.Nc, self.n
+        self._gindex, gcoords = [], []
+        for lev, cl in enumerate(coords):
+            # a group at position G holds the patches 2G + (0|1) of the level
+            gl = sorted({(px // 2, py // 2, pz // 2) for px, py, pz in cl},
+                        key=lambda g: (g[2], g[1], g[0]))
+            self._gindex.append({g: i for i, g in enumerate(gl)})
+            gcoords.append(gl)
+        self.blocks, self.origins, self.cnbr, self.corigin = [], [], [None], [None]
+        for lev, gl in enumerate(gcoords):
+            ng = (Nc << lev) // n
+            idx = self._gindex[lev]
+            nbr = np.full((len(gl), 27), -1, dtype=np.int32)
+            for b, (gx, gy, gz) in enumerate(gl):
+                for rz in (-1, 0, 1):
+                    for ry in (-1, 0, 1):
+                        for rx in (-1, 0, 1):
+                            q = ((gx + rx) % ng, (gy + ry) % ng, (gz + rz) % ng)
+                            nbr[b, (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)] = idx.get(q, -1)
+            self.blocks.append(BlockSet(np.full(len(gl), n), np.full(len(gl), 1.0 / (Nc << lev)),
+                                        nbr))
+            self.origins.append(np.array([(n * gz, n * gy, n * gx) for gx, gy, gz in gl],
+                                         dtype=np.int64).reshape(-1, 3))
+            if lev == 0:
+                continue
+            # group G of level lev holds the children of patch G of level lev-1,
+            # which sits in group G // 2 of that level at octant G % 2
+            ngp = (Nc << (lev - 1)) // n
+            prev = self._gindex[lev - 1]
+            cnbr = np.empty((len(gl), 27), dtype=np.int32)
+            corigin = np.empty((len(gl), 3), dtype=np.int32)
+            for b, (gx, gy, gz) in enumerate(gl):
+                par = (gx // 2, gy // 2, gz // 2)
+                corigin[b] = [PATCH * (gx % 2), PATCH * (gy % 2), PATCH * (gz % 2)]
+                for rz in (-1, 0, 1):
+                    for ry in (-1, 0, 1):
+                        for rx in (-1, 0, 1):
+                            q = ((par[0] + rx) % ngp, (par[1] + ry) % ngp, (par[2] + rz) % ngp)
+                            cnbr[b, (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)] = prev.get(q, -1)
+            self.cnbr.append(cnbr)
+            self.corigin.append(corigin)
 
     def locate(self, level, px, py, pz):
-        return self._index[level][(px, py, pz)], (0, 0, 0)
+        if self.n == PATCH:
+            return self._index[level][(px, py, pz)], (0, 0, 0)
+        return (self._gindex[level][(px // 2, py // 2, pz // 2)],
+                (PATCH * (px % 2), PATCH * (py % 2), PATCH * (pz % 2)))
 
     @staticmethod
     def refined_from_patches(Nc: int, patches):

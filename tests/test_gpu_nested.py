@@ -1,10 +1,12 @@
 """The nested-level driver on the device (paper_0907_3390_amd.amr.NestedDevice):
-three levels of 8^3 patches, every level sub-cycled in its parent's step
-(Sec. 2.1), each pair closed finest first, against the oracle's recursive
-step: FP64 within 1e-12 and FP32 within 1e-5 (relative L1 per level and
-variable, the oracle run on the FP32-rounded start); the leaf totals are
-conserved over several root steps; a captured HIP graph of two root steps
-replays to the eager steps' bits."""
+three levels held as 8^3 patches or as 2^3 patch groups of 16^3 (Sec. 3.1),
+every level sub-cycled in its parent's step (Sec. 2.1), each pair closed
+finest first, against the oracle's recursive step: FP64 within 1e-12 and
+FP32 within 1e-5 (relative L1 per level and variable, the oracle run on the
+FP32-rounded start); the leaf totals are conserved over several root steps;
+a captured HIP graph of two root steps replays to the eager steps' bits.
+Patch groups advance in FP32 only (the flux-recording FP64 advance holds
+blocks of edge 8); their conservation is checked on the full hierarchy."""
 import numpy as np
 import pytest
 import torch
@@ -47,26 +49,28 @@ def _states(seed, f32):
 
 
 def _blocks(L, states):
-    return [np.stack([st[:, z:z + 8, y:y + 8, x:x + 8] for z, y, x in L.origins[lev]])
+    e = L.n
+    return [np.stack([st[:, z:z + e, y:y + e, x:x + e] for z, y, x in L.origins[lev]])
             for lev, st in enumerate(states)]
 
 
 def _dense(L, blocks):
-    out = []
+    out, e = [], L.n
     for lev, bl in enumerate(blocks):
         M = NC << lev
         g = np.zeros((5, M, M, M))
         for b, (z, y, x) in zip(bl, L.origins[lev]):
-            g[:, z:z + 8, y:y + 8, x:x + 8] = b
+            g[:, z:z + e, y:y + e, x:x + e] = b
         out.append(g)
     return out
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_nested_driver_matches_oracle(ctx, dtype):
-    note(f"nested driver, three levels, dtype={dtype}")
+@pytest.mark.parametrize("dtype,n", [(torch.float64, 8), (torch.float32, 8),
+                                     (torch.float32, 16)])
+def test_nested_driver_matches_oracle(ctx, dtype, n):
+    note(f"nested driver, three levels, dtype={dtype}, blocks of {n}^3")
     states = _states(500, dtype == torch.float32)
-    dev = amr.NestedDevice(ctx, NC, _refined(), dtype=dtype)
+    dev = amr.NestedDevice(ctx, NC, _refined(), dtype=dtype, n=n)
     L = dev.L
     dev.upload([b.astype(np.float32) if dtype == torch.float32 else b for b in _blocks(L, states)])
     dt = 0.1 / NC
@@ -136,33 +140,37 @@ def test_nested_step_graph_replay(ctx):
         g.close()
 
 
-def test_nested_full_size_conserves_fp32(ctx):
+@pytest.mark.parametrize("n", [8, 16])
+def test_nested_full_size_conserves_fp32(ctx, n):
     """The full multi-level hierarchy (128^3 base, levels 1-3, 18 152 patches,
-    the bench's configuration), FP32, every level sub-cycled: over four root
-    steps (32 level-3 steps) the leaf totals drift by no more than the FP32
-    rounding of the stored state (1e-6 of each variable's scale; momentum
-    against mass times the signal speed, the gas starting at rest), and no
-    cell is floored or non-physical."""
+    the bench's configuration, as patches or as 2269 patch groups), FP32,
+    every level sub-cycled: over four root steps (32 level-3 steps) the leaf
+    totals drift by no more than the FP32 rounding of the stored state (1e-6
+    of each variable's scale; momentum against mass times the signal speed,
+    the gas starting at rest), and no cell is floored or non-physical."""
     from paper_0907_3390_amd import layout
-    note("nested driver, full multi-level hierarchy, fp32")
+    note(f"nested driver, full multi-level hierarchy, fp32, blocks of {n}^3")
     ml = wl.multilevel()
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
-    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32)
+    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
-    per = [np.zeros((n, 5, 8, 8, 8), dtype=np.float32) for n in dev.nb]
+    per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
+    # leaf mask per cell: a patch's cells are leaves unless the patch is refined
+    leaf = [np.ones((k, 1, n, n, n), dtype=bool) for k in dev.nb]
     for i, (l, px, py, pz) in enumerate(ml.patches):
-        per[l][L.locate(l, px, py, pz)[0]] = interior[i]
-    dev.upload(per)
-    leaf = [np.ones(n, dtype=bool) for n in dev.nb]
-    for (l, px, py, pz) in L.patches:
+        b, (ox, oy, oz) = L.locate(l, px, py, pz)
+        per[l][b, :, oz:oz + 8, oy:oy + 8, ox:ox + 8] = interior[i]
         if l < len(refined) and refined[l][pz, py, px]:
-            leaf[l][L.locate(l, px, py, pz)[0]] = False
+            leaf[l][b, :, oz:oz + 8, oy:oy + 8, ox:ox + 8] = False
+    dev.upload(per)
 
     def sums(blocks, f=lambda a: a):
-        return sum(f(blocks[l][leaf[l]].astype(np.float64)).sum(axis=(0, 2, 3, 4)) * 8.0 ** -l
+        return sum((f(blocks[l].astype(np.float64)) * leaf[l]).sum(axis=(0, 2, 3, 4)) * 8.0 ** -l
                    for l in range(len(blocks)))
     before, scale = sums(per), sums(per, np.abs)
+    with pytest.raises(ValueError):
+        amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float64, n=16)
     c_max = float(np.sqrt(5.0 / 3.0 * ml.P0 / min(b[:, 0].min() for b in per)))
     scale[1:4] = scale[0] * c_max
     dt = 0.5 / ml.base / c_max

@@ -233,3 +233,64 @@ def test_stream_chains_cover_and_follow_the_axis():
     assert bl.tolist() == [1, 2, 3] and st.tolist() == [0, 3]
     assert default_chain_len(32768) == 32 and default_chain_len(4096) == 4
     assert default_chain_len(10 ** 7) == 64
+
+
+def test_nested_levels_as_patch_groups():
+    """NestedLevels with n = 16: every patch of every level lies in one
+    group at its octant (the group's origin plus the offset is the patch's
+    origin in the patch view); siblings are groups at +-1; every coarse
+    group that a group's coarse-fine ghost zone or stencil can reach (the
+    level-(l-1) groups holding the parent patch's 26 neighbours) is named
+    in cnbr; the closing tables restrict each group once into the group
+    holding its parent at that patch's octant, and the face rows cover the
+    same coarse faces as the patch view (same coarse cells, 8x8 instead of
+    4x4 pieces)."""
+    r0 = np.zeros((4, 4, 4), dtype=bool)
+    r0[1:3, 1:3, 1:3] = True
+    r1 = np.zeros((8, 8, 8), dtype=bool)
+    r1[3, 3, 3] = r1[3, 3, 4] = r1[3, 4, 3] = True
+    P = layout.NestedLevels(32, [r0, r1])
+    G = layout.NestedLevels(32, [r0, r1], 16)
+    assert [b.n_blocks for b in G.blocks] == [8, 8, 3]
+    assert all(np.all(b.edges == 16) for b in G.blocks)
+    for (l, px, py, pz) in P.patches:
+        pb, _ = P.locate(l, px, py, pz)
+        gb, (ox, oy, oz) = G.locate(l, px, py, pz)
+        assert tuple(P.origins[l][pb]) == (G.origins[l][gb][0] + oz, G.origins[l][gb][1] + oy,
+                                            G.origins[l][gb][2] + ox)
+    for l in (1, 2):
+        for b in range(G.blocks[l].n_blocks):
+            gz, gy, gx = (G.origins[l][b] // 16).tolist()
+            # the parent patch (gx, gy, gz) of level l-1 and its 26 neighbours
+            # are all in groups named by cnbr, at the offsets corigin implies
+            cx, cy, cz = G.corigin[l][b]
+            assert (cx, cy, cz) == (8 * (gx % 2), 8 * (gy % 2), 8 * (gz % 2))
+            n_p = (32 << (l - 1)) // 8
+            for rz in (-1, 0, 1):
+                for ry in (-1, 0, 1):
+                    for rx in (-1, 0, 1):
+                        q = ((gx + rx) % n_p, (gy + ry) % n_p, (gz + rz) % n_p)
+                        cb, off = G.locate(l - 1, *q)
+                        # the region of that patch's group around the central group
+                        rel = [c // 2 - g // 2 for c, g in zip((gx + rx, gy + ry, gz + rz), (gx, gy, gz))]
+                        reg = (rel[0] + 1) + 3 * (rel[1] + 1) + 9 * (rel[2] + 1)
+                        assert G.cnbr[l][b][reg] == cb
+    tp, tg = P.tables(), G.tables()
+    for lev in tp:
+        rr, fr, _ = tg[lev]
+        assert len(rr) == G.blocks[lev + 1].n_blocks
+        assert len(np.unique(rr[:, 0])) == len(rr)
+        # normalise to absolute coarse face cells (axis, side, plane coordinate, two face coords)
+        def absolute(L, rows, e_f):
+            h = e_f // 2
+            res = set()
+            hi_lo = {0: (2, 1), 1: (2, 0), 2: (1, 0)}
+            for c, d, s, qc, oa, ob, f, qf in rows:
+                z, y, x = L.origins[lev][c]
+                org = {0: x, 1: y, 2: z}
+                hi, lo = hi_lo[int(d)]
+                for a in range(oa, oa + h):
+                    for b2 in range(ob, ob + h):
+                        res.add((int(d), int(s), org[int(d)] + 8 * int(qc), org[hi] + a, org[lo] + b2))
+            return res
+        assert absolute(P, tp[lev][1], 8) == absolute(G, fr, 16)
