@@ -485,7 +485,7 @@ def run_closing(ctx, ml, reps=10):
     return res
 
 
-def run_nested(ctx, ml, reps=4, n=8):
+def run_nested(ctx, ml, reps=4, n=8, gather=False):
     """The multi-level hierarchy advanced with every level sub-cycled (FP32,
     as 8^3 patches or, n = 16, as 2^3 patch groups): one root step is one
     step of level 0, two of level 1, four of level 2 and eight of level 3,
@@ -498,7 +498,7 @@ def run_nested(ctx, ml, reps=4, n=8):
     from paper_0907_3390_amd import amr, layout, tvd
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
     top = len(refined)
-    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n)
+    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
     per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
@@ -561,13 +561,16 @@ def run_nested(ctx, ml, reps=4, n=8):
     scale[1:4] = scale[0] * float(sm.item())
     drift = float(np.max(np.abs(after - before) / scale))
     held = "18 152 patches of 8^3" if n == 8 else "2269 patch groups of 16^3"
+    how = ("coarse-fine cells interpolated into stand-ins for missing siblings, ghost zones "
+           "gathered by the advance" if gather else "ghosted copies filled before every advance")
     res = {"workload": f"multi-level hierarchy (128^3 base, levels 1-3, {held}), "
-                       "FP32, every level sub-cycled, every pair closed",
+                       f"FP32, every level sub-cycled, every pair closed; {how}",
+           "ghost_zones": "gathered" if gather else "ghosted copies",
            "blocks_per_level": dev.nb, "block_edge": n, "cell_updates_per_root_step": updates,
            "root_step_ms_eager": ms_eager, "root_step_ms_graph": ms_graph,
            "value": updates / (ms_graph * 1e-3), "unit": "cell-updates/s",
            "root_steps_run": steps, "leaf_total_drift": drift}
-    log(f"bench: nested sub-cycled step ({n}^3 blocks): {ms_eager:.3f} ms eager, {ms_graph:.3f} ms as graph replay "
+    log(f"bench: nested sub-cycled step ({n}^3 blocks, gather {gather}): {ms_eager:.3f} ms eager, {ms_graph:.3f} ms as graph replay "
         f"per root step ({updates / 1e6:.1f} M cell-updates), {res['value'] / 1e9:.2f} G "
         f"cell-updates/s; leaf totals drift {drift:.1e} over {steps} root steps")
     return res
@@ -1015,7 +1018,23 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the ghost fill, multi-level, closing, nested, Poisson, "
                          "gravity and uneven-batch measurements")
+    ap.add_argument("--only", choices=["amr_fill", "nested"], default=None,
+                    help="run only this measurement and print its record (profiling)")
     args = ap.parse_args()
+    if args.only:
+        import torch
+        from paper_0907_3390_amd import tvd, workloads as wl
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        ctx = tvd.Context(0)
+        if args.only == "nested":
+            ml = wl.multilevel()
+            rec = {"nested_subcycled_step": run_nested(ctx, ml, n=16, gather=True),
+                   "ghosted_copies": run_nested(ctx, ml, n=16)}
+        else:
+            rec = {"amr_ghost_fill": run_amr_fill(ctx)}
+        ctx.close()
+        print(json.dumps(rec), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -1196,8 +1215,9 @@ def main():
         out["closing_step"] = run_closing(ctx, ml)
         log("bench: nested sub-cycled step on the multi-level hierarchy")
         torch.cuda.empty_cache()
-        out["nested_subcycled_step"] = run_nested(ctx, ml, n=16)
-        out["nested_subcycled_step"]["patches_8cube"] = run_nested(ctx, ml, n=8)
+        out["nested_subcycled_step"] = run_nested(ctx, ml, n=16, gather=True)
+        out["nested_subcycled_step"]["groups_ghosted_copies"] = run_nested(ctx, ml, n=16)
+        out["nested_subcycled_step"]["patches_8cube"] = run_nested(ctx, ml, n=8, gather=True)
         log("bench: Poisson SOR on patch groups")
         torch.cuda.empty_cache()
         out["poisson_sor"] = run_poisson(ctx)

@@ -450,6 +450,32 @@ int tvd_fill_ghosts_amr(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nb
                         const tvd_batch *coarse, const void *d_coarse_interior,
                         const int32_t *d_cnbr, const int32_t *d_corigin, void *stream);
 
+/*
+ * The coarse-fine ghost zones of a gathering advance (Sec. 2.2: a ghost cell
+ * is copied from the sibling when it exists, else interpolated from the
+ * level one coarser; here the copy is the gathering advance's own read of
+ * the sibling's interior, and only the interpolated cells are produced).
+ * The fine level's interior buffer d_fine_interior holds n_sources blocks:
+ * the fine batch's n_blocks real blocks (dense, uniform edge 8 or 16), then
+ * source-only blocks that stand in for missing siblings.  For every real
+ * block b and every ghost cell of b whose region r has d_nbr[27*b + r] =
+ * s with n_blocks <= s < n_sources, the cell is interpolated exactly as in
+ * tvd_fill_ghosts_amr (same corigin, cnbr and coarse batch conventions),
+ * from the coarse level at time fraction w, each coarse value being
+ * old + w (new - old) (w = 0: d_coarse_old alone; d_coarse_new may then be
+ * NULL), and written into block s's interior at the cell's position
+ * relative to s.  Cells with a real sibling (s < n_blocks) are left to the
+ * advance.  A cell needed by several real blocks receives the same value
+ * from each.  Then tvd_patch_advance_flux_gather with the same table and
+ * n_sources advances the real blocks.  A source index at or beyond
+ * n_sources, or a coarse stencil leaving the 27 coarse blocks, is counted
+ * as non-physical and the cell left untouched.  Asynchronous on stream.
+ */
+int tvd_fill_coarse_fine(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nbr,
+                         int32_t n_sources, void *d_fine_interior, const tvd_batch *coarse,
+                         const void *d_coarse_old, const void *d_coarse_new, double w,
+                         const int32_t *d_cnbr, const int32_t *d_corigin, void *stream);
+
 /* ---- closing step of a level pair (Sec. 2.1 step 3, Sec. 3.1) --------------- */
 
 /*
@@ -484,6 +510,22 @@ int tvd_patch_advance_flux(tvd_ctx *ctx, const tvd_batch *batch, const void *d_u
                            double flux_weight, int32_t accumulate, int32_t sweep_order,
                            double gamma, double p_floor, int32_t flags, double *d_smax,
                            double *d_sums, void *stream);
+
+/*
+ * tvd_patch_advance_flux reading its ghost zones from the neighbours'
+ * interiors (as tvd_patch_advance_gather) instead of a ghosted copy: d_u_in
+ * holds n_sources interior blocks (0: n_blocks), the batch's real blocks
+ * first, then source-only blocks that d_nbr may name as neighbours but that
+ * are not advanced (the stand-ins for missing siblings that
+ * tvd_fill_coarse_fine fills).  Uniform edge, batched kernel (flags AUTO or
+ * BATCHED); the other arguments as for tvd_patch_advance_flux.
+ */
+int tvd_patch_advance_flux_gather(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
+                                  int32_t n_sources, const void *d_u_in, void *d_u_out,
+                                  void *d_flux, const int64_t *d_flux_off, double flux_weight,
+                                  int32_t accumulate, int32_t sweep_order, double gamma,
+                                  double p_floor, int32_t flags, double *d_smax, double *d_sums,
+                                  void *stream);
 
 /*
  * d_out[i] = d_a[i] + w (d_b[i] - d_a[i]), i < n, in the dtype (w rounded

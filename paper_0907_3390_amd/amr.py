@@ -126,13 +126,14 @@ class NestedDevice:
     a time-interpolated state."""
 
     def __init__(self, ctx: tvd.Context, Nc: int, refined, dtype=torch.float64,
-                 gamma: float = GAMMA, n: int = 8):
+                 gamma: float = GAMMA, n: int = 8, gather: bool = False):
         if n == 16 and dtype != torch.float32:
             raise ValueError("patch groups (n = 16) advance in FP32: the flux-recording FP64 "
                              "advance holds blocks of edge 8 only")
         self.ctx, self.dtype, self.gamma = ctx, dtype, gamma
         self.L = L = layout.NestedLevels(Nc, refined, n)
         self.n = n
+        self.gather = gather
         self.code = tvd.dtype_code(dtype)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         z = lambda k: torch.zeros(k, dtype=dtype, device="cuda")
@@ -140,10 +141,19 @@ class NestedDevice:
         ctx.tvd_reserve(max(self.nb))
         rs = layout.flux_record_size(n)
         self.cells = n ** 3
-        self.u = [z(k * 5 * n ** 3) for k in self.nb]
-        self.u_new = [z(k * 5 * n ** 3) for k in self.nb]
-        self.u_gh = [z(k * 5 * (n + 6) ** 3) for k in self.nb]
-        self.u_half = [z(k * 5 * n ** 3) for k in self.nb[:-1]]
+        if gather:
+            # interiors followed by the stand-ins for missing siblings, which
+            # the coarse-fine fill writes and the gathering advance reads
+            st = [L.stand_ins(lev) for lev in range(L.n_levels)]
+            self.vnbr = [dev(t) for t, _ in st]
+            self.nsrc = [k for _, k in st]
+        else:
+            self.nsrc = list(self.nb)
+        self.u = [z(k * 5 * n ** 3) for k in self.nsrc]
+        self.u_new = [z(k * 5 * n ** 3) for k in self.nsrc]
+        if not gather:
+            self.u_gh = [z(k * 5 * (n + 6) ** 3) for k in self.nb]
+            self.u_half = [z(k * 5 * n ** 3) for k in self.nb[:-1]]
         # level 0 takes one step per root step, the others two
         self.rec = [[z(n * rs)] if lev == 0 else [z(n * rs), z(n * rs)]
                     for lev, n in enumerate(self.nb)]
@@ -159,13 +169,14 @@ class NestedDevice:
     def upload(self, states):
         """Per level the block interiors (B_l, 5, n, n, n) in NestedLevels
         order."""
-        for buf, s in zip(self.u, states):
-            buf.copy_(torch.from_numpy(np.ascontiguousarray(s)).reshape(-1))
+        for buf, s, k in zip(self.u, states, self.nb):
+            buf[:k * 5 * self.cells].copy_(torch.from_numpy(np.ascontiguousarray(s)).reshape(-1))
 
     def download(self):
         """Per level the block interiors (B_l, 5, n, n, n), FP64 numpy."""
         n = self.n
-        return [b.double().cpu().numpy().reshape(k, 5, n, n, n) for b, k in zip(self.u, self.nb)]
+        return [b[:k * 5 * n ** 3].double().cpu().numpy().reshape(k, 5, n, n, n)
+                for b, k in zip(self.u, self.nb)]
 
     def _batch(self, lev, dt):
         return tvd.Batch(self.code, self.nb[lev], self.n, dt=dt, dh=1.0 / (self.L.Nc << lev))
@@ -179,6 +190,8 @@ class NestedDevice:
     def _subcycle(self, lev, dt, order):
         """Level lev takes two steps of dt/2 inside level lev-1's step of dt,
         whose old state is u[lev-1] and whose advanced one u_new[lev-1]."""
+        if self.gather:
+            return self._subcycle_gather(lev, dt, order)
         ctx, h = self.ctx, 0.5 * dt
         ctx.tvd_lerp(self.code, self.nb[lev - 1] * 5 * self.cells, self.u[lev - 1],
                      self.u_new[lev - 1], self.u_half[lev - 1], 0.5)
@@ -198,15 +211,44 @@ class NestedDevice:
         ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(self.n), self.rec[lev][0],
                      self.rec[lev][1], self.rec_mean[lev], 0.5)
 
+    def _subcycle_gather(self, lev, dt, order):
+        """_subcycle without ghosted copies: the coarse-fine fill writes only
+        the interpolated ghost cells, into the stand-ins for missing
+        siblings, from the coarse level interpolated in time on the fly, and
+        the gathering advance reads the rest from the siblings."""
+        ctx, h = self.ctx, 0.5 * dt
+        fb, cb = self._batch(lev, h), self._batch(lev - 1, h)
+        for k in (0, 1):
+            o = order if k == 0 else 1 - order
+            ctx.tvd_fill_coarse_fine(fb, self.vnbr[lev], self.nsrc[lev], self.u[lev], cb,
+                                     self.u[lev - 1], self.u_new[lev - 1], 0.5 * k,
+                                     self.cnbr[lev], self.corigin[lev])
+            ctx.tvd_patch_advance_flux_gather(fb, self.vnbr[lev], self.nsrc[lev], self.u[lev],
+                                              self.u_new[lev], self.rec[lev][k], None, o,
+                                              self.gamma)
+            if lev + 1 < self.L.n_levels:
+                self._k[lev] = k
+                self._subcycle(lev + 1, h, o)
+                self._close(lev, h)
+            self.u[lev], self.u_new[lev] = self.u_new[lev], self.u[lev]
+        ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(self.n), self.rec[lev][0],
+                     self.rec[lev][1], self.rec_mean[lev], 0.5)
+
     def step(self, dt: float, order: int):
         """One root step of dt in sweep order `order` (every level sub-cycled,
         every pair closed)."""
         ctx = self.ctx
         self._k = [0] * self.L.n_levels
         b0 = self._batch(0, dt)
-        ctx.tvd_fill_ghosts(b0, self.nbr[0], self.u[0], self.u_gh[0])
-        ctx.tvd_patch_advance_flux(b0, self.u_gh[0], self.u_new[0], self.rec[0][0], None, order,
-                                   self.gamma)
+        if self.gather:
+            # the root grid is complete: every ghost cell is a sibling's
+            ctx.tvd_patch_advance_flux_gather(b0, self.vnbr[0], self.nsrc[0], self.u[0],
+                                              self.u_new[0], self.rec[0][0], None, order,
+                                              self.gamma)
+        else:
+            ctx.tvd_fill_ghosts(b0, self.nbr[0], self.u[0], self.u_gh[0])
+            ctx.tvd_patch_advance_flux(b0, self.u_gh[0], self.u_new[0], self.rec[0][0], None,
+                                       order, self.gamma)
         if self.L.n_levels > 1:
             self._subcycle(1, dt, order)
             self._close(0, dt)

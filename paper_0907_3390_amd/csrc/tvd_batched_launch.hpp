@@ -19,7 +19,16 @@ inline hipError_t launch_b(int order, bool gather, const KParams& kp, hipStream_
   const dim3 grid(kp.nblocks), block(NT);
   if (kp.flux) {
     if constexpr (kFluxVariant<T, N, NT, PAD, SPLIT>) {
-      if (gather) return hipErrorInvalidValue;
+      if (gather) {
+        if (kp.flux_acc) {
+          if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, true, 2>), grid, block, 0, s, kp);
+          else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, true, 2>), grid, block, 0, s, kp);
+        } else {
+          if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, true, 1>), grid, block, 0, s, kp);
+          else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, true, 1>), grid, block, 0, s, kp);
+        }
+        return hipGetLastError();
+      }
       if (kp.flux_acc) {
         if (order == 0) hipLaunchKernelGGL((k_batched<T, N, 0, NT, PAD, SPLIT, false, 2>), grid, block, 0, s, kp);
         else hipLaunchKernelGGL((k_batched<T, N, 1, NT, PAD, SPLIT, false, 2>), grid, block, 0, s, kp);

@@ -464,7 +464,7 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
     __syncthreads();
     if (active && tid < 27) {
       const int nb = kp.nbr[27 * (int64_t)b + tid];
-      const bool ok = nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == N;
+      const bool ok = nb >= 0 && nb < kp.nsrc && block_edge(kp, nb) == N;
       if (!ok) atomicAdd(&sm.nbad, 1);
       sm.nboff[tid] = ok ? (kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * N3) : 0;
     }
@@ -497,7 +497,16 @@ __device__ __forceinline__ void advance_block(const KParams& kp, int b, int tid,
         for (int r = 0; r < 3; ++r) src.p[r] = uin + sm.nboff[(rx + 1) + 3 * (ry + 1) + 9 * r] + t;
       }
       const LdsSink0<T, L, D0> dst{S, c1, c2};
-      pencil_sweep<T, N>(src, dst, cf);
+      T* fp = nullptr;
+      if constexpr (FLUX) {
+        // as for the ghosted source below: x pencils face (z, y) = (c2, c1),
+        // z pencils face (y, x) = (c1, c2)
+        const bool in = c1 >= kG && c1 < N + kG && c2 >= kG && c2 < N + kG;
+        fp = in ? flux_entry<T, N>(frec, D0, (ORDER == 0 ? c2 : c1) - kG,
+                                   (ORDER == 0 ? c1 : c2) - kG)
+                : nullptr;
+      }
+      pencil_sweep<T, N>(src, tap<FLUX, T, N, D0>(dst, fp, 0, kp), cf);
     }
   } else {
     const T* __restrict__ bin =

@@ -198,6 +198,7 @@ tvd::KParams make_params(tvd_ctx* ctx, const tvd_batch* b, const void* uin, void
   kp.gamma = gamma;
   kp.pfloor = pfloor;
   kp.nblocks = b->n_blocks;
+  kp.nsrc = b->n_blocks;
   kp.edge = b->d_edge ? 0 : b->edge;
   kp.nbr = nullptr;
   kp.diag = 0;
@@ -343,10 +344,17 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
                  int32_t sweep_order, double gamma, double p_floor, int32_t flags,
                  double* d_smax, double* d_sums, void* stream, const int32_t* d_nbr,
                  void* d_flux = nullptr, const int64_t* d_flux_off = nullptr,
-                 double flux_w = 1.0, int flux_acc = 0) {
+                 double flux_w = 1.0, int flux_acc = 0, int32_t n_sources = 0) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   int st = check_batch(ctx, batch);
   if (st) return st;
+  if (n_sources == 0) n_sources = batch->n_blocks;
+  if (n_sources < batch->n_blocks)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "n_sources %d < n_blocks %d", n_sources,
+                batch->n_blocks);
+  if (n_sources > batch->n_blocks && (batch->d_edge || !d_nbr))
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "source-only blocks need a gathering advance of uniform edge");
   if ((st = check_gamma(ctx, gamma, p_floor))) return st;
   if (sweep_order != TVD_XYZ && sweep_order != TVD_ZYX)
     return fail(ctx, TVD_ERR_INVALID_ARG, "sweep_order %d", sweep_order);
@@ -379,7 +387,7 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
     const size_t m = d_nbr ? batch->edge : batch->edge + 6, n = batch->edge;
     const char* a = (const char*)d_u_in;
     const char* b = (const char*)d_u_out;
-    const size_t la = (size_t)batch->n_blocks * 5 * m * m * m * es;
+    const size_t la = (size_t)n_sources * 5 * m * m * m * es;
     const size_t lb = (size_t)batch->n_blocks * 5 * n * n * n * es;
     if (a < b + lb && b < a + la) return fail(ctx, TVD_ERR_ALIAS, "input and output overlap");
   }
@@ -389,6 +397,9 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   const bool fuse = d_smax || d_sums;
   const bool persistent = flags == TVD_KERNEL_PERSISTENT ||
                           (batch->d_edge && flags == TVD_KERNEL_AUTO);
+  if (d_flux && d_nbr && persistent)
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "the gathering flux-recording advance runs the batched kernel (uniform edge)");
   if ((fuse || persistent) && (st = need_workspace(ctx, batch->n_blocks))) return st;
   tvd::KParams kp = make_params(ctx, batch, d_u_in, d_u_out, gamma, p_floor);
   hipError_t e;
@@ -399,6 +410,7 @@ int advance_impl(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u_in, void*
   if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(kp.ws_sums, 10 * (int64_t)batch->n_blocks, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
   kp.nbr = d_nbr;
+  kp.nsrc = n_sources;
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
   kp.flux = d_flux;
   kp.flux_off = d_flux_off;
@@ -678,6 +690,27 @@ int tvd_patch_advance_flux(tvd_ctx* ctx, const tvd_batch* batch, const void* d_u
     return fail(ctx, TVD_ERR_INVALID_ARG, "accumulate %d is neither 0 nor 1", accumulate);
   return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
                       d_sums, stream, nullptr, d_flux, d_flux_off, flux_weight, accumulate);
+}
+
+int tvd_patch_advance_flux_gather(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                                  int32_t n_sources, const void* d_u_in, void* d_u_out,
+                                  void* d_flux, const int64_t* d_flux_off, double flux_weight,
+                                  int32_t accumulate, int32_t sweep_order, double gamma,
+                                  double p_floor, int32_t flags, double* d_smax, double* d_sums,
+                                  void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  if (!d_nbr) return fail(ctx, TVD_ERR_INVALID_ARG, "d_nbr is NULL");
+  if (!d_flux) return fail(ctx, TVD_ERR_INVALID_ARG, "d_flux is NULL");
+  if (n_sources < 0) return fail(ctx, TVD_ERR_INVALID_ARG, "n_sources %d < 0", n_sources);
+  if (!(flux_weight == flux_weight) || flux_weight < -1e300 || flux_weight > 1e300)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "flux_weight %g", flux_weight);
+  if (accumulate != 0 && accumulate != 1)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "accumulate %d is neither 0 nor 1", accumulate);
+  if (flags == TVD_KERNEL_PLAIN || flags == TVD_KERNEL_PERSISTENT)
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "the gathering flux-recording advance is batched");
+  return advance_impl(ctx, batch, d_u_in, d_u_out, sweep_order, gamma, p_floor, flags, d_smax,
+                      d_sums, stream, d_nbr, d_flux, d_flux_off, flux_weight, accumulate,
+                      n_sources);
 }
 
 int tvd_lerp(tvd_ctx* ctx, int32_t dtype, int64_t n, const void* d_a, const void* d_b,
@@ -1082,6 +1115,41 @@ int tvd_fill_ghosts_amr(tvd_ctx* ctx, const tvd_batch* fine, const int32_t* d_nb
                                              coarse->d_out_off, coarse->n_blocks, coarse->edge,
                                              d_cnbr, d_corigin, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "coarse-fine ghost fill launch");
+  return TVD_OK;
+}
+
+int tvd_fill_coarse_fine(tvd_ctx* ctx, const tvd_batch* fine, const int32_t* d_nbr,
+                         int32_t n_sources, void* d_fine_interior, const tvd_batch* coarse,
+                         const void* d_coarse_old, const void* d_coarse_new, double w,
+                         const int32_t* d_cnbr, const int32_t* d_corigin, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, fine);
+  if (st) return st;
+  if ((st = check_batch(ctx, coarse))) return st;
+  if (coarse->dtype != fine->dtype)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "coarse and fine batches differ in dtype");
+  if (fine->d_edge || fine->d_in_off || fine->d_out_off)
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "the fine batch must be dense with a uniform edge");
+  if (coarse->d_edge || (coarse->edge != 8 && coarse->edge != 16))
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "coarse blocks must have a uniform edge of 8 (patches) or 16 (patch groups)");
+  if (n_sources < fine->n_blocks)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "n_sources %d < n_blocks %d", n_sources,
+                fine->n_blocks);
+  if (!(w >= 0.0 && w <= 1.0)) return fail(ctx, TVD_ERR_INVALID_ARG, "w %g outside [0, 1]", w);
+  if (fine->n_blocks == 0 || n_sources == fine->n_blocks) return TVD_OK;
+  if (!d_nbr || !d_fine_interior || !d_coarse_old || !d_cnbr || !d_corigin ||
+      (w != 0.0 && !d_coarse_new))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "NULL pointer");
+  if (d_fine_interior == d_coarse_old || d_fine_interior == d_coarse_new)
+    return fail(ctx, TVD_ERR_ALIAS, "the fine interiors are a coarse state");
+  DeviceGuard g(ctx->device);
+  tvd::KParams kp = make_params(ctx, fine, nullptr, d_fine_interior, 1.0, 0.0);
+  kp.nsrc = n_sources;
+  hipError_t e = tvd::launch_fill_coarse_fine(
+      fine->dtype, kp, d_nbr, d_coarse_old, w != 0.0 ? d_coarse_new : d_coarse_old, w,
+      coarse->d_out_off, coarse->n_blocks, coarse->edge, d_cnbr, d_corigin, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "coarse-fine fill launch");
   return TVD_OK;
 }
 

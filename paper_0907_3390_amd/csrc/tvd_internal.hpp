@@ -22,6 +22,8 @@ struct KParams {
   const double* d_dh;
   double dt, dh, gamma, pfloor;
   int nblocks;
+  int nsrc;                      // blocks a gathering advance may read as neighbours
+                                 // (>= nblocks; the extra ones are sources only)
   int edge;                      // uniform edge (0 when d_edge is used)
   const int32_t* nbr;            // [nblocks][27] neighbour table (gather mode)
   int diag;                      // kDiagSpeed | kDiagSums
@@ -82,6 +84,14 @@ hipError_t launch_fill_ghosts(int dtype, const KParams& kp, const int32_t* nbr, 
 hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* nbr, int max_edge,
                                   const void* cin, const int64_t* coff, int ncoarse, int cedge,
                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s);
+// Coarse-fine ghost cells of a gathering advance into source-only blocks
+// (kp.nblocks real fine blocks of uniform edge kp.edge, nbr entries >=
+// kp.nblocks and < kp.nsrc name the stand-ins, interiors at kp.uout), the
+// coarse level at old + w (new - old).
+hipError_t launch_fill_coarse_fine(int dtype, const KParams& kp, const int32_t* nbr,
+                                   const void* cold, const void* cnew, double w,
+                                   const int64_t* coff, int ncoarse, int cedge,
+                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 // Closing step of a level pair: ck is the coarse level (interior blocks read
 // and written at uout / out_off, flux records at flux / flux_off), fk the

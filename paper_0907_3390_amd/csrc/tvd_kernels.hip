@@ -396,6 +396,87 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
   }
 }
 
+// Coarse neighbourhood at a time between two coarse states: each coarse
+// value is old + w (new - old) (w = 0: the old state alone), the same
+// expression as tvd_lerp.
+template <typename T>
+struct CoarseNbhdT {
+  CoarseNbhd<T> a, b;
+  T w;
+  __device__ inline bool get(int ix, int iy, int iz, T u[kNV]) const {
+    const bool ok = a.get(ix, iy, iz, u);
+    if (w != T(0)) {
+      T v[kNV];
+      b.get(ix, iy, iz, v);
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) u[k] = u[k] + w * (v[k] - u[k]);
+    }
+    return ok;
+  }
+};
+
+// The coarse-fine ghost zones of a gathering advance: fine block b's ghost
+// cells in every region whose neighbour entry names a source-only block
+// (index >= kp.nblocks: a stand-in for the missing sibling) are
+// interpolated from the coarse level (Min-Mod limited, as in
+// fill_interp) and written into that block's interior, where the
+// gathering advance reads them; regions with a real sibling are left to
+// the advance.  Cells shared by several fine blocks get the same value from
+// each (the same coarse cells in the same order).
+template <typename T>
+__global__ __launch_bounds__(kFillNT) void k_fill_coarse_fine(
+    KParams kp, const int32_t* nbr, int chunks, const T* cold, const T* cnew, T w,
+    const int64_t* coff, int ncoarse, int cshift, const int32_t* cnbr, const int32_t* corigin) {
+  const int b = blockIdx.x / chunks;
+  const int chunk = blockIdx.x % chunks;
+  const int n = kp.edge;
+  const int m = n + 2 * kG;
+  const int cell = chunk * kFillNT + threadIdx.x;
+  if (cell >= m * m * m) return;
+  const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+  const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
+  const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
+  const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
+  const int v = nbr[27 * (int64_t)b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
+  if (v < kp.nblocks) return;  // the block itself, or a real sibling
+  if (v >= kp.nsrc || ncoarse <= 0) {
+    atomicAdd(&kp.counters[1], 1ull);
+    return;
+  }
+  const int64_t n3 = (int64_t)n * n * n;
+  T* d = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[v] : (int64_t)v * kNV * n3) +
+         ((x - kG - rx * n) + n * ((y - kG - ry * n) + n * (z - kG - rz * n)));
+  const int fx = 2 * corigin[3 * b + 0] + x - kG;
+  const int fy = 2 * corigin[3 * b + 1] + y - kG;
+  const int fz = 2 * corigin[3 * b + 2] + z - kG;
+  const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;
+  const T q = T(0.25);
+  const T dx = (fx & 1) ? q : -q, dy = (fy & 1) ? q : -q, dz = (fz & 1) ? q : -q;
+  const int32_t* cn27 = cnbr + 27 * (int64_t)b;
+  const CoarseNbhdT<T> cn{{cold, coff, cn27, ncoarse, cshift}, {cnew, coff, cn27, ncoarse, cshift},
+                          w};
+  T u[kNV], xp[kNV], xm[kNV], yp[kNV], ym[kNV], zp[kNV], zm[kNV];
+  bool ok = cn.get(cx, cy, cz, u);
+  ok = cn.get(cx + 1, cy, cz, xp) & ok;
+  ok = cn.get(cx - 1, cy, cz, xm) & ok;
+  ok = cn.get(cx, cy + 1, cz, yp) & ok;
+  ok = cn.get(cx, cy - 1, cz, ym) & ok;
+  ok = cn.get(cx, cy, cz + 1, zp) & ok;
+  ok = cn.get(cx, cy, cz - 1, zm) & ok;
+  if (!ok) {
+    atomicAdd(&kp.counters[1], 1ull);
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) {
+    T o = u[k];
+    o = o + dx * minmod(xp[k] - u[k], u[k] - xm[k]);
+    o = o + dy * minmod(yp[k] - u[k], u[k] - ym[k]);
+    o = o + dz * minmod(zp[k] - u[k], u[k] - zm[k]);
+    d[(int64_t)k * n3] = o;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // closing step of a level pair (Sec. 2.1, step 3; Sec. 3.1)
 // ---------------------------------------------------------------------------
@@ -884,6 +965,25 @@ hipError_t launch_fill_ghosts_amr(int dtype, const KParams& kp, const int32_t* n
   else
     hipLaunchKernelGGL((k_fill_ghosts_amr<double>), grid, block, 0, s, kp, nbr, chunks,
                        static_cast<const double*>(cin), coff, ncoarse, cshift, cnbr, corigin);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_coarse_fine(int dtype, const KParams& kp, const int32_t* nbr,
+                                   const void* cold, const void* cnew, double w,
+                                   const int64_t* coff, int ncoarse, int cedge,
+                                   const int32_t* cnbr, const int32_t* corigin, hipStream_t s) {
+  const int cshift = cedge == 16 ? 4 : 3;
+  const int m = kp.edge + 2 * kG;
+  const int chunks = (m * m * m + kFillNT - 1) / kFillNT;
+  const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
+  if (dtype == 1)
+    hipLaunchKernelGGL((k_fill_coarse_fine<float>), grid, block, 0, s, kp, nbr, chunks,
+                       static_cast<const float*>(cold), static_cast<const float*>(cnew), (float)w,
+                       coff, ncoarse, cshift, cnbr, corigin);
+  else
+    hipLaunchKernelGGL((k_fill_coarse_fine<double>), grid, block, 0, s, kp, nbr, chunks,
+                       static_cast<const double*>(cold), static_cast<const double*>(cnew), w,
+                       coff, ncoarse, cshift, cnbr, corigin);
   return hipGetLastError();
 }
 

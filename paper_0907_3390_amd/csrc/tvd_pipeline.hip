@@ -164,7 +164,7 @@ hipError_t run_host_pipeline(const HostPipe& hp, double times[7]) {
         KParams kp = hp.kp;
         kp.uin = d_in(s);
         kp.uout = d_out(s);
-        kp.nblocks = (int)(hi - lo);
+        kp.nblocks = kp.nsrc = (int)(hi - lo);
         e2 = launch_batched(hp.dtype, hp.order, hp.variant, false, kp, st);
       }
       if (e2 == hipSuccess && te) e2 = hipEventRecord(te[2], st);

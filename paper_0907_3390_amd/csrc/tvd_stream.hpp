@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
       const int b = sp.blocks[c0 + w / 27];
       if (b < 0 || b >= kp.nblocks) continue;  // counted above
       const int nb = kp.nbr[27 * (int64_t)b + w % 27];
-      if (!(nb >= 0 && nb < kp.nblocks && block_edge(kp, nb) == E &&
+      if (!(nb >= 0 && nb < kp.nsrc && block_edge(kp, nb) == E &&
             (kp.out_off ? kp.out_off[nb] : (int64_t)nb * kNV * E * E * E) % kAlign == 0))
         atomicAdd(&sm.nbad, 1);
     }

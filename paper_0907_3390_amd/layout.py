@@ -557,6 +557,29 @@ class NestedLevels:
             self.cnbr.append(cnbr)
             self.corigin.append(corigin)
 
+    def stand_ins(self, level):
+        """The source-only stand-ins for the missing siblings of level
+        `level`'s blocks (tvd_fill_coarse_fine, tvd_patch_advance_flux_gather):
+        returns (nbr, n_sources) where nbr is the level's sibling table with
+        every -1 replaced by an index >= n_blocks, one per missing block
+        position (shared by all the blocks around it, numbered in order of
+        first use), and n_sources = n_blocks + the number of stand-ins."""
+        bs = self.blocks[level]
+        n = self.n
+        ng = (self.Nc << level) // n
+        nbr = bs.nbr.copy()
+        pos = self.origins[level] // n          # (z, y, x) block coordinates
+        index = {}
+        for b in range(bs.n_blocks):
+            z, y, x = (int(v) for v in pos[b])
+            for r in np.nonzero(nbr[b] < 0)[0]:
+                rx, ry, rz = r % 3 - 1, (r // 3) % 3 - 1, r // 9 - 1
+                q = ((x + rx) % ng, (y + ry) % ng, (z + rz) % ng)
+                if q not in index:
+                    index[q] = bs.n_blocks + len(index)
+                nbr[b, r] = index[q]
+        return nbr, bs.n_blocks + len(index)
+
     def locate(self, level, px, py, pz):
         if self.n == PATCH:
             return self._index[level][(px, py, pz)], (0, 0, 0)

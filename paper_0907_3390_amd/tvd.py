@@ -45,6 +45,7 @@ EXPORTS = [
     "tvd_close_level", "tvd_poisson_sor", "tvd_gravity", "tvd_lerp",
     "tvd_patch_advance_stream", "tvd_patch_advance_stream_noalloc",
     "tvd_pipeline_stage_bytes", "tvd_patch_advance_host",
+    "tvd_patch_advance_flux_gather", "tvd_fill_coarse_fine",
 ]
 
 
@@ -118,6 +119,10 @@ def load(path: str = LIB_PATH):
         "tvd_patch_advance_flux": (ctypes.c_int, [vp, bp, vp, vp, vp, vp, dbl, i32, i32, dbl, dbl,
                                                   i32, vp, vp, vp]),
         "tvd_lerp": (ctypes.c_int, [vp, i32, ctypes.c_int64, vp, vp, vp, dbl, vp]),
+        "tvd_patch_advance_flux_gather": (ctypes.c_int, [vp, bp, vp, i32, vp, vp, vp, vp, dbl,
+                                                         i32, i32, dbl, dbl, i32, vp, vp, vp]),
+        "tvd_fill_coarse_fine": (ctypes.c_int, [vp, bp, vp, i32, vp, bp, vp, vp, dbl, vp, vp,
+                                                vp]),
         "tvd_restrict": (ctypes.c_int, [vp, bp, vp, bp, vp, vp, i32, vp]),
         "tvd_flux_correct": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), vp]),
@@ -332,6 +337,26 @@ class Context:
                                              _ptr(flux), _ptr(flux_off), flux_weight, accumulate,
                                              sweep_order, gamma, p_floor, flags, _ptr(smax),
                                              _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_patch_advance_flux_gather(self, batch: Batch, nbr, n_sources: int, u_in, u_out, flux,
+                                      flux_off, sweep_order: int, gamma: float,
+                                      p_floor: float = 0.0, flags: int = TVD_KERNEL_AUTO,
+                                      smax=None, sums=None, stream=None, check: bool = True,
+                                      flux_weight: float = 1.0, accumulate: int = 0):
+        st = self.lib.tvd_patch_advance_flux_gather(
+            self.h, batch.ref, _ptr(nbr), n_sources, _ptr(u_in), _ptr(u_out), _ptr(flux),
+            _ptr(flux_off), flux_weight, accumulate, sweep_order, gamma, p_floor, flags,
+            _ptr(smax), _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_fill_coarse_fine(self, fine: Batch, nbr, n_sources: int, fine_interior, coarse: Batch,
+                             coarse_old, coarse_new, w: float, cnbr, corigin, stream=None,
+                             check: bool = True):
+        st = self.lib.tvd_fill_coarse_fine(self.h, fine.ref, _ptr(nbr), n_sources,
+                                           _ptr(fine_interior), coarse.ref, _ptr(coarse_old),
+                                           _ptr(coarse_new), w, _ptr(cnbr), _ptr(corigin),
+                                           _stream(stream))
         return self._check(st) if check else st
 
     def tvd_lerp(self, dtype: int, n: int, a, b, out, w: float, stream=None, check: bool = True):

@@ -440,3 +440,42 @@ def test_multilevel_closing_conserves_full_size(ctx, hierarchy, mode):
     # the leaf total
     root = _hierarchy_sums(ml, P_got, 8, False)[0]
     assert np.all(np.abs(root - after) <= tol * scale)
+
+
+@pytest.mark.parametrize("dtype,n", [(torch.float64, 8), (torch.float32, 8), (torch.float32, 16)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_flux_records_gathering_advance(ctx, dtype, n, order):
+    """tvd_patch_advance_flux_gather (ghost zones read from the neighbours'
+    interiors, one source-only block appended) gives the same state and the
+    same flux records, bit for bit, as tvd_patch_advance_flux on the
+    ghosted copies, in writing and in accumulating mode."""
+    note(f"gathering flux-recording advance dtype={dtype} n={n} order={order}")
+    N = 32
+    g = wl.lognormal(N, seed=70 + n + order, sigma_ln=0.6)
+    if dtype == torch.float32:
+        g = g.astype(np.float32).astype(np.float64)
+    bs = layout.periodic_grid_blockset(N, n)
+    nb, code = bs.n_blocks, tvd.dtype_code(dtype)
+    batch = tvd.Batch(code, nb, n, dt=0.2 / N, dh=1.0 / N)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    interior = dev(bs.pack_interior(layout.grid_to_blocks(g, n))).to(dtype)
+    # one extra source-only block (never named by the table): the source count
+    # may exceed n_blocks
+    src = torch.cat([interior, torch.full((5 * n ** 3,), float("nan"), dtype=dtype,
+                                          device="cuda")])
+    ghosted = torch.zeros(bs.in_total, dtype=dtype, device="cuda")
+    ctx.tvd_fill_ghosts(batch, dev(bs.nbr), interior, ghosted)
+    rs = layout.flux_record_size(n)
+    for acc in (0, 1):
+        out_a = torch.zeros(bs.out_total, dtype=dtype, device="cuda")
+        out_b = torch.zeros_like(out_a)
+        rec_a = torch.ones(nb * rs, dtype=dtype, device="cuda")
+        rec_b = torch.ones_like(rec_a)
+        ctx.tvd_patch_advance_flux(batch, ghosted, out_a, rec_a, None, order, GAMMA,
+                                   flux_weight=0.5, accumulate=acc)
+        ctx.tvd_patch_advance_flux_gather(batch, dev(bs.nbr), nb + 1, src, out_b, rec_b, None,
+                                          order, GAMMA, flux_weight=0.5, accumulate=acc)
+        torch.cuda.synchronize()
+        assert torch.equal(out_a, out_b)
+        assert torch.equal(rec_a, rec_b)
+        assert torch.isfinite(rec_b).all()

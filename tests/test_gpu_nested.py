@@ -93,6 +93,34 @@ def test_nested_driver_matches_oracle(ctx, dtype, n):
               FP64 if dtype == torch.float64 else (1e-5, 1e-4))
 
 
+@pytest.mark.parametrize("dtype,n", [(torch.float64, 8), (torch.float32, 8),
+                                     (torch.float32, 16)])
+def test_nested_gather_equals_ghosted_copies(ctx, dtype, n):
+    """The driver without ghosted copies (coarse-fine cells interpolated into
+    stand-ins for the missing siblings, with the coarse level interpolated
+    in time on the fly; the gathering flux-recording advance) gives the same
+    bits as the driver that materialises every ghosted block, over two root
+    steps, with no cell counted as non-physical."""
+    note(f"nested driver, gathering vs ghosted copies, dtype={dtype}, blocks of {n}^3")
+    states = _states(530, dtype == torch.float32)
+    ref = amr.NestedDevice(ctx, NC, _refined(), dtype=dtype, n=n)
+    got = amr.NestedDevice(ctx, NC, _refined(), dtype=dtype, n=n, gather=True)
+    assert got.nsrc[1] > got.nb[1]
+    blocks = [b.astype(np.float32) if dtype == torch.float32 else b
+              for b in _blocks(ref.L, states)]
+    for d in (ref, got):
+        d.upload(blocks)
+    ctx.tvd_read_flags()
+    dt = 0.1 / NC
+    for o in (0, 1):
+        ref.step(dt, o)
+        got.step(dt, o)
+    torch.cuda.synchronize()
+    assert ctx.tvd_read_flags()[2] == 0
+    for a, b in zip(ref.download(), got.download()):
+        assert np.array_equal(a, b)
+
+
 def test_nested_driver_conserves_over_steps(ctx):
     states = _states(510, False)
     dev = amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float64)
@@ -140,8 +168,8 @@ def test_nested_step_graph_replay(ctx):
         g.close()
 
 
-@pytest.mark.parametrize("n", [8, 16])
-def test_nested_full_size_conserves_fp32(ctx, n):
+@pytest.mark.parametrize("n,gather", [(8, False), (16, False), (16, True)])
+def test_nested_full_size_conserves_fp32(ctx, n, gather):
     """The full multi-level hierarchy (128^3 base, levels 1-3, 18 152 patches,
     the bench's configuration, as patches or as 2269 patch groups), FP32,
     every level sub-cycled: over four root steps (32 level-3 steps) the leaf
@@ -149,10 +177,10 @@ def test_nested_full_size_conserves_fp32(ctx, n):
     of each variable's scale; momentum against mass times the signal speed,
     the gas starting at rest), and no cell is floored or non-physical."""
     from paper_0907_3390_amd import layout
-    note(f"nested driver, full multi-level hierarchy, fp32, blocks of {n}^3")
+    note(f"nested driver, full multi-level hierarchy, fp32, blocks of {n}^3, gather {gather}")
     ml = wl.multilevel()
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
-    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n)
+    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
     per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
