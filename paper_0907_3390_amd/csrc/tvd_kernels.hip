@@ -396,85 +396,141 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
   }
 }
 
-// Coarse neighbourhood at a time between two coarse states: each coarse
-// value is old + w (new - old) (w = 0: the old state alone), the same
-// expression as tvd_lerp.
-template <typename T>
-struct CoarseNbhdT {
-  CoarseNbhd<T> a, b;
-  T w;
-  __device__ inline bool get(int ix, int iy, int iz, T u[kNV]) const {
-    const bool ok = a.get(ix, iy, iz, u);
-    if (w != T(0)) {
-      T v[kNV];
-      b.get(ix, iy, iz, v);
-#pragma unroll
-      for (int k = 0; k < kNV; ++k) u[k] = u[k] + w * (v[k] - u[k]);
-    }
-    return ok;
-  }
-};
-
 // The coarse-fine ghost zones of a gathering advance: fine block b's ghost
 // cells in every region whose neighbour entry names a source-only block
 // (index >= kp.nblocks: a stand-in for the missing sibling) are
-// interpolated from the coarse level (Min-Mod limited, as in
-// fill_interp) and written into that block's interior, where the
-// gathering advance reads them; regions with a real sibling are left to
-// the advance.  Cells shared by several fine blocks get the same value from
-// each (the same coarse cells in the same order).
+// interpolated from the coarse level (Min-Mod limited, as in fill_interp)
+// and written into that block's interior, where the gathering advance
+// reads them; regions with a real sibling are left to the advance.  The
+// coarse level is taken at old + w (new - old) (w = 0: the old state
+// alone), the same expression as tvd_lerp.
+//
+// One workgroup per (fine block, ghost region).  The coarse cells under the
+// region's ghost slab (3 fine cells thick) and the ring of cells around them
+// that their stencils reach are staged in LDS first, each read once (at
+// old + w (new - old)) with all of a thread's reads in flight together; then
+// one thread per coarse cell under the slab takes the three limited slopes
+// from LDS and writes those of the cell's eight children that lie in the
+// slab, each as u + dx s_x + dy s_y + dz s_z in that order, the same
+// operations as for a single ghost cell in fill_interp.  Cells shared by the
+// slabs of several fine blocks get the same value from each.
+constexpr int kCfNT = 128;     // coarse cells under a face slab of a 16^3 block: 2 x 8 x 8
+constexpr int kCfStage = 400;  // staged coarse cells of that slab: 4 x 10 x 10
+constexpr int kCfPer = (kCfStage + kCfNT - 1) / kCfNT;
+
 template <typename T>
-__global__ __launch_bounds__(kFillNT) void k_fill_coarse_fine(
-    KParams kp, const int32_t* nbr, int chunks, const T* cold, const T* cnew, T w,
-    const int64_t* coff, int ncoarse, int cshift, const int32_t* cnbr, const int32_t* corigin) {
-  const int b = blockIdx.x / chunks;
-  const int chunk = blockIdx.x % chunks;
-  const int n = kp.edge;
-  const int m = n + 2 * kG;
-  const int cell = chunk * kFillNT + threadIdx.x;
-  if (cell >= m * m * m) return;
-  const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
-  const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
-  const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
-  const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
-  const int v = nbr[27 * (int64_t)b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
-  if (v < kp.nblocks) return;  // the block itself, or a real sibling
+__global__ __launch_bounds__(kCfNT) void k_fill_coarse_fine(
+    KParams kp, const int32_t* nbr, const T* cold, const T* cnew, T w, const int64_t* coff,
+    int ncoarse, int cshift, const int32_t* cnbr, const int32_t* corigin) {
+  __shared__ T sv[kNV][kCfStage];
+  __shared__ int sok[kCfStage];
+  __shared__ int32_t scb[27];
+  const int b = blockIdx.x / 26, rr = blockIdx.x % 26;
+  const int r = rr < 13 ? rr : rr + 1;
+  const int ra[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
+  const int v = nbr[27 * (int64_t)b + r];
+  if (v < kp.nblocks) return;  // a real sibling (uniform over the workgroup)
+  const int n = kp.edge, h = n / 2;
+  const int co[3] = {corigin[3 * b + 0], corigin[3 * b + 1], corigin[3 * b + 2]};
+  // per axis: the slab's ghosted fine coordinates [lo, hi) and the coarse
+  // cells [c0, c0 + cnt) under it
+  int lo[3], hi[3], c0[3], cnt[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ra[a] < 0 ? 0 : (ra[a] == 0 ? kG : n + kG);
+    hi[a] = ra[a] < 0 ? kG : (ra[a] == 0 ? n + kG : n + 2 * kG);
+    c0[a] = ra[a] < 0 ? co[a] - 2 : (ra[a] == 0 ? co[a] : co[a] + h);
+    cnt[a] = ra[a] == 0 ? h : 2;
+  }
+  const int t = threadIdx.x;
+  const bool mine = t < cnt[0] * cnt[1] * cnt[2];
+  const int l[3] = {t % cnt[0], (t / cnt[0]) % cnt[1], t / (cnt[0] * cnt[1])};
+  int kids = 0;  // children of this thread's coarse cell inside the slab
+#pragma unroll
+  for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+    for (int py = 0; py < 2; ++py)
+#pragma unroll
+      for (int px = 0; px < 2; ++px) {
+        const int g[3] = {2 * (c0[0] + l[0]) + px - 2 * co[0] + kG,
+                          2 * (c0[1] + l[1]) + py - 2 * co[1] + kG,
+                          2 * (c0[2] + l[2]) + pz - 2 * co[2] + kG};
+        kids += g[0] >= lo[0] && g[0] < hi[0] && g[1] >= lo[1] && g[1] < hi[1] &&
+                g[2] >= lo[2] && g[2] < hi[2];
+      }
   if (v >= kp.nsrc || ncoarse <= 0) {
-    atomicAdd(&kp.counters[1], 1ull);
+    if (mine) atomicAdd(&kp.counters[1], (unsigned long long)kids);
     return;
   }
-  const int64_t n3 = (int64_t)n * n * n;
-  T* d = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[v] : (int64_t)v * kNV * n3) +
-         ((x - kG - rx * n) + n * ((y - kG - ry * n) + n * (z - kG - rz * n)));
-  const int fx = 2 * corigin[3 * b + 0] + x - kG;
-  const int fy = 2 * corigin[3 * b + 1] + y - kG;
-  const int fz = 2 * corigin[3 * b + 2] + z - kG;
-  const int cx = fx >> 1, cy = fy >> 1, cz = fz >> 1;
-  const T q = T(0.25);
-  const T dx = (fx & 1) ? q : -q, dy = (fy & 1) ? q : -q, dz = (fz & 1) ? q : -q;
-  const int32_t* cn27 = cnbr + 27 * (int64_t)b;
-  const CoarseNbhdT<T> cn{{cold, coff, cn27, ncoarse, cshift}, {cnew, coff, cn27, ncoarse, cshift},
-                          w};
-  T u[kNV], xp[kNV], xm[kNV], yp[kNV], ym[kNV], zp[kNV], zm[kNV];
-  bool ok = cn.get(cx, cy, cz, u);
-  ok = cn.get(cx + 1, cy, cz, xp) & ok;
-  ok = cn.get(cx - 1, cy, cz, xm) & ok;
-  ok = cn.get(cx, cy + 1, cz, yp) & ok;
-  ok = cn.get(cx, cy - 1, cz, ym) & ok;
-  ok = cn.get(cx, cy, cz + 1, zp) & ok;
-  ok = cn.get(cx, cy, cz - 1, zm) & ok;
-  if (!ok) {
-    atomicAdd(&kp.counters[1], 1ull);
-    return;
+  if (t < 27) scb[t] = cnbr[27 * (int64_t)b + t];
+  __syncthreads();
+  // stage the box [c0 - 1, c0 + cnt + 1) per axis
+  const int s[3] = {cnt[0] + 2, cnt[1] + 2, cnt[2] + 2};
+  const int ns = s[0] * s[1] * s[2];
+  const CoarseNbhd<T> ca{cold, coff, scb, ncoarse, cshift}, cb{cnew, coff, scb, ncoarse, cshift};
+  T a[kCfPer][kNV], e[kCfPer][kNV];
+  bool okj[kCfPer];
+#pragma unroll
+  for (int j = 0; j < kCfPer; ++j) {
+    const int i = min(t + j * kCfNT, ns - 1);  // past the box: a repeat of its last cell
+    const int ix = c0[0] - 1 + i % s[0], iy = c0[1] - 1 + (i / s[0]) % s[1],
+              iz = c0[2] - 1 + i / (s[0] * s[1]);
+    okj[j] = ca.get(ix, iy, iz, a[j]);
+    if (w != T(0)) cb.get(ix, iy, iz, e[j]);
   }
 #pragma unroll
-  for (int k = 0; k < kNV; ++k) {
-    T o = u[k];
-    o = o + dx * minmod(xp[k] - u[k], u[k] - xm[k]);
-    o = o + dy * minmod(yp[k] - u[k], u[k] - ym[k]);
-    o = o + dz * minmod(zp[k] - u[k], u[k] - zm[k]);
-    d[(int64_t)k * n3] = o;
+  for (int j = 0; j < kCfPer; ++j) {
+    const int i = t + j * kCfNT;
+    if (i >= ns) continue;
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) sv[k][i] = w != T(0) ? a[j][k] + w * (e[j][k] - a[j][k]) : a[j][k];
+    sok[i] = okj[j];
   }
+  __syncthreads();
+  if (!mine) return;
+  const int sc = (l[0] + 1) + s[0] * ((l[1] + 1) + s[1] * (l[2] + 1));
+  const int sx1 = 1, sy1 = s[0], sz1 = s[0] * s[1];
+  const bool ok = sok[sc] & sok[sc + sx1] & sok[sc - sx1] & sok[sc + sy1] & sok[sc - sy1] &
+                  sok[sc + sz1] & sok[sc - sz1];
+  if (!ok) {
+    atomicAdd(&kp.counters[1], (unsigned long long)kids);
+    return;
+  }
+  T u[kNV], sx[kNV], sy[kNV], sz[kNV];
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) {
+    u[k] = sv[k][sc];
+    sx[k] = minmod(sv[k][sc + sx1] - u[k], u[k] - sv[k][sc - sx1]);
+    sy[k] = minmod(sv[k][sc + sy1] - u[k], u[k] - sv[k][sc - sy1]);
+    sz[k] = minmod(sv[k][sc + sz1] - u[k], u[k] - sv[k][sc - sz1]);
+  }
+  const int64_t n3 = (int64_t)n * n * n;
+  T* d = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[v] : (int64_t)v * kNV * n3);
+  const T q = T(0.25);
+#pragma unroll
+  for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+    for (int py = 0; py < 2; ++py)
+#pragma unroll
+      for (int px = 0; px < 2; ++px) {
+        const int g[3] = {2 * (c0[0] + l[0]) + px - 2 * co[0] + kG,
+                          2 * (c0[1] + l[1]) + py - 2 * co[1] + kG,
+                          2 * (c0[2] + l[2]) + pz - 2 * co[2] + kG};
+        if (!(g[0] >= lo[0] && g[0] < hi[0] && g[1] >= lo[1] && g[1] < hi[1] && g[2] >= lo[2] &&
+              g[2] < hi[2]))
+          continue;
+        const T dx = px ? q : -q, dy = py ? q : -q, dz = pz ? q : -q;
+        const int64_t o = (g[0] - kG - ra[0] * n) + n * ((g[1] - kG - ra[1] * n) +
+                                                           (int64_t)n * (g[2] - kG - ra[2] * n));
+#pragma unroll
+        for (int k = 0; k < kNV; ++k) {
+          T val = u[k];
+          val = val + dx * sx[k];
+          val = val + dy * sy[k];
+          val = val + dz * sz[k];
+          d[(int64_t)k * n3 + o] = val;
+        }
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -973,15 +1029,13 @@ hipError_t launch_fill_coarse_fine(int dtype, const KParams& kp, const int32_t* 
                                    const int64_t* coff, int ncoarse, int cedge,
                                    const int32_t* cnbr, const int32_t* corigin, hipStream_t s) {
   const int cshift = cedge == 16 ? 4 : 3;
-  const int m = kp.edge + 2 * kG;
-  const int chunks = (m * m * m + kFillNT - 1) / kFillNT;
-  const dim3 grid((unsigned)kp.nblocks * chunks), block(kFillNT);
+  const dim3 grid((unsigned)kp.nblocks * 26u), block(kCfNT);
   if (dtype == 1)
-    hipLaunchKernelGGL((k_fill_coarse_fine<float>), grid, block, 0, s, kp, nbr, chunks,
+    hipLaunchKernelGGL((k_fill_coarse_fine<float>), grid, block, 0, s, kp, nbr,
                        static_cast<const float*>(cold), static_cast<const float*>(cnew), (float)w,
                        coff, ncoarse, cshift, cnbr, corigin);
   else
-    hipLaunchKernelGGL((k_fill_coarse_fine<double>), grid, block, 0, s, kp, nbr, chunks,
+    hipLaunchKernelGGL((k_fill_coarse_fine<double>), grid, block, 0, s, kp, nbr,
                        static_cast<const double*>(cold), static_cast<const double*>(cnew), w,
                        coff, ncoarse, cshift, cnbr, corigin);
   return hipGetLastError();
