@@ -469,7 +469,9 @@ int tvd_fill_ghosts_amr(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nb
  * from each.  Then tvd_patch_advance_flux_gather with the same table and
  * n_sources advances the real blocks.  A source index at or beyond
  * n_sources, or a coarse stencil leaving the 27 coarse blocks, is counted
- * as non-physical and the cell left untouched.  Asynchronous on stream.
+ * as non-physical and the cell left untouched.  The fine batch may hold at
+ * most 1 290 555 blocks (one launch of 26 x 128 work-items per block);
+ * more is TVD_ERR_UNSUPPORTED.  Asynchronous on stream.
  */
 int tvd_fill_coarse_fine(tvd_ctx *ctx, const tvd_batch *fine, const int32_t *d_nbr,
                          int32_t n_sources, void *d_fine_interior, const tvd_batch *coarse,

@@ -1137,6 +1137,8 @@ int tvd_fill_coarse_fine(tvd_ctx* ctx, const tvd_batch* fine, const int32_t* d_n
     return fail(ctx, TVD_ERR_INVALID_ARG, "n_sources %d < n_blocks %d", n_sources,
                 fine->n_blocks);
   if (!(w >= 0.0 && w <= 1.0)) return fail(ctx, TVD_ERR_INVALID_ARG, "w %g outside [0, 1]", w);
+  if ((int64_t)fine->n_blocks * 26 * 128 >= (int64_t)1 << 32)
+    return fail(ctx, TVD_ERR_UNSUPPORTED, "n_blocks %d > 1290555 (launch size)", fine->n_blocks);
   if (fine->n_blocks == 0 || n_sources == fine->n_blocks) return TVD_OK;
   if (!d_nbr || !d_fine_interior || !d_coarse_old || !d_cnbr || !d_corigin ||
       (w != 0.0 && !d_coarse_new))

@@ -405,33 +405,50 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
 // coarse level is taken at old + w (new - old) (w = 0: the old state
 // alone), the same expression as tvd_lerp.
 //
-// One workgroup per (fine block, ghost region).  The coarse cells under the
-// region's ghost slab (3 fine cells thick) and the ring of cells around them
+// One workgroup per (fine block, ghost region) pair; pairs with a real
+// sibling return at once.  (A grid-stride loop of 8 workgroups per CU over
+// the pairs ran 1.4 times longer: each wave then waits, at its first
+// barrier of a pair, for the stores of the previous one.)  For each
+// stand-in region, the coarse cells under the region's ghost slab (3 fine cells thick) and the ring of cells around them
 // that their stencils reach are staged in LDS first, each read once (at
-// old + w (new - old)) with all of a thread's reads in flight together; then
-// one thread per coarse cell under the slab takes the three limited slopes
-// from LDS and writes those of the cell's eight children that lie in the
-// slab, each as u + dx s_x + dy s_y + dz s_z in that order, the same
+// old + w (new - old)) with all of a thread's reads in flight together; one
+// thread per coarse cell under the slab then takes the cell's three limited
+// slopes, which replace the staged values in LDS; last, one thread per fine
+// cell of the slab (x fastest, so that neighbouring lanes write neighbouring
+// addresses) writes u + dx s_x + dy s_y + dz s_z in that order, the same
 // operations as for a single ghost cell in fill_interp.  Cells shared by the
 // slabs of several fine blocks get the same value from each.
 constexpr int kCfNT = 128;     // coarse cells under a face slab of a 16^3 block: 2 x 8 x 8
 constexpr int kCfStage = 400;  // staged coarse cells of that slab: 4 x 10 x 10
 constexpr int kCfPer = (kCfStage + kCfNT - 1) / kCfNT;
+static_assert(4 * kCfNT >= kCfStage, "the slopes reuse the staging buffer");
 
+// floor(i / d) for 0 <= i < 4096 and 1 <= d <= 26 by a 24-bit multiply and a
+// shift, m = ceil(2^16 / d) (exact over that range, checked exhaustively).
+struct SmallDiv {
+  unsigned m;
+  __device__ explicit SmallDiv(int d) : m((65536u + (unsigned)d - 1u) / (unsigned)d) {}
+  __device__ int operator()(int i) const { return (int)(__umul24((unsigned)i, m) >> 16); }
+};
+
+// One (fine block b, ghost region) pair of k_fill_coarse_fine; every return
+// is uniform over the workgroup.
 template <typename T>
-__global__ __launch_bounds__(kCfNT) void k_fill_coarse_fine(
-    KParams kp, const int32_t* nbr, const T* cold, const T* cnew, T w, const int64_t* coff,
-    int ncoarse, int cshift, const int32_t* cnbr, const int32_t* corigin) {
-  __shared__ T sv[kNV][kCfStage];
-  __shared__ int sok[kCfStage];
-  __shared__ int32_t scb[27];
-  const int b = blockIdx.x / 26, rr = blockIdx.x % 26;
+__device__ __forceinline__ void fill_cf_pair(const KParams& kp, int b, int rr, int t,
+                                             const int32_t* nbr, const T* cold, const T* cnew,
+                                             T w, const int64_t* coff, int ncoarse, int cshift,
+                                             const int32_t* cnbr, const int32_t* corigin,
+                                             T* sbuf, int* sgood, int* sok, int32_t* scb) {
   const int r = rr < 13 ? rr : rr + 1;
   const int ra[3] = {r % 3 - 1, (r / 3) % 3 - 1, r / 9 - 1};
+  // the neighbour entry, b's corner and b's coarse table are read together,
+  // before the pair is known to need them: one wait instead of three
   const int v = nbr[27 * (int64_t)b + r];
+  int co[3] = {corigin[3 * b + 0], corigin[3 * b + 1], corigin[3 * b + 2]};
+  int cbt = cnbr[27 * (int64_t)b + (t < 27 ? t : 0)];
+  asm volatile("" : "+v"(cbt), "+s"(co[0]), "+s"(co[1]), "+s"(co[2]));
   if (v < kp.nblocks) return;  // a real sibling (uniform over the workgroup)
   const int n = kp.edge, h = n / 2;
-  const int co[3] = {corigin[3 * b + 0], corigin[3 * b + 1], corigin[3 * b + 2]};
   // per axis: the slab's ghosted fine coordinates [lo, hi) and the coarse
   // cells [c0, c0 + cnt) under it
   int lo[3], hi[3], c0[3], cnt[3];
@@ -442,9 +459,10 @@ __global__ __launch_bounds__(kCfNT) void k_fill_coarse_fine(
     c0[a] = ra[a] < 0 ? co[a] - 2 : (ra[a] == 0 ? co[a] : co[a] + h);
     cnt[a] = ra[a] == 0 ? h : 2;
   }
-  const int t = threadIdx.x;
   const bool mine = t < cnt[0] * cnt[1] * cnt[2];
-  const int l[3] = {t % cnt[0], (t / cnt[0]) % cnt[1], t / (cnt[0] * cnt[1])};
+  // cnt is 2 or h (4 or 8): powers of two
+  const int lg0 = __builtin_ctz(cnt[0]), lg1 = __builtin_ctz(cnt[1]);
+  const int l[3] = {t & (cnt[0] - 1), (t >> lg0) & (cnt[1] - 1), t >> (lg0 + lg1)};
   int kids = 0;  // children of this thread's coarse cell inside the slab
 #pragma unroll
   for (int pz = 0; pz < 2; ++pz)
@@ -462,19 +480,21 @@ __global__ __launch_bounds__(kCfNT) void k_fill_coarse_fine(
     if (mine) atomicAdd(&kp.counters[1], (unsigned long long)kids);
     return;
   }
-  if (t < 27) scb[t] = cnbr[27 * (int64_t)b + t];
+  if (t < 27) scb[t] = cbt;
   __syncthreads();
   // stage the box [c0 - 1, c0 + cnt + 1) per axis
   const int s[3] = {cnt[0] + 2, cnt[1] + 2, cnt[2] + 2};
   const int ns = s[0] * s[1] * s[2];
+  const SmallDiv div0(s[0]), div1(s[1]);
   const CoarseNbhd<T> ca{cold, coff, scb, ncoarse, cshift}, cb{cnew, coff, scb, ncoarse, cshift};
   T a[kCfPer][kNV], e[kCfPer][kNV];
   bool okj[kCfPer];
 #pragma unroll
   for (int j = 0; j < kCfPer; ++j) {
     const int i = min(t + j * kCfNT, ns - 1);  // past the box: a repeat of its last cell
-    const int ix = c0[0] - 1 + i % s[0], iy = c0[1] - 1 + (i / s[0]) % s[1],
-              iz = c0[2] - 1 + i / (s[0] * s[1]);
+    const int q0 = div0(i), q1 = div1(q0);
+    const int ix = c0[0] - 1 + (i - q0 * s[0]), iy = c0[1] - 1 + (q0 - q1 * s[1]),
+              iz = c0[2] - 1 + q1;
     okj[j] = ca.get(ix, iy, iz, a[j]);
     if (w != T(0)) cb.get(ix, iy, iz, e[j]);
   }
@@ -483,54 +503,82 @@ __global__ __launch_bounds__(kCfNT) void k_fill_coarse_fine(
     const int i = t + j * kCfNT;
     if (i >= ns) continue;
 #pragma unroll
-    for (int k = 0; k < kNV; ++k) sv[k][i] = w != T(0) ? a[j][k] + w * (e[j][k] - a[j][k]) : a[j][k];
+    for (int k = 0; k < kNV; ++k) sbuf[k * kCfStage + i] = w != T(0) ? a[j][k] + w * (e[j][k] - a[j][k]) : a[j][k];
     sok[i] = okj[j];
   }
   __syncthreads();
-  if (!mine) return;
-  const int sc = (l[0] + 1) + s[0] * ((l[1] + 1) + s[1] * (l[2] + 1));
-  const int sx1 = 1, sy1 = s[0], sz1 = s[0] * s[1];
-  const bool ok = sok[sc] & sok[sc + sx1] & sok[sc - sx1] & sok[sc + sy1] & sok[sc - sy1] &
-                  sok[sc + sz1] & sok[sc - sz1];
-  if (!ok) {
-    atomicAdd(&kp.counters[1], (unsigned long long)kids);
-    return;
-  }
   T u[kNV], sx[kNV], sy[kNV], sz[kNV];
+  if (mine) {
+    const int sc = (l[0] + 1) + s[0] * ((l[1] + 1) + s[1] * (l[2] + 1));
+    const int sx1 = 1, sy1 = s[0], sz1 = s[0] * s[1];
+    const bool ok = sok[sc] & sok[sc + sx1] & sok[sc - sx1] & sok[sc + sy1] & sok[sc - sy1] &
+                    sok[sc + sz1] & sok[sc - sz1];
+    sgood[t] = ok;
+    if (!ok) atomicAdd(&kp.counters[1], (unsigned long long)kids);
+    const T* sv = sbuf;
 #pragma unroll
-  for (int k = 0; k < kNV; ++k) {
-    u[k] = sv[k][sc];
-    sx[k] = minmod(sv[k][sc + sx1] - u[k], u[k] - sv[k][sc - sx1]);
-    sy[k] = minmod(sv[k][sc + sy1] - u[k], u[k] - sv[k][sc - sy1]);
-    sz[k] = minmod(sv[k][sc + sz1] - u[k], u[k] - sv[k][sc - sz1]);
+    for (int k = 0; k < kNV; ++k) {
+      const T* c = sv + k * kCfStage + sc;
+      u[k] = c[0];
+      sx[k] = minmod(c[sx1] - u[k], u[k] - c[-sx1]);
+      sy[k] = minmod(c[sy1] - u[k], u[k] - c[-sy1]);
+      sz[k] = minmod(c[sz1] - u[k], u[k] - c[-sz1]);
+    }
   }
+  __syncthreads();
+  if (mine) {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) {
+      sbuf[(0 * kNV + k) * kCfNT + t] = u[k];
+      sbuf[(1 * kNV + k) * kCfNT + t] = sx[k];
+      sbuf[(2 * kNV + k) * kCfNT + t] = sy[k];
+      sbuf[(3 * kNV + k) * kCfNT + t] = sz[k];
+    }
+  }
+  __syncthreads();
+  const int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+  const int nf = ex * ey * ez;
   const int64_t n3 = (int64_t)n * n * n;
   T* d = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[v] : (int64_t)v * kNV * n3);
   const T q = T(0.25);
+  const SmallDiv divx(ex), divy(ey);
+  for (int f = t; f < nf; f += kCfNT) {
+    const int q0 = divx(f), q1 = divy(q0);
+    const int g[3] = {lo[0] + (f - q0 * ex), lo[1] + (q0 - q1 * ey), lo[2] + q1};
+    // fine index relative to the central coarse block's corner, its coarse
+    // cell (floor) and that cell's place under the slab
+    const int fi[3] = {2 * co[0] + g[0] - kG, 2 * co[1] + g[1] - kG, 2 * co[2] + g[2] - kG};
+    const int lc = ((fi[0] >> 1) - c0[0]) +
+                   cnt[0] * (((fi[1] >> 1) - c0[1]) + cnt[1] * ((fi[2] >> 1) - c0[2]));
+    if (!sgood[lc]) continue;
+    const T dx = (fi[0] & 1) ? q : -q, dy = (fi[1] & 1) ? q : -q, dz = (fi[2] & 1) ? q : -q;
+    const int64_t o = (g[0] - kG - ra[0] * n) + n * ((g[1] - kG - ra[1] * n) +
+                                                       (int64_t)n * (g[2] - kG - ra[2] * n));
 #pragma unroll
-  for (int pz = 0; pz < 2; ++pz)
-#pragma unroll
-    for (int py = 0; py < 2; ++py)
-#pragma unroll
-      for (int px = 0; px < 2; ++px) {
-        const int g[3] = {2 * (c0[0] + l[0]) + px - 2 * co[0] + kG,
-                          2 * (c0[1] + l[1]) + py - 2 * co[1] + kG,
-                          2 * (c0[2] + l[2]) + pz - 2 * co[2] + kG};
-        if (!(g[0] >= lo[0] && g[0] < hi[0] && g[1] >= lo[1] && g[1] < hi[1] && g[2] >= lo[2] &&
-              g[2] < hi[2]))
-          continue;
-        const T dx = px ? q : -q, dy = py ? q : -q, dz = pz ? q : -q;
-        const int64_t o = (g[0] - kG - ra[0] * n) + n * ((g[1] - kG - ra[1] * n) +
-                                                           (int64_t)n * (g[2] - kG - ra[2] * n));
-#pragma unroll
-        for (int k = 0; k < kNV; ++k) {
-          T val = u[k];
-          val = val + dx * sx[k];
-          val = val + dy * sy[k];
-          val = val + dz * sz[k];
-          d[(int64_t)k * n3 + o] = val;
-        }
-      }
+    for (int k = 0; k < kNV; ++k) {
+      T val = sbuf[(0 * kNV + k) * kCfNT + lc];
+      val = val + dx * sbuf[(1 * kNV + k) * kCfNT + lc];
+      val = val + dy * sbuf[(2 * kNV + k) * kCfNT + lc];
+      val = val + dz * sbuf[(3 * kNV + k) * kCfNT + lc];
+      d[(int64_t)k * n3 + o] = val;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCfNT) void k_fill_coarse_fine(
+    KParams kp, const int32_t* nbr, const T* cold, const T* cnew, T w, const int64_t* coff,
+    int ncoarse, int cshift, const int32_t* cnbr, const int32_t* corigin) {
+  // staged values [kNV][kCfStage], then slopes [4][kNV][kCfNT] (u, s_x, s_y, s_z)
+  __shared__ T sbuf[4 * kNV * kCfNT];
+  __shared__ int sgood[kCfNT];
+  __shared__ int sok[kCfStage];
+  __shared__ int32_t scb[27];
+  // contiguous ranges of pairs per XCD: a block's regions, and neighbouring
+  // blocks, whose coarse boxes overlap, meet in the same L2
+  const int i = xcd_block(blockIdx.x, gridDim.x);
+  fill_cf_pair<T>(kp, i / 26, i % 26, threadIdx.x, nbr, cold, cnew, w, coff, ncoarse, cshift, cnbr,
+                  corigin, sbuf, sgood, sok, scb);
 }
 
 // ---------------------------------------------------------------------------
