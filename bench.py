@@ -275,7 +275,8 @@ def run_uneven(ctx, graph_steps=50):
     mixed-edge launch), then `graph_steps` steps are captured as one HIP graph
     and replayed; the mixed layout is also timed with one launch per edge."""
     import torch
-    from paper_0907_3390_amd import tvd, tuning, workloads as wl
+    from paper_0907_3390_amd import layout, tvd, tuning, workloads as wl
+    from paper_0907_3390_amd.driver import DeviceBlocks
     boxes = wl.sound_wave_boxes(seed=4)
     grids = [g.astype(np.float32).astype(np.float64) for g in boxes.grids]
     cells = sum(g.shape[1] ** 3 for g in grids)
@@ -310,6 +311,29 @@ def run_uneven(ctx, graph_steps=50):
         log(f"bench: uneven batch {name}: {res[name]['value'] / 1e9:.2f} G cell-updates/s")
         del dev
         torch.cuda.empty_cache()
+    # the 571 boxes of 32^3 alone: each box one edge-32 block, streamed along
+    # itself, against the same boxes as 16^3 groups (per-block gathering)
+    big = [i for i, g in enumerate(grids) if g.shape[1] == 32]
+    bg, bd = [grids[i] for i in big], [boxes.dh[i] for i in big]
+    bcells = len(big) * 32 ** 3
+    sub = {"boxes": len(big), "cells": bcells}
+    for name, e, stream in (("edge32_streamed", 32, True), ("groups16_per_block", 16, False)):
+        bs = layout.boxes_blockset([32] * len(bg), lambda L, e=e: e, bd)
+        dev = DeviceBlocks(ctx, bs, dtype=torch.float32, gather=True, stream=stream,
+                           gamma=GAMMA, cfl=CFL)
+        dev.upload(layout.boxes_to_blocks(bg, lambda L, e=e: e))
+        if not stream:
+            dev.dt.fill_(CFL * float(np.min(bs.dh)) / 4.0)
+            ctx.tvd_autotune(dev.batch, dev.nbr, dev.interior, dev.spare, GAMMA, reps=2)
+        dev.run(2)
+        ms = tuning.graph_ms_per_step(dev, pairs=10)
+        sub[name] = {"value": bcells / (ms * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms,
+                     "blocks": bs.n_blocks}
+        log(f"bench: uneven batch, 32^3 boxes {name}: {sub[name]['value'] / 1e9:.2f} G "
+            f"cell-updates/s ({ms:.3f} ms per step)")
+        del dev
+        torch.cuda.empty_cache()
+    res["boxes_32cube"] = sub
     st, fl, bad = ctx.tvd_read_flags()
     res["health"] = {"floored": fl, "nonphysical": bad}
     return res
@@ -1018,7 +1042,7 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the ghost fill, multi-level, closing, nested, Poisson, "
                          "gravity and uneven-batch measurements")
-    ap.add_argument("--only", choices=["amr_fill", "nested"], default=None,
+    ap.add_argument("--only", choices=["amr_fill", "nested", "uneven"], default=None,
                     help="run only this measurement and print its record (profiling)")
     args = ap.parse_args()
     if args.only:
@@ -1030,6 +1054,8 @@ def main():
             ml = wl.multilevel()
             rec = {"nested_subcycled_step": run_nested(ctx, ml, n=16, gather=True),
                    "ghosted_copies": run_nested(ctx, ml, n=16)}
+        elif args.only == "uneven":
+            rec = {"uneven_batch": run_uneven(ctx)}
         else:
             rec = {"amr_ghost_fill": run_amr_fill(ctx)}
         ctx.close()
