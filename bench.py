@@ -59,8 +59,13 @@ HBM_PEAK_GBS = 8000.0
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_fp32_edge16_512blast_traffic.txt")
-KERNEL_SOURCES = ["paper_0907_3390_amd/csrc/tvd_stream.hpp", "paper_0907_3390_amd/csrc/tvd_block.hpp",
-                  "paper_0907_3390_amd/csrc/tvd_device.hpp"]
+# the sources the headline kernel (k_stream<float, 16, ...>) is compiled from
+KERNEL_SOURCES = ["paper_0907_3390_amd/csrc/tvd_k_stream_f32.hip",
+                  "paper_0907_3390_amd/csrc/tvd_stream.hpp",
+                  "paper_0907_3390_amd/csrc/tvd_stream_params.hpp",
+                  "paper_0907_3390_amd/csrc/tvd_block.hpp",
+                  "paper_0907_3390_amd/csrc/tvd_device.hpp",
+                  "paper_0907_3390_amd/csrc/tvd_internal.hpp"]
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 error; HBM GB/s % of peak"
 
 
