@@ -720,36 +720,39 @@ def run_amr_fill(ctx, reps=20):
                        "(fine origin 128 along each axis), FP32"}
     c_in = torch.from_numpy(layout.grid_to_blocks(coarse_grid, 8)).cuda().reshape(-1)
     for n in (8, 16):
-        coarse_bs, fine_bs, cnbr, corigin = layout.two_level(Nc, origin, shape, n)
-        m = n + 6
-        nb = fine_bs.n_blocks
-        f_in = torch.from_numpy(layout.grid_to_blocks(fine, n)).cuda().reshape(-1)
-        f_gh = torch.empty(nb * 5 * m ** 3, dtype=torch.float32, device="cuda")
-        nbr = torch.from_numpy(fine_bs.nbr).cuda()
-        cn = torch.from_numpy(cnbr).cuda()
-        co = torch.from_numpy(corigin).cuda()
-        fb = tvd.Batch(tvd.TVD_F32, nb, n, dt=1e-3, dh=0.5 / Nc)
-        cb = tvd.Batch(tvd.TVD_F32, coarse_bs.n_blocks, 8, dt=1e-3, dh=1.0 / Nc)
-        ctx.tvd_fill_ghosts_amr(fb, nbr, f_in, f_gh, cb, c_in, cn, co)
-        a = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
+        for curve in ("morton", "linear"):
+            coarse_bs, fine_bs, cnbr, corigin = layout.two_level(Nc, origin, shape, n, curve=curve)
+            m = n + 6
+            nb = fine_bs.n_blocks
+            f_in = torch.from_numpy(layout.grid_to_blocks(fine, n, fine_bs.perm)).cuda().reshape(-1)
+            f_gh = torch.empty(nb * 5 * m ** 3, dtype=torch.float32, device="cuda")
+            nbr = torch.from_numpy(fine_bs.nbr).cuda()
+            cn = torch.from_numpy(cnbr).cuda()
+            co = torch.from_numpy(corigin).cuda()
+            fb = tvd.Batch(tvd.TVD_F32, nb, n, dt=1e-3, dh=0.5 / Nc)
+            cb = tvd.Batch(tvd.TVD_F32, coarse_bs.n_blocks, 8, dt=1e-3, dh=1.0 / Nc)
             ctx.tvd_fill_ghosts_amr(fb, nbr, f_in, f_gh, cb, c_in, cn, co)
-        e.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(e) / reps
-        # cells interpolated: ghost cells of blocks on the box surface
-        ghost_cells = nb * (m ** 3 - n ** 3)
-        bytes_alg = nb * m ** 3 * 20 + nb * n ** 3 * 20 + (128 + 4) ** 3 * 20
-        res[f"edge{n}"] = {"blocks": nb, "ms": ms, "ghosted_cells_per_s": nb * m ** 3 / (ms * 1e-3),
-                           "ghost_cells": ghost_cells,
-                           "algorithmic_GBs": bytes_alg / (ms * 1e-3) / 1e9,
-                           "hbm_frac": bytes_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        log(f"bench: coarse-fine ghost fill, edge {n}: {ms:.3f} ms, "
-            f"{res[f'edge{n}']['algorithmic_GBs']:.0f} GB/s algorithmic")
-        del f_in, f_gh
-        torch.cuda.empty_cache()
+            a = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                ctx.tvd_fill_ghosts_amr(fb, nbr, f_in, f_gh, cb, c_in, cn, co)
+            e.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(e) / reps
+            # cells interpolated: ghost cells of blocks on the box surface
+            ghost_cells = nb * (m ** 3 - n ** 3)
+            bytes_alg = nb * m ** 3 * 20 + nb * n ** 3 * 20 + (128 + 4) ** 3 * 20
+            key = f"edge{n}" if curve == "morton" else f"edge{n}_linear_numbering"
+            res[key] = {"blocks": nb, "block_order": curve, "ms": ms,
+                        "ghosted_cells_per_s": nb * m ** 3 / (ms * 1e-3),
+                        "ghost_cells": ghost_cells,
+                        "algorithmic_GBs": bytes_alg / (ms * 1e-3) / 1e9,
+                        "hbm_frac": bytes_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"bench: coarse-fine ghost fill, edge {n}, {curve} numbering: {ms:.3f} ms, "
+                f"{res[key]['algorithmic_GBs']:.0f} GB/s algorithmic")
+            del f_in, f_gh
+            torch.cuda.empty_cache()
     st, fl, bad = ctx.tvd_read_flags()
     res["health"] = {"nonphysical": bad}
     return res

@@ -197,6 +197,27 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// floor(i / d) by a 24-bit multiply and a shift, m = ceil(2^K / d), for small
+// numerators and divisors; checked exhaustively: K = 16 is exact for
+// 0 <= i < 4096 and 1 <= d <= 26, K = 19 for 0 <= i < 16384 and 2 <= d <= 32
+// (the product staying below 2^32).
+template <int K>
+struct SmallDiv {
+  unsigned m;
+  __device__ explicit SmallDiv(int d) : m(((1u << K) + (unsigned)d - 1u) / (unsigned)d) {}
+  __device__ int operator()(int i) const { return (int)(__umul24((unsigned)i, m) >> K); }
+};
+
+// (x, y, z) of ghosted cell `cell` of an m^3 block (m = n + 6 <= 22, so
+// cell < 10648); dm divides by m
+__device__ __forceinline__ void ghosted_xyz(int cell, int m, const SmallDiv<19>& dm, int& x,
+                                            int& y, int& z) {
+  const int q = dm(cell), r = dm(q);
+  x = cell - q * m;
+  y = q - r * m;
+  z = r;
+}
+
 // ---------------------------------------------------------------------------
 // sibling ghost fill
 // ---------------------------------------------------------------------------
@@ -206,15 +227,20 @@ constexpr int kFillNT = 256;
 template <typename T>
 __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32_t* nbr,
                                                         int chunks) {
-  const int b = blockIdx.x / chunks;
-  const int chunk = blockIdx.x % chunks;
+  // contiguous ranges of (block, chunk) items per XCD: a block's chunks, and
+  // neighbouring blocks, which read the same sibling interiors, share an L2
+  const int item = xcd_block(blockIdx.x, gridDim.x);
+  const int b = item / chunks;
+  const int chunk = item % chunks;
   const int n = block_edge(kp, b);
   const int m = n + 2 * kG;
   const int m3 = m * m * m;
+  const SmallDiv<19> dm(m);
   const int n3 = n * n * n;
   const int cell = chunk * kFillNT + threadIdx.x;
   if (cell >= m3) return;
-  const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+  int x, y, z;
+  ghosted_xyz(cell, m, dm, x, y, z);
   const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
   const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
   const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
@@ -337,11 +363,15 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
                                                             const int64_t* coff, int ncoarse,
                                                             int cshift, const int32_t* cnbr,
                                                             const int32_t* corigin) {
-  const int b = blockIdx.x / chunks;
-  const int chunk = blockIdx.x % chunks;
+  // contiguous ranges of (block, chunk) items per XCD: a block's chunks, and
+  // neighbouring blocks, which read the same sibling interiors, share an L2
+  const int item = xcd_block(blockIdx.x, gridDim.x);
+  const int b = item / chunks;
+  const int chunk = item % chunks;
   const int n = block_edge(kp, b);
   const int m = n + 2 * kG;
   const int m3 = m * m * m;
+  const SmallDiv<19> dm(m);
   const int n3 = n * n * n;
   T* d = reinterpret_cast<T*>(const_cast<void*>(kp.uin)) +
          (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
@@ -356,7 +386,8 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
     kind[i] = 0;
     sp[i] = own;  // a valid address for the unconditional reads below
     if (cell < m3) {
-      const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+      int x, y, z;
+      ghosted_xyz(cell, m, dm, x, y, z);
       const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
       const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
       const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
@@ -391,7 +422,8 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
   for (int i = 0; i < kFillCPT; ++i) {
     if (kind[i] != 2) continue;
     const int cell = (chunk * kFillCPT + i) * kFillNT + threadIdx.x;
-    const int x = cell % m, y = (cell / m) % m, z = cell / (m * m);
+    int x, y, z;
+    ghosted_xyz(cell, m, dm, x, y, z);
     fill_interp<T>(kp, b, x, y, z, d, m3, cell, cin, coff, ncoarse, cshift, cnbr, corigin);
   }
 }
@@ -422,14 +454,6 @@ constexpr int kCfNT = 128;     // coarse cells under a face slab of a 16^3 block
 constexpr int kCfStage = 400;  // staged coarse cells of that slab: 4 x 10 x 10
 constexpr int kCfPer = (kCfStage + kCfNT - 1) / kCfNT;
 static_assert(4 * kCfNT >= kCfStage, "the slopes reuse the staging buffer");
-
-// floor(i / d) for 0 <= i < 4096 and 1 <= d <= 26 by a 24-bit multiply and a
-// shift, m = ceil(2^16 / d) (exact over that range, checked exhaustively).
-struct SmallDiv {
-  unsigned m;
-  __device__ explicit SmallDiv(int d) : m((65536u + (unsigned)d - 1u) / (unsigned)d) {}
-  __device__ int operator()(int i) const { return (int)(__umul24((unsigned)i, m) >> 16); }
-};
 
 // One (fine block b, ghost region) pair of k_fill_coarse_fine; every return
 // is uniform over the workgroup.
@@ -485,7 +509,7 @@ __device__ __forceinline__ void fill_cf_pair(const KParams& kp, int b, int rr, i
   // stage the box [c0 - 1, c0 + cnt + 1) per axis
   const int s[3] = {cnt[0] + 2, cnt[1] + 2, cnt[2] + 2};
   const int ns = s[0] * s[1] * s[2];
-  const SmallDiv div0(s[0]), div1(s[1]);
+  const SmallDiv<16> div0(s[0]), div1(s[1]);
   const CoarseNbhd<T> ca{cold, coff, scb, ncoarse, cshift}, cb{cnew, coff, scb, ncoarse, cshift};
   T a[kCfPer][kNV], e[kCfPer][kNV];
   bool okj[kCfPer];
@@ -541,7 +565,7 @@ __device__ __forceinline__ void fill_cf_pair(const KParams& kp, int b, int rr, i
   const int64_t n3 = (int64_t)n * n * n;
   T* d = reinterpret_cast<T*>(kp.uout) + (kp.out_off ? kp.out_off[v] : (int64_t)v * kNV * n3);
   const T q = T(0.25);
-  const SmallDiv divx(ex), divy(ey);
+  const SmallDiv<16> divx(ex), divy(ey);
   for (int f = t; f < nf; f += kCfNT) {
     const int q0 = divx(f), q1 = divy(q0);
     const int g[3] = {lo[0] + (f - q0 * ex), lo[1] + (q0 - q1 * ey), lo[2] + q1};

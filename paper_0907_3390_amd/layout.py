@@ -174,7 +174,7 @@ def blocks_to_boxes(blocks, box_edges, block_edge_for) -> list:
     return out
 
 
-def two_level(Nc: int, origin, shape, n: int):
+def two_level(Nc: int, origin, shape, n: int, curve: str = "linear"):
     """A coarse-fine configuration: the periodic coarse level of Nc^3 cells as
     8^3 patches (x fastest), and a box of fine cells (the level one finer, 2 Nc
     cells per axis) of shape (Lz, Ly, Lx) at fine-cell origin (oz, oy, ox), cut
@@ -185,7 +185,9 @@ def two_level(Nc: int, origin, shape, n: int):
     Returns (coarse BlockSet, fine BlockSet whose sibling table is -1 outside
     the box, cnbr [B, 27] coarse patches around each fine block's parent,
     corigin [B, 3] the fine block's corner in coarse cells relative to its
-    parent's corner, x first)."""
+    parent's corner, x first).  curve "morton" numbers the fine blocks along
+    the Morton curve instead (fine.perm then maps block k to the x-fastest
+    block perm[k] of the box, for grid_to_blocks)."""
     Lz, Ly, Lx = shape
     oz, oy, ox = origin
     if any(v % n for v in (Lz, Ly, Lx, oz, oy, ox)) or Nc % 8:
@@ -214,7 +216,17 @@ def two_level(Nc: int, origin, shape, n: int):
                     px, py, pz = ((parent[0] + rx) % npc, (parent[1] + ry) % npc,
                                   (parent[2] + rz) % npc)
                     cnbr[b, r] = px + npc * (py + npc * pz)
+    perm = None
+    if curve == "morton":
+        perm = morton_perm(nbx, nby, nbz)
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(nb)
+        nbr = np.where(nbr[perm] >= 0, inv[np.maximum(nbr[perm], 0)], -1).astype(np.int32)
+        cnbr, corigin = cnbr[perm], corigin[perm]
+    elif curve != "linear":
+        raise ValueError(f"unknown curve {curve!r}")
     fine = BlockSet(np.full(nb, n), np.full(nb, 0.5 / Nc), nbr)
+    fine.perm = perm
     return coarse, fine, cnbr, corigin
 
 

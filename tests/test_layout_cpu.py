@@ -294,3 +294,26 @@ def test_nested_levels_as_patch_groups():
                         res.add((int(d), int(s), org[int(d)] + 8 * int(qc), org[hi] + a, org[lo] + b2))
             return res
         assert absolute(P, tp[lev][1], 8) == absolute(G, fr, 16)
+
+
+def test_two_level_morton_numbering():
+    """Morton numbering of the fine box renumbers the blocks only: the sibling
+    table, the coarse tables and the cut interiors are the linear ones
+    permuted, and the blocks are those of the box in that order."""
+    import numpy as np
+    from paper_0907_3390_amd import layout
+    for n in (8, 16):
+        _, f1, cn1, co1 = layout.two_level(64, (32, 32, 32), (64, 64, 64), n)
+        _, f2, cn2, co2 = layout.two_level(64, (32, 32, 32), (64, 64, 64), n, curve="morton")
+        p = f2.perm
+        inv = np.empty_like(p)
+        inv[p] = np.arange(len(p))
+        want = np.where(f1.nbr[p] >= 0, inv[np.maximum(f1.nbr[p], 0)], -1)
+        assert np.array_equal(f2.nbr, want)
+        assert np.array_equal(cn2, cn1[p]) and np.array_equal(co2, co1[p])
+        assert sorted(p.tolist()) == list(range(f1.n_blocks))
+        g = np.arange(5 * 64 ** 3, dtype=np.float64).reshape(5, 64, 64, 64)
+        assert np.array_equal(layout.grid_to_blocks(g, n, p), layout.grid_to_blocks(g, n)[p])
+        # consecutive Morton blocks are face neighbours more often than not
+        adj = sum(int(k + 1 in f2.nbr[k]) for k in range(f2.n_blocks - 1))
+        assert adj > 0.5 * (f2.n_blocks - 1)
