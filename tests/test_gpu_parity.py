@@ -671,6 +671,23 @@ def test_full_size_256cube_bench_config_fp32(ctx, stream):
     _full_size_sampled(ctx, g, 16, torch.float32, 2, dt, picks, bounds=FP32_ROUGH, stream=stream)
 
 
+@pytest.mark.parametrize("n,stream", [(16, True), (8, False)])
+def test_full_size_256cube_fp64(ctx, n, stream):
+    """The 256^3 rough lognormal workload at full size in FP64: as 4096
+    groups of 16^3 by the streamed advance, or as 32768 patches of 8^3 by the
+    per-block gathering kernel (Morton-numbered): two steps (xyz, zyx), 24
+    sampled blocks against the oracle's dependency-cone result, relative L1
+    and Linf <= 1e-12 per variable, and the fused FP64 sums conserved to
+    1e-13 of each variable's scale."""
+    note(f"full size 256^3 lognormal fp64, edge {n}, stream={stream}")
+    g = wl.lognormal(256, seed=2024)
+    S = oracle.max_signal_speed(g, GAMMA)
+    dt = 0.5 / 256 / S
+    nb = (256 // n) ** 3
+    picks = sorted(set(int(x) for x in wl.rng(3).integers(0, nb, size=24)) | {0, nb - 1})
+    _full_size_sampled(ctx, g, n, torch.float64, 2, dt, picks, bounds=FP64, stream=stream)
+
+
 @pytest.mark.parametrize("stream", [False, True])
 def test_full_size_512cube_sedov_fp32(ctx, stream):
     """The headline workload at full size: 512^3 = 262144 patches of 8^3 run
