@@ -224,9 +224,37 @@ __device__ __forceinline__ void ghosted_xyz(int cell, int m, const SmallDiv<19>&
 
 constexpr int kFillNT = 256;
 
+// The 27 region sources of block b, resolved once per workgroup by threads
+// 0..26 into LDS: kind 1 (sibling copy, base = the source's interior), 2 (no
+// sibling: base = own interior) or 0 (a source out of range or of another
+// edge: its cells are counted as non-physical).  The caller synchronises.
+template <typename T>
+__device__ __forceinline__ void resolve_regions(const KParams& kp, const int32_t* nbr, int b,
+                                                int n, const T* own, const T** s_base,
+                                                int* s_kind) {
+  const int r = threadIdx.x;
+  if (r >= 27) return;
+  const int src = nbr[27 * (int64_t)b + r];
+  int kind = 2;
+  const T* base = own;
+  if (src >= 0) {
+    if (src >= kp.nblocks || block_edge(kp, src) != n) {
+      kind = 0;
+    } else {
+      kind = 1;
+      base = reinterpret_cast<const T*>(kp.uout) +
+             (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n * n * n);
+    }
+  }
+  s_kind[r] = kind;
+  s_base[r] = base;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32_t* nbr,
                                                         int chunks) {
+  __shared__ const T* s_base[27];
+  __shared__ int s_kind[27];
   // contiguous ranges of (block, chunk) items per XCD: a block's chunks, and
   // neighbouring blocks, which read the same sibling interiors, share an L2
   const int item = xcd_block(blockIdx.x, gridDim.x);
@@ -237,6 +265,10 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32
   const int m3 = m * m * m;
   const SmallDiv<19> dm(m);
   const int n3 = n * n * n;
+  const T* own = reinterpret_cast<const T*>(kp.uout) +
+                 (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * n3);
+  resolve_regions<T>(kp, nbr, b, n, own, s_base, s_kind);
+  __syncthreads();
   const int cell = chunk * kFillNT + threadIdx.x;
   if (cell >= m3) return;
   int x, y, z;
@@ -244,20 +276,19 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts(KParams kp, const int32
   const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
   const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
   const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
-  const int src = nbr[27 * b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
-  if (src < 0) return;
-  if (src >= kp.nblocks || block_edge(kp, src) != n) {
+  const int r = (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1);
+  const int kind = s_kind[r];
+  if (kind == 2) return;  // no sibling: left to the caller
+  if (kind == 0) {
     atomicAdd(&kp.counters[1], 1ull);
     return;
   }
   const int sx = x - kG - rx * n, sy = y - kG - ry * n, sz = z - kG - rz * n;
-  const int so = sx + n * (sy + n * sz);
-  const T* s = reinterpret_cast<const T*>(kp.uout) +
-               (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n3);
+  const T* sp = s_base[r] + (sx + n * (sy + n * sz));
   T* d = reinterpret_cast<T*>(const_cast<void*>(kp.uin)) +
          (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
 #pragma unroll
-  for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = s[(int64_t)k * n3 + so];
+  for (int k = 0; k < kNV; ++k) d[(int64_t)k * m3 + cell] = sp[(int64_t)k * n3];
 }
 
 // ---------------------------------------------------------------------------
@@ -363,6 +394,8 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
                                                             const int64_t* coff, int ncoarse,
                                                             int cshift, const int32_t* cnbr,
                                                             const int32_t* corigin) {
+  __shared__ const T* s_base[27];
+  __shared__ int s_kind[27];
   // contiguous ranges of (block, chunk) items per XCD: a block's chunks, and
   // neighbouring blocks, which read the same sibling interiors, share an L2
   const int item = xcd_block(blockIdx.x, gridDim.x);
@@ -377,6 +410,8 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
          (kp.in_off ? kp.in_off[b] : (int64_t)b * kNV * m3);
   const T* own = reinterpret_cast<const T*>(kp.uout) +
                  (kp.out_off ? kp.out_off[b] : (int64_t)b * kNV * n3);
+  resolve_regions<T>(kp, nbr, b, n, own, s_base, s_kind);
+  __syncthreads();
   // 0: no cell, 1: sibling copy from sp[i], 2: interpolated
   int kind[kFillCPT];
   const T* sp[kFillCPT];
@@ -391,17 +426,13 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
       const int rx = x < kG ? -1 : (x >= n + kG ? 1 : 0);
       const int ry = y < kG ? -1 : (y >= n + kG ? 1 : 0);
       const int rz = z < kG ? -1 : (z >= n + kG ? 1 : 0);
-      const int src = nbr[27 * b + (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1)];
-      if (src < 0) {
-        kind[i] = 2;
-      } else if (src >= kp.nblocks || block_edge(kp, src) != n) {
+      const int r = (rx + 1) + 3 * (ry + 1) + 9 * (rz + 1);
+      kind[i] = s_kind[r];
+      if (kind[i] == 0) {
         atomicAdd(&kp.counters[1], 1ull);
-      } else {
+      } else if (kind[i] == 1) {
         const int sx = x - kG - rx * n, sy = y - kG - ry * n, sz = z - kG - rz * n;
-        sp[i] = reinterpret_cast<const T*>(kp.uout) +
-                (kp.out_off ? kp.out_off[src] : (int64_t)src * kNV * n3) +
-                (sx + n * (sy + n * sz));
-        kind[i] = 1;
+        sp[i] = s_base[r] + (sx + n * (sy + n * sz));
       }
     }
   }
