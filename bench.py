@@ -1050,7 +1050,7 @@ def main():
     ap.add_argument("--extras", action="store_true",
                     help="also run the ghost fill, multi-level, closing, nested, Poisson, "
                          "gravity and uneven-batch measurements")
-    ap.add_argument("--only", choices=["amr_fill", "nested", "uneven"], default=None,
+    ap.add_argument("--only", choices=["amr_fill", "nested", "uneven", "gravity"], default=None,
                     help="run only this measurement and print its record (profiling)")
     args = ap.parse_args()
     if args.only:
@@ -1064,6 +1064,8 @@ def main():
                    "ghosted_copies": run_nested(ctx, ml, n=16)}
         elif args.only == "uneven":
             rec = {"uneven_batch": run_uneven(ctx)}
+        elif args.only == "gravity":
+            rec = {"gravity_operator": run_gravity(ctx, make_ic().astype(np.float32))}
         else:
             rec = {"amr_ghost_fill": run_amr_fill(ctx)}
         ctx.close()
