@@ -472,15 +472,16 @@ __global__ __launch_bounds__(kFillNT) void k_fill_ghosts_amr(KParams kp, const i
 // sibling return at once.  (A grid-stride loop of 8 workgroups per CU over
 // the pairs ran 1.4 times longer: each wave then waits, at its first
 // barrier of a pair, for the stores of the previous one.)  For each
-// stand-in region, the coarse cells under the region's ghost slab (3 fine cells thick) and the ring of cells around them
-// that their stencils reach are staged in LDS first, each read once (at
-// old + w (new - old)) with all of a thread's reads in flight together; one
-// thread per coarse cell under the slab then takes the cell's three limited
-// slopes, which replace the staged values in LDS; last, one thread per fine
-// cell of the slab (x fastest, so that neighbouring lanes write neighbouring
-// addresses) writes u + dx s_x + dy s_y + dz s_z in that order, the same
-// operations as for a single ghost cell in fill_interp.  Cells shared by the
-// slabs of several fine blocks get the same value from each.
+// stand-in region, the coarse cells under the region's ghost slab (3 fine
+// cells thick) and the ring of cells around them that their stencils reach
+// are staged in LDS first, each read once (at old + w (new - old)) with all
+// of a thread's reads in flight together; one thread per coarse cell under
+// the slab then takes the cell's three limited slopes, which replace the
+// staged values in LDS; last, one thread per fine cell of the slab (x
+// fastest, so that neighbouring lanes write neighbouring addresses) writes
+// u + dx s_x + dy s_y + dz s_z in that order, the same operations as for a
+// single ghost cell in fill_interp.  Cells shared by the slabs of several
+// fine blocks get the same value from each.
 constexpr int kCfNT = 128;     // coarse cells under a face slab of a 16^3 block: 2 x 8 x 8
 constexpr int kCfStage = 400;  // staged coarse cells of that slab: 4 x 10 x 10
 constexpr int kCfPer = (kCfStage + kCfNT - 1) / kCfNT;
