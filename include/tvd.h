@@ -530,6 +530,31 @@ int tvd_patch_advance_flux_gather(tvd_ctx *ctx, const tvd_batch *batch, const in
                                   void *stream);
 
 /*
+ * tvd_patch_advance_flux_gather organised as tvd_patch_advance_stream
+ * (chains of blocks along the axis swept last, the third sweep carried
+ * along each chain in registers): the same state and the same flux records
+ * bit for bit (Sec. 3.1, step 8: the fluxes across patch boundaries).  Each
+ * chain block records the fluxes through its own planes at multiples of 8
+ * cells, a plane between two chain blocks in both blocks' records, as the
+ * per-block advance does.
+ *   batch    TVD_F32, dense blocks of uniform edge 16 (else
+ *            TVD_ERR_UNSUPPORTED); d_u_in holds n_sources blocks (real ones
+ *            first, then source-only stand-ins), d_u_out n_blocks.
+ *   chains   as for tvd_patch_advance_stream; every neighbour of a chain
+ *            block must be a block below n_sources, of edge 16.  Blocks
+ *            that no valid chain covers are neither advanced nor recorded.
+ *   d_flux, d_flux_off, flux_weight, accumulate  as for
+ *            tvd_patch_advance_flux; d_flux must not overlap the states.
+ * No fused diagnostics.  Asynchronous on stream; capture-safe.
+ */
+int tvd_patch_advance_stream_flux(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
+                                  int32_t n_sources, const tvd_chains *chains,
+                                  const void *d_u_in, void *d_u_out, void *d_flux,
+                                  const int64_t *d_flux_off, double flux_weight,
+                                  int32_t accumulate, int32_t sweep_order, double gamma,
+                                  double p_floor, void *stream);
+
+/*
  * d_out[i] = d_a[i] + w (d_b[i] - d_a[i]), i < n, in the dtype (w rounded
  * to it): linear interpolation in time between two states of a level, e.g.
  * the coarse level half-way through its step for the ghost zones of a fine

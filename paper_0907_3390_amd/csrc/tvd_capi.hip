@@ -463,11 +463,20 @@ namespace {
 // workspace) and tvd_patch_advance_stream_noalloc (partials in the static
 // scratch array): ws_smax [cap] and ws_sums [10 * cap] hold the per-tile
 // partials of the fused signal speed and sums.
+// Flux records of the streamed advance (tvd_patch_advance_stream_flux).
+struct StreamFlux {
+  int32_t n_sources;
+  void* flux;
+  const int64_t* flux_off;
+  double w;
+  bool acc;
+};
+
 int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
                 const tvd_chains* chains, const void* d_u_in, void* d_u_out, int32_t sweep_order,
                 double gamma, double p_floor, int32_t flags, double* d_smax, double* d_sums,
                 void* stream, double* ws_smax, double* ws_sums, int64_t cap,
-                const char* cap_hint) {
+                const char* cap_hint, const StreamFlux* fx = nullptr) {
   if (!ctx) return TVD_ERR_INVALID_ARG;
   int st = check_batch(ctx, batch, true);
   if (st) return st;
@@ -493,10 +502,20 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   const int quads = batch->edge == 32 ? 4 : 1;
   if (!batch->d_in_off && !batch->d_out_off) {
     const size_t n = batch->edge;
-    const size_t len = (size_t)batch->n_blocks * 5 * n * n * n * elem_size(batch->dtype);
+    const size_t blk = 5 * n * n * n * elem_size(batch->dtype);
+    const size_t len_out = (size_t)batch->n_blocks * blk;
+    const size_t len_in = (size_t)(fx ? fx->n_sources : batch->n_blocks) * blk;
     const char* a = (const char*)d_u_in;
     const char* b = (const char*)d_u_out;
-    if (a < b + len && b < a + len) return fail(ctx, TVD_ERR_ALIAS, "input and output overlap");
+    if (a < b + len_out && b < a + len_in)
+      return fail(ctx, TVD_ERR_ALIAS, "input and output overlap");
+    if (fx && !fx->flux_off) {
+      const size_t len_f = (size_t)batch->n_blocks * tvd::flux_record_size(batch->edge) *
+                           elem_size(batch->dtype);
+      const char* f = (const char*)fx->flux;
+      if ((f < a + len_in && a < f + len_f) || (f < b + len_out && b < f + len_f))
+        return fail(ctx, TVD_ERR_ALIAS, "the flux records overlap a state");
+    }
   }
   const int64_t parts = (int64_t)batch->n_blocks * quads;
   if ((d_smax || d_sums) && parts > 0x7fffffff)
@@ -512,6 +531,13 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   kp.diag = (d_smax ? tvd::kDiagSpeed : 0) | (d_sums ? tvd::kDiagSums : 0);
   kp.ws_smax = ws_smax;
   kp.ws_sums = ws_sums;
+  if (fx) {
+    kp.nsrc = fx->n_sources;
+    kp.flux = fx->flux;
+    kp.flux_off = fx->flux_off;
+    kp.flux_w = fx->w;
+    kp.flux_acc = fx->acc ? 1 : 0;
+  }
   tvd::StreamParams sp;
   sp.start = chains->d_start;
   sp.blocks = chains->d_blocks;
@@ -525,9 +551,12 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(ws_sums, 10 * parts, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
   const bool splitb = flags != TVD_STREAM_WHOLE_B;
-  e = batch->dtype == TVD_F32
-          ? tvd::launch_stream_f32(sweep_order, batch->edge, splitb, kp, sp, s)
-          : tvd::launch_stream_f64(sweep_order, batch->edge, splitb, kp, sp, s);
+  if (fx)
+    e = tvd::launch_stream_flux_f32(sweep_order, fx->acc, kp, sp, s);
+  else
+    e = batch->dtype == TVD_F32
+            ? tvd::launch_stream_f32(sweep_order, batch->edge, splitb, kp, sp, s)
+            : tvd::launch_stream_f64(sweep_order, batch->edge, splitb, kp, sp, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "streamed kernel launch");
   if (d_smax) {
     e = tvd::launch_finalize_max(ws_smax, (int)parts, d_smax, s);
@@ -583,6 +612,33 @@ int tvd_patch_advance_stream_noalloc(tvd_ctx* ctx, const tvd_batch* batch, const
   return stream_impl(ctx, batch, d_nbr, chains, d_u_in, d_u_out, sweep_order, gamma, p_floor,
                      flags, d_smax, d_sums, stream, ctx->scratch,
                      ctx->scratch + kScratchParts, kScratchParts, "the static scratch array");
+}
+
+int tvd_patch_advance_stream_flux(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
+                                  int32_t n_sources, const tvd_chains* chains,
+                                  const void* d_u_in, void* d_u_out, void* d_flux,
+                                  const int64_t* d_flux_off, double flux_weight,
+                                  int32_t accumulate, int32_t sweep_order, double gamma,
+                                  double p_floor, void* stream) {
+  if (!ctx) return TVD_ERR_INVALID_ARG;
+  int st = check_batch(ctx, batch, true);
+  if (st) return st;
+  if (batch->dtype != TVD_F32 || batch->d_edge || batch->edge != 16 || batch->d_in_off ||
+      batch->d_out_off)
+    return fail(ctx, TVD_ERR_UNSUPPORTED,
+                "flux records of the streamed advance: FP32, dense blocks of edge 16");
+  if (n_sources < batch->n_blocks)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "n_sources %d < n_blocks %d", n_sources,
+                batch->n_blocks);
+  if (!d_flux) return fail(ctx, TVD_ERR_INVALID_ARG, "d_flux is NULL");
+  if (accumulate != 0 && accumulate != 1)
+    return fail(ctx, TVD_ERR_INVALID_ARG, "accumulate %d (0 or 1)", accumulate);
+  if (!(flux_weight > -1e300 && flux_weight < 1e300))
+    return fail(ctx, TVD_ERR_INVALID_ARG, "flux_weight %g is not finite", flux_weight);
+  const StreamFlux fx{n_sources, d_flux, d_flux_off, flux_weight, accumulate != 0};
+  return stream_impl(ctx, batch, d_nbr, chains, d_u_in, d_u_out, sweep_order, gamma, p_floor,
+                     TVD_KERNEL_AUTO, nullptr, nullptr, stream, ctx->ws_smax, ctx->ws_sums,
+                     ctx->ws_blocks, "the workspace (tvd_reserve)", &fx);
 }
 
 int tvd_pipeline_stage_bytes(int32_t dtype, int32_t edge, const tvd_host_pipeline* pipe,

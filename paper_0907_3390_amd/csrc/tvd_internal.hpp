@@ -125,6 +125,10 @@ hipError_t launch_stream_f32(int order, int edge, bool splitb, const KParams& kp
                              const StreamParams& sp, hipStream_t s);
 hipError_t launch_stream_f64(int order, int edge, bool splitb, const KParams& kp,
                              const StreamParams& sp, hipStream_t s);
+// The streamed advance writing (accumulate false) or adding to the flux
+// records at kp.flux (kp.flux_w, kp.flux_off): FP32, edge 16.
+hipError_t launch_stream_flux_f32(int order, bool accumulate, const KParams& kp,
+                                  const StreamParams& sp, hipStream_t s);
 // Zero n doubles (fill kernel, capture-safe).
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 

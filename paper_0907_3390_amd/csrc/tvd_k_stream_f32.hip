@@ -1,5 +1,6 @@
 // Streamed advance, FP32: the compiled instantiations (block edges 16 and 32,
-// both sweep orders, slabs of 8 planes).
+// both sweep orders, slabs of 8 planes; with flux records, edge 16 and the
+// half-pencil second sweep).
 #include "tvd_stream.hpp"
 
 namespace tvd {
@@ -22,6 +23,19 @@ hipError_t launch_stream_f32(int order, int edge, bool splitb, const KParams& kp
     return order == 0 ? launch_one<32, 0, false>(kp, sp, s) : launch_one<32, 1, false>(kp, sp, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <int ORDER, int FLUX>
+static hipError_t launch_flux(const KParams& kp, const StreamParams& sp, hipStream_t s) {
+  const dim3 grid((unsigned)sp.n_chains * (unsigned)sp.quads), block(kStreamNT);
+  hipLaunchKernelGGL((k_stream<float, 16, ORDER, 8, true, FLUX>), grid, block, 0, s, kp, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_flux_f32(int order, bool accumulate, const KParams& kp,
+                                  const StreamParams& sp, hipStream_t s) {
+  if (accumulate) return order == 0 ? launch_flux<0, 2>(kp, sp, s) : launch_flux<1, 2>(kp, sp, s);
+  return order == 0 ? launch_flux<0, 1>(kp, sp, s) : launch_flux<1, 1>(kp, sp, s);
 }
 
 }  // namespace tvd

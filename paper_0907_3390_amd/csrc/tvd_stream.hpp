@@ -220,7 +220,15 @@ __device__ __forceinline__ void static_for(F&& f) {
 // three ghost planes before the first block (its S- neighbour), the blocks'
 // planes, and three ghost planes after the last block (its S+ neighbour).
 // Consuming plane g finishes cell g - 3 of every column.
-template <typename T, int E, int ORDER, int P, bool SPLITB>
+//
+// FLUX (0 none, 1 write, 2 add): the patch-boundary flux records of
+// tvd_patch_advance_flux, w H through every plane at a multiple of 8 cells
+// of every chain block, for the block's own face cells: the first two
+// sweeps' planes from phases A and B (own rows and columns of the tile, the
+// interface a tile shares with the one before it recorded by that one),
+// the third sweep's from the ring, a plane between two chain blocks going
+// to both blocks' records (as each block's own advance would record it).
+template <typename T, int E, int ORDER, int P, bool SPLITB, int FLUX = 0>
 struct StreamChain {
   using AX = StreamAxes<ORDER, E>;
   using SL = SlabLayout<P>;
@@ -238,6 +246,12 @@ struct StreamChain {
   StreamRing<T> ring;
   CellDiag dg;
   T run[RUN][kNV];
+
+  // flux record of block b (FLUX != 0)
+  __device__ __forceinline__ T* record(int b) const {
+    return reinterpret_cast<T*>(kp.flux) +
+           (kp.flux_off ? kp.flux_off[b] : (int64_t)b * flux_record_size(E));
+  }
 
   // Phase A and B of the slab planes pl in [lo, hi), plane pl being plane
   // s_lo + pl of block `cb` (rs = 0) or of its neighbour at S-offset rs (the
@@ -278,7 +292,18 @@ struct StreamChain {
 #pragma unroll
         for (int ra = 0; ra < 3; ++ra) src.p[ra] = uin + sm.nb9[ra + 3 * (rb + 1)] + row;
         const StreamSinkA<T, P, AX::A> dst{sm.s, r, pl};
-        pencil_sweep<T, kTile>(src, dst, cf);
+        if constexpr (FLUX != 0) {
+          // own rows of the tile, planes of the chain's blocks: face
+          // (z, y) = (s, b) of an x pencil, (y, x) = (b, s) of a z pencil
+          const int s_ = s_lo + pl;
+          T* fp = nullptr;
+          if (rs == 0 && r >= kG && r < kG + kTile)
+            fp = ORDER == 0 ? flux_entry<T, E>(record(cb), 0, s_, b)
+                            : flux_entry<T, E>(record(cb), 2, b, s_);
+          pencil_sweep<T, kTile>(src, tap<FLUX, T, E, AX::A>(dst, fp, a0, kp), cf);
+        } else {
+          pencil_sweep<T, kTile>(src, dst, cf);
+        }
       }
     }
     __syncthreads();
@@ -289,7 +314,17 @@ struct StreamChain {
       const bool act = pl >= lo && pl < hi;   // 2 * 16 * P = 256 half pencils
       const Shifted<StreamPencilB<T, P, AX::B>> acc{{sm.s, p % kTile, pl}, off};
       Held<T, kTile / 2> held;
-      if (act) pencil_sweep<T, kTile / 2>(acc, held, cf);
+      if constexpr (FLUX != 0) {
+        // face (z, x) = (s, a) of a y pencil (a, s: A and S coordinates)
+        const int a = a0 + p % kTile, s_ = s_lo + pl;
+        T* fp = nullptr;
+        if (rs == 0)
+          fp = ORDER == 0 ? flux_entry<T, E>(record(cb), 1, s_, a)
+                          : flux_entry<T, E>(record(cb), 1, a, s_);
+        if (act) pencil_sweep<T, kTile / 2>(acc, tap<FLUX, T, E, AX::B>(held, fp, b0 + off, kp), cf);
+      } else {
+        if (act) pencil_sweep<T, kTile / 2>(acc, held, cf);
+      }
       __syncthreads();
       if (act) held.flush(acc);
     } else {
@@ -299,7 +334,16 @@ struct StreamChain {
       const int pl = p / kTile;
       if (l < per && p < npen && pl >= lo && pl < hi) {
         const StreamPencilB<T, P, AX::B> acc{sm.s, p % kTile, pl};
-        pencil_sweep<T, kTile>(acc, acc, cf);
+        if constexpr (FLUX != 0) {
+          const int a = a0 + p % kTile, s_ = s_lo + pl;
+          T* fp = nullptr;
+          if (rs == 0)
+            fp = ORDER == 0 ? flux_entry<T, E>(record(cb), 1, s_, a)
+                            : flux_entry<T, E>(record(cb), 1, a, s_);
+          pencil_sweep<T, kTile>(acc, tap<FLUX, T, E, AX::B>(acc, fp, b0, kp), cf);
+        } else {
+          pencil_sweep<T, kTile>(acc, acc, cf);
+        }
       }
     }
     __syncthreads();
@@ -347,6 +391,31 @@ struct StreamChain {
     diag_publish<kStreamNT>(dg, b * sp.quads + quad, dh, kp, sm.red, tid);
   }
 
+  // The third sweep's flux through chain plane q (0 .. C*E, a multiple of
+  // 8), just computed by the ring (ring.Hp), into the record of the block
+  // above the plane and, on a boundary between two chain blocks, of the
+  // block below it too.  Face (y, x) = (b, a) of a z column, (z, y) = (a, b)
+  // of an x column.
+  __device__ __forceinline__ void ring_flux(int q, int al, int bl) {
+    if (q < 0 || q > C * E) return;
+    const int a = a0 + al, b = b0 + bl;
+    const T w = (T)kp.flux_w;
+    auto put = [&](int blk, int plane) {
+      T* f = (ORDER == 0 ? flux_entry<T, E>(record(blk), 2, b, a)
+                         : flux_entry<T, E>(record(blk), 0, a, b)) +
+             plane * (kNV * E * E);
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
+        T* c = f + gcomp<AX::S>(k) * (E * E);
+        if constexpr (FLUX == 2) *c = *c + w * ring.Hp[k];
+        else *c = w * ring.Hp[k];
+      }
+    };
+    const int kk = q / E, r = q % E;
+    if (kk < C) put(sp.blocks[chain0 + kk], r / kPatch);
+    if (r == 0 && kk >= 1) put(sp.blocks[chain0 + kk - 1], E / kPatch);
+  }
+
   // Phase S over the slab planes pl in [lo, hi): plane pl is chain plane
   // g = g0 + pl, chain step g + 3, ring position (3 + pl) mod 4 (g0 is a
   // multiple of 4 minus 0 for the blocks' planes and the closing ghost
@@ -365,6 +434,12 @@ struct StreamChain {
 #pragma unroll
         for (int k = 0; k < kNV; ++k) u[k] = sm.s[gcomp<AX::S>(k) * SL::VP + o];
         ring.template step<j4>(u, cf, out);
+        if constexpr (FLUX != 0 && pl == 2) {
+          // the flux of this step is that of chain plane g0 (the interface
+          // below cell g0), a multiple of 8 for the blocks' slabs and the
+          // closing ghost slab
+          ring_flux(g0, al, bl);
+        }
         // finished cell g - 3, at position (pl - 3) mod RUN of its 16-byte run
         constexpr int rpos = ((pl - kG) % RUN + RUN) % RUN;
         if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out);
@@ -406,7 +481,7 @@ struct StreamChain {
   }
 };
 
-template <typename T, int E, int ORDER, int P, bool SPLITB>
+template <typename T, int E, int ORDER, int P, bool SPLITB, int FLUX = 0>
 __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_stream(
     KParams kp, StreamParams sp) {
   using AX = StreamAxes<ORDER, E>;
@@ -456,7 +531,7 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
       atomicAdd(&kp.counters[1], (unsigned long long)C * (E * E * E / sp.quads));
     return;  // uniform over the workgroup
   }
-  StreamChain<T, E, ORDER, P, SPLITB> ch{kp, sp, sm};
+  StreamChain<T, E, ORDER, P, SPLITB, FLUX> ch{kp, sp, sm};
   ch.tid = tid;
   ch.quad = quad;
   ch.a0 = kTile * (quad & 1);

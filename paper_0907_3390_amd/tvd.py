@@ -45,7 +45,7 @@ EXPORTS = [
     "tvd_close_level", "tvd_poisson_sor", "tvd_gravity", "tvd_lerp",
     "tvd_patch_advance_stream", "tvd_patch_advance_stream_noalloc",
     "tvd_pipeline_stage_bytes", "tvd_patch_advance_host",
-    "tvd_patch_advance_flux_gather", "tvd_fill_coarse_fine",
+    "tvd_patch_advance_flux_gather", "tvd_fill_coarse_fine", "tvd_patch_advance_stream_flux",
 ]
 
 
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
                                                          i32, i32, dbl, dbl, i32, vp, vp, vp]),
         "tvd_fill_coarse_fine": (ctypes.c_int, [vp, bp, vp, i32, vp, bp, vp, vp, dbl, vp, vp,
                                                 vp]),
+        "tvd_patch_advance_stream_flux": (ctypes.c_int, [vp, bp, vp, i32, vp, vp, vp, vp, vp,
+                                                         dbl, i32, i32, dbl, dbl, vp]),
         "tvd_restrict": (ctypes.c_int, [vp, bp, vp, bp, vp, vp, i32, vp]),
         "tvd_flux_correct": (ctypes.c_int, [vp, bp, vp, vp, vp, bp, vp, vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), vp]),
@@ -348,6 +350,17 @@ class Context:
             self.h, batch.ref, _ptr(nbr), n_sources, _ptr(u_in), _ptr(u_out), _ptr(flux),
             _ptr(flux_off), flux_weight, accumulate, sweep_order, gamma, p_floor, flags,
             _ptr(smax), _ptr(sums), _stream(stream))
+        return self._check(st) if check else st
+
+    def tvd_patch_advance_stream_flux(self, batch: Batch, nbr, n_sources: int, chains: "Chains",
+                                      u_in, u_out, flux, flux_off, sweep_order: int,
+                                      gamma: float, p_floor: float = 0.0,
+                                      flux_weight: float = 1.0, accumulate: int = 0,
+                                      stream=None, check: bool = True):
+        st = self.lib.tvd_patch_advance_stream_flux(
+            self.h, batch.ref, _ptr(nbr), n_sources, chains.ref, _ptr(u_in), _ptr(u_out),
+            _ptr(flux), _ptr(flux_off), flux_weight, accumulate, sweep_order, gamma, p_floor,
+            _stream(stream))
         return self._check(st) if check else st
 
     def tvd_fill_coarse_fine(self, fine: Batch, nbr, n_sources: int, fine_interior, coarse: Batch,
