@@ -514,7 +514,8 @@ def run_closing(ctx, ml, reps=10):
     return res
 
 
-def run_nested(ctx, ml, reps=4, n=8, gather=False):
+def run_nested(ctx, ml, reps=4, n=8, gather=False, stream_min_blocks=None,
+               stream_chain_len=None):
     """The multi-level hierarchy advanced with every level sub-cycled (FP32,
     as 8^3 patches or, n = 16, as 2^3 patch groups): one root step is one
     step of level 0, two of level 1, four of level 2 and eight of level 3,
@@ -522,12 +523,14 @@ def run_nested(ctx, ml, reps=4, n=8, gather=False):
     (amr.NestedDevice).  Timed with HIP events
     over `reps` root steps run eagerly, and as replays of a HIP graph of two
     root steps (xyz, zyx).  Also reports the drift of the leaf totals over
-    the timed steps (host sums of the downloaded state)."""
+    the timed steps (host sums of the downloaded state).  stream_min_blocks:
+    levels of at least that many groups advance by the streamed kernel."""
     import torch
     from paper_0907_3390_amd import amr, layout, tvd
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
     top = len(refined)
-    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather)
+    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather,
+                           stream_min_blocks=stream_min_blocks, stream_chain_len=stream_chain_len)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
     per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
@@ -595,11 +598,14 @@ def run_nested(ctx, ml, reps=4, n=8, gather=False):
     res = {"workload": f"multi-level hierarchy (128^3 base, levels 1-3, {held}), "
                        f"FP32, every level sub-cycled, every pair closed; {how}",
            "ghost_zones": "gathered" if gather else "ghosted copies",
+           "streamed_levels": [lev for lev, c in enumerate(dev.chains) if c is not None],
            "blocks_per_level": dev.nb, "block_edge": n, "cell_updates_per_root_step": updates,
            "root_step_ms_eager": ms_eager, "root_step_ms_graph": ms_graph,
            "value": updates / (ms_graph * 1e-3), "unit": "cell-updates/s",
            "root_steps_run": steps, "leaf_total_drift": drift}
-    log(f"bench: nested sub-cycled step ({n}^3 blocks, gather {gather}): {ms_eager:.3f} ms eager, {ms_graph:.3f} ms as graph replay "
+    log(f"bench: nested sub-cycled step ({n}^3 blocks, gather {gather}, streamed levels "
+        f"{res['streamed_levels']}, chains of {stream_chain_len}): {ms_eager:.3f} ms eager, "
+        f"{ms_graph:.3f} ms as graph replay "
         f"per root step ({updates / 1e6:.1f} M cell-updates), {res['value'] / 1e9:.2f} G "
         f"cell-updates/s; leaf totals drift {drift:.1e} over {steps} root steps")
     return res
@@ -1253,6 +1259,10 @@ def main():
         torch.cuda.empty_cache()
         out["nested_subcycled_step"] = run_nested(ctx, ml, n=16, gather=True)
         out["nested_subcycled_step"]["groups_ghosted_copies"] = run_nested(ctx, ml, n=16)
+        # levels 0-2 by the streamed advance with flux records, chains of 2
+        # blocks (slower here: few chains per level, see the design notes)
+        out["nested_subcycled_step"]["groups_streamed_levels"] = run_nested(
+            ctx, ml, n=16, gather=True, stream_min_blocks=512, stream_chain_len=2)
         out["nested_subcycled_step"]["patches_8cube"] = run_nested(ctx, ml, n=8, gather=True)
         log("bench: Poisson SOR on patch groups")
         torch.cuda.empty_cache()

@@ -126,10 +126,14 @@ class NestedDevice:
     a time-interpolated state."""
 
     def __init__(self, ctx: tvd.Context, Nc: int, refined, dtype=torch.float64,
-                 gamma: float = GAMMA, n: int = 8, gather: bool = False):
+                 gamma: float = GAMMA, n: int = 8, gather: bool = False,
+                 stream_min_blocks: int | None = None, stream_chain_len: int | None = None):
         if n == 16 and dtype != torch.float32:
             raise ValueError("patch groups (n = 16) advance in FP32: the flux-recording FP64 "
                              "advance holds blocks of edge 8 only")
+        if stream_min_blocks is not None and not (gather and n == 16):
+            raise ValueError("the streamed advance with flux records takes FP32 patch groups "
+                             "with stand-ins (n = 16, gather = True)")
         self.ctx, self.dtype, self.gamma = ctx, dtype, gamma
         self.L = L = layout.NestedLevels(Nc, refined, n)
         self.n = n
@@ -159,6 +163,23 @@ class NestedDevice:
                     for lev, n in enumerate(self.nb)]
         self.rec_mean = [None] + [z(n * rs) for n in self.nb[1:]]
         self.nbr = [dev(b.nbr) for b in L.blocks]
+        # levels of at least stream_min_blocks blocks advance by the streamed
+        # kernel, over chains along z (forward order) and x (backward order)
+        # of at most stream_chain_len blocks (default driver.default_chain_len);
+        # smaller levels keep the per-block kernel, whose one workgroup per
+        # block fills more of the chip than a level's few chains would
+        self.chains = [None] * L.n_levels
+        if stream_min_blocks is not None:
+            from .driver import default_chain_len
+            for lev in range(L.n_levels):
+                if self.nb[lev] < stream_min_blocks:
+                    continue
+                cl = stream_chain_len or default_chain_len(self.nb[lev])
+                ch = {}
+                for order, axis in ((tvd.TVD_XYZ, 2), (tvd.TVD_ZYX, 0)):
+                    st_, bl_ = layout.stream_chains(st[lev][0][:self.nb[lev]], axis, cl)
+                    ch[order] = tvd.Chains(dev(st_), dev(bl_))
+                self.chains[lev] = ch
         self.cnbr = [None] + [dev(t) for t in L.cnbr[1:]]
         self.corigin = [None] + [dev(t) for t in L.corigin[1:]]
         self.rows = {}
@@ -211,6 +232,19 @@ class NestedDevice:
         ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(self.n), self.rec[lev][0],
                      self.rec[lev][1], self.rec_mean[lev], 0.5)
 
+    def _advance_gather(self, lev, batch, rec, order):
+        """Level lev's advance with flux records, ghost zones read from the
+        siblings and stand-ins: streamed over chains, or per block."""
+        if self.chains[lev] is not None:
+            self.ctx.tvd_patch_advance_stream_flux(batch, self.vnbr[lev], self.nsrc[lev],
+                                                   self.chains[lev][order], self.u[lev],
+                                                   self.u_new[lev], rec, None, order,
+                                                   self.gamma)
+        else:
+            self.ctx.tvd_patch_advance_flux_gather(batch, self.vnbr[lev], self.nsrc[lev],
+                                                   self.u[lev], self.u_new[lev], rec, None, order,
+                                                   self.gamma)
+
     def _subcycle_gather(self, lev, dt, order):
         """_subcycle without ghosted copies: the coarse-fine fill writes only
         the interpolated ghost cells, into the stand-ins for missing
@@ -223,9 +257,7 @@ class NestedDevice:
             ctx.tvd_fill_coarse_fine(fb, self.vnbr[lev], self.nsrc[lev], self.u[lev], cb,
                                      self.u[lev - 1], self.u_new[lev - 1], 0.5 * k,
                                      self.cnbr[lev], self.corigin[lev])
-            ctx.tvd_patch_advance_flux_gather(fb, self.vnbr[lev], self.nsrc[lev], self.u[lev],
-                                              self.u_new[lev], self.rec[lev][k], None, o,
-                                              self.gamma)
+            self._advance_gather(lev, fb, self.rec[lev][k], o)
             if lev + 1 < self.L.n_levels:
                 self._k[lev] = k
                 self._subcycle(lev + 1, h, o)
@@ -242,9 +274,7 @@ class NestedDevice:
         b0 = self._batch(0, dt)
         if self.gather:
             # the root grid is complete: every ghost cell is a sibling's
-            ctx.tvd_patch_advance_flux_gather(b0, self.vnbr[0], self.nsrc[0], self.u[0],
-                                              self.u_new[0], self.rec[0][0], None, order,
-                                              self.gamma)
+            self._advance_gather(0, b0, self.rec[0][0], order)
         else:
             ctx.tvd_fill_ghosts(b0, self.nbr[0], self.u[0], self.u_gh[0])
             ctx.tvd_patch_advance_flux(b0, self.u_gh[0], self.u_new[0], self.rec[0][0], None,

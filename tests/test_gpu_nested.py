@@ -121,6 +121,33 @@ def test_nested_gather_equals_ghosted_copies(ctx, dtype, n):
         assert np.array_equal(a, b)
 
 
+def test_nested_streamed_levels_equal_per_block(ctx):
+    """Patch groups with stand-ins: every level advanced by the streamed
+    kernel with flux records (chains along z and x over each level's blocks)
+    gives the same bits as the per-block gathering advance, over two root
+    steps."""
+    note("nested driver, streamed levels vs per-block advance, fp32 groups")
+    states = _states(531, True)
+    ref = amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float32, n=16, gather=True)
+    got = amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float32, n=16, gather=True,
+                           stream_min_blocks=1)
+    assert all(c is not None for c in got.chains)
+    blocks = [b.astype(np.float32) for b in _blocks(ref.L, states)]
+    for d in (ref, got):
+        d.upload(blocks)
+    ctx.tvd_read_flags()
+    dt = 0.1 / NC
+    for o in (0, 1):
+        ref.step(dt, o)
+        got.step(dt, o)
+    torch.cuda.synchronize()
+    assert ctx.tvd_read_flags()[2] == 0
+    for a, b in zip(ref.download(), got.download()):
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float32, n=16, stream_min_blocks=1)
+
+
 def test_nested_driver_conserves_over_steps(ctx):
     states = _states(510, False)
     dev = amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float64)
@@ -168,19 +195,23 @@ def test_nested_step_graph_replay(ctx):
         g.close()
 
 
-@pytest.mark.parametrize("n,gather", [(8, False), (16, False), (16, True)])
-def test_nested_full_size_conserves_fp32(ctx, n, gather):
+@pytest.mark.parametrize("n,gather,stream_min", [(8, False, None), (16, False, None),
+                                                 (16, True, None), (16, True, 512)])
+def test_nested_full_size_conserves_fp32(ctx, n, gather, stream_min):
     """The full multi-level hierarchy (128^3 base, levels 1-3, 18 152 patches,
-    the bench's configuration, as patches or as 2269 patch groups), FP32,
+    the bench's configuration, as patches or as 2269 patch groups, the
+    larger levels of groups optionally by the streamed advance), FP32,
     every level sub-cycled: over four root steps (32 level-3 steps) the leaf
     totals drift by no more than the FP32 rounding of the stored state (1e-6
     of each variable's scale; momentum against mass times the signal speed,
     the gas starting at rest), and no cell is floored or non-physical."""
     from paper_0907_3390_amd import layout
-    note(f"nested driver, full multi-level hierarchy, fp32, blocks of {n}^3, gather {gather}")
+    note(f"nested driver, full multi-level hierarchy, fp32, blocks of {n}^3, gather {gather}, "
+         f"streamed levels from {stream_min} blocks")
     ml = wl.multilevel()
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
-    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather)
+    dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather,
+                           stream_min_blocks=stream_min)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
     per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
