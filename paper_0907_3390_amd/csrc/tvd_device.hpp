@@ -193,12 +193,14 @@ struct CSum {
   double s, c;
 };
 
+// Neumaier's compensated step: the rounding error of s + v, recovered
+// exactly, goes to the compensation.  The error is taken by Knuth's
+// branch-free TwoSum, which yields the same exact value as Neumaier's
+// magnitude test with (s - t) + v or (v - t) + s, in fewer instructions.
 __device__ __forceinline__ void csum_add(CSum& a, double v) {
   const double t = a.s + v;
-  if (__builtin_fabs(a.s) >= __builtin_fabs(v))
-    a.c += (a.s - t) + v;
-  else
-    a.c += (v - t) + a.s;
+  const double z = t - a.s;
+  a.c += (a.s - (t - z)) + (v - z);
   a.s = t;
 }
 
