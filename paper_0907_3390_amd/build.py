@@ -35,6 +35,16 @@ def build(verbose: bool = False, extra=(), out: str = LIB, jobs: int | None = No
     os.makedirs(os.path.dirname(out), exist_ok=True)
     objdir = os.path.join(OBJDIR, "%d" % os.getpid())
     os.makedirs(objdir, exist_ok=True)
+    try:
+        return _build(objdir, verbose, extra, out, jobs)
+    finally:
+        # the objects of this build only: removed whether it succeeded or not
+        for f in os.listdir(objdir):
+            os.remove(os.path.join(objdir, f))
+        os.rmdir(objdir)
+
+
+def _build(objdir: str, verbose: bool, extra, out: str, jobs: int | None) -> str:
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 1)))
     base = ["hipcc"] + FLAGS + list(extra) + ["-I", INCLUDE, "-I", CSRC]
     cmds = [(src, base + ["-c", os.path.join(CSRC, src), "-o",
@@ -65,11 +75,10 @@ def build(verbose: bool = False, extra=(), out: str = LIB, jobs: int | None = No
     r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
+        if os.path.exists(tmp):
+            os.remove(tmp)
         raise RuntimeError("hipcc failed linking libtvd.so")
     os.replace(tmp, out)
-    for f in os.listdir(objdir):
-        os.remove(os.path.join(objdir, f))
-    os.rmdir(objdir)
     return out
 
 
