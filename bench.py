@@ -515,7 +515,7 @@ def run_closing(ctx, ml, reps=10):
 
 
 def run_nested(ctx, ml, reps=4, n=8, gather=False, stream_min_blocks=None,
-               stream_chain_len=None):
+               stream_chain_len=None, overlap=False):
     """The multi-level hierarchy advanced with every level sub-cycled (FP32,
     as 8^3 patches or, n = 16, as 2^3 patch groups): one root step is one
     step of level 0, two of level 1, four of level 2 and eight of level 3,
@@ -530,7 +530,8 @@ def run_nested(ctx, ml, reps=4, n=8, gather=False, stream_min_blocks=None,
     refined = layout.NestedLevels.refined_from_patches(ml.base, ml.patches)
     top = len(refined)
     dev = amr.NestedDevice(ctx, ml.base, refined, dtype=torch.float32, n=n, gather=gather,
-                           stream_min_blocks=stream_min_blocks, stream_chain_len=stream_chain_len)
+                           stream_min_blocks=stream_min_blocks, stream_chain_len=stream_chain_len,
+                           overlap=overlap)
     L = dev.L
     interior = ml.ghosted[:, :, 3:11, 3:11, 3:11]
     per = [np.zeros((k, 5, n, n, n), dtype=np.float32) for k in dev.nb]
@@ -567,24 +568,30 @@ def run_nested(ctx, ml, reps=4, n=8, gather=False, stream_min_blocks=None,
     e.record(stream)
     torch.cuda.synchronize()
     ms_eager = a.elapsed_time(e) / reps
-    s = torch.cuda.Stream()
-    s.wait_stream(stream)
-    with torch.cuda.stream(s):
-        ctx.tvd_graph_begin(s)
-        for o in (0, 1):
-            dev.step(dt, o)
-        g = ctx.tvd_graph_end(s)
-    torch.cuda.synchronize()
-    try:
-        g.replay(stream)
-        a.record(stream)
-        for r in range(reps // 2):
-            g.replay(stream)
-        e.record(stream)
+    ms_graph = None
+    if not overlap:  # the overlapped driver is not captured (amr.NestedDevice.step)
+        s = torch.cuda.Stream()
+        s.wait_stream(stream)
+        with torch.cuda.stream(s):
+            ctx.tvd_graph_begin(s)
+            for o in (0, 1):
+                dev.step(dt, o)
+            g = ctx.tvd_graph_end(s)
         torch.cuda.synchronize()
-        ms_graph = a.elapsed_time(e) / (2 * (reps // 2))
-    finally:
-        g.close()
+        try:
+            g.replay(stream)
+            a.record(stream)
+            for r in range(reps // 2):
+                g.replay(stream)
+            e.record(stream)
+            torch.cuda.synchronize()
+            ms_graph = a.elapsed_time(e) / (2 * (reps // 2))
+        finally:
+            g.close()
+    else:
+        # as many root steps as the graph replays would have run
+        for r in range(2 + 2 * (reps // 2)):
+            dev.step(dt, r % 2)
     after = leaf_sums(dev.download())
     steps = 2 + reps + 2 + 2 * (reps // 2)
     updates = sum((1 << l) * k * n ** 3 for l, k in enumerate(dev.nb))
@@ -599,13 +606,15 @@ def run_nested(ctx, ml, reps=4, n=8, gather=False, stream_min_blocks=None,
                        f"FP32, every level sub-cycled, every pair closed; {how}",
            "ghost_zones": "gathered" if gather else "ghosted copies",
            "streamed_levels": [lev for lev, c in enumerate(dev.chains) if c is not None],
+           "levels_overlapped": overlap,
            "blocks_per_level": dev.nb, "block_edge": n, "cell_updates_per_root_step": updates,
            "root_step_ms_eager": ms_eager, "root_step_ms_graph": ms_graph,
-           "value": updates / (ms_graph * 1e-3), "unit": "cell-updates/s",
+           "value": updates / ((ms_graph or ms_eager) * 1e-3), "unit": "cell-updates/s",
            "root_steps_run": steps, "leaf_total_drift": drift}
-    log(f"bench: nested sub-cycled step ({n}^3 blocks, gather {gather}, streamed levels "
-        f"{res['streamed_levels']}, chains of {stream_chain_len}): {ms_eager:.3f} ms eager, "
-        f"{ms_graph:.3f} ms as graph replay "
+    log(f"bench: nested sub-cycled step ({n}^3 blocks, gather {gather}, overlap {overlap}, "
+        f"streamed levels {res['streamed_levels']}, chains of {stream_chain_len}): "
+        f"{ms_eager:.3f} ms eager, "
+        f"{ms_graph or float('nan'):.3f} ms as graph replay "
         f"per root step ({updates / 1e6:.1f} M cell-updates), {res['value'] / 1e9:.2f} G "
         f"cell-updates/s; leaf totals drift {drift:.1e} over {steps} root steps")
     return res
@@ -1067,6 +1076,7 @@ def main():
         if args.only == "nested":
             ml = wl.multilevel()
             rec = {"nested_subcycled_step": run_nested(ctx, ml, n=16, gather=True),
+                   "overlapped_levels": run_nested(ctx, ml, n=16, gather=True, overlap=True),
                    "ghosted_copies": run_nested(ctx, ml, n=16)}
         elif args.only == "uneven":
             rec = {"uneven_batch": run_uneven(ctx)}
@@ -1259,6 +1269,10 @@ def main():
         torch.cuda.empty_cache()
         out["nested_subcycled_step"] = run_nested(ctx, ml, n=16, gather=True)
         out["nested_subcycled_step"]["groups_ghosted_copies"] = run_nested(ctx, ml, n=16)
+        # each level on its own stream, a level's first sub-step beside its
+        # parent's advance (eager steps only: this driver is not captured)
+        out["nested_subcycled_step"]["groups_overlapped_levels"] = run_nested(
+            ctx, ml, n=16, gather=True, overlap=True)
         # levels 0-2 by the streamed advance with flux records, chains of 2
         # blocks (slower here: few chains per level, see the design notes)
         out["nested_subcycled_step"]["groups_streamed_levels"] = run_nested(

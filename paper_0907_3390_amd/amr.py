@@ -127,10 +127,13 @@ class NestedDevice:
 
     def __init__(self, ctx: tvd.Context, Nc: int, refined, dtype=torch.float64,
                  gamma: float = GAMMA, n: int = 8, gather: bool = False,
-                 stream_min_blocks: int | None = None, stream_chain_len: int | None = None):
+                 stream_min_blocks: int | None = None, stream_chain_len: int | None = None,
+                 overlap: bool = False):
         if n == 16 and dtype != torch.float32:
             raise ValueError("patch groups (n = 16) advance in FP32: the flux-recording FP64 "
                              "advance holds blocks of edge 8 only")
+        if overlap and not gather:
+            raise ValueError("overlapped levels need the gathering driver (gather = True)")
         if stream_min_blocks is not None and not (gather and n == 16):
             raise ValueError("the streamed advance with flux records takes FP32 patch groups "
                              "with stand-ins (n = 16, gather = True)")
@@ -182,6 +185,16 @@ class NestedDevice:
                 self.chains[lev] = ch
         self.cnbr = [None] + [dev(t) for t in L.cnbr[1:]]
         self.corigin = [None] + [dev(t) for t in L.corigin[1:]]
+        # overlap: level l >= 1 works on a stream of its own, and its first
+        # sub-step inside a step of level l-1 runs while level l-1 advances
+        # (it reads only level l-1's old state); events order the rest
+        self.overlap = overlap
+        if overlap:
+            nl = L.n_levels
+            self.streams = [None] + [torch.cuda.Stream() for _ in range(1, nl)]
+            self.ev_fork = [torch.cuda.Event() for _ in range(nl)]
+            self.ev_adv = [torch.cuda.Event() for _ in range(nl)]
+            self.ev_done = [torch.cuda.Event() for _ in range(nl)]
         self.rows = {}
         for lev, (rr, fr, _) in L.tables().items():
             gr, gs = layout.group_face_rows(fr)
@@ -202,11 +215,11 @@ class NestedDevice:
     def _batch(self, lev, dt):
         return tvd.Batch(self.code, self.nb[lev], self.n, dt=dt, dh=1.0 / (self.L.Nc << lev))
 
-    def _close(self, lev, dt):
+    def _close(self, lev, dt, stream=None):
         rr, gr, gs = self.rows[lev]
         self.ctx.tvd_close_level(self._batch(lev, dt), self.u_new[lev], self.rec[lev][self._k[lev]],
                                  None, self._batch(lev + 1, 0.5 * dt), self.u[lev + 1],
-                                 self.rec_mean[lev + 1], None, rr, gr, gs)
+                                 self.rec_mean[lev + 1], None, rr, gr, gs, stream=stream)
 
     def _subcycle(self, lev, dt, order):
         """Level lev takes two steps of dt/2 inside level lev-1's step of dt,
@@ -232,18 +245,58 @@ class NestedDevice:
         ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(self.n), self.rec[lev][0],
                      self.rec[lev][1], self.rec_mean[lev], 0.5)
 
-    def _advance_gather(self, lev, batch, rec, order):
+    def _advance_gather(self, lev, batch, rec, order, stream=None):
         """Level lev's advance with flux records, ghost zones read from the
         siblings and stand-ins: streamed over chains, or per block."""
         if self.chains[lev] is not None:
             self.ctx.tvd_patch_advance_stream_flux(batch, self.vnbr[lev], self.nsrc[lev],
                                                    self.chains[lev][order], self.u[lev],
                                                    self.u_new[lev], rec, None, order,
-                                                   self.gamma)
+                                                   self.gamma, stream=stream)
         else:
             self.ctx.tvd_patch_advance_flux_gather(batch, self.vnbr[lev], self.nsrc[lev],
                                                    self.u[lev], self.u_new[lev], rec, None, order,
-                                                   self.gamma)
+                                                   self.gamma, stream=stream)
+
+    def _advance_then_child(self, lev, batch, rec, order, dt, s):
+        """Overlap: level lev's advance on stream s, with level lev+1's two
+        sub-steps of dt/2 (o = order first) on its own stream, forked before
+        the advance (the first sub-step needs only level lev's old state;
+        the second waits for the advance), then the closing of the pair on
+        s once both are done."""
+        c = lev + 1
+        cs = self.streams[c]
+        self.ev_fork[lev].record(s)
+        cs.wait_event(self.ev_fork[lev])
+        self._advance_gather(lev, batch, rec, order, stream=s)
+        self.ev_adv[lev].record(s)
+        self._run_level(c, dt, order, cs, self.ev_adv[lev])
+        self.ev_done[c].record(cs)
+        s.wait_event(self.ev_done[c])
+        self._close(lev, dt, stream=s)
+
+    def _run_level(self, lev, dt, order, s, parent_advanced):
+        """Overlap: level lev's two sub-steps of dt/2 inside its parent's step
+        of dt, issued on stream s; parent_advanced is recorded after the
+        parent's advance, which the second sub-step's coarse-fine fill (the
+        parent's old and new states, w = 1/2) needs."""
+        ctx, h = self.ctx, 0.5 * dt
+        fb, cb = self._batch(lev, h), self._batch(lev - 1, h)
+        for k in (0, 1):
+            o = order if k == 0 else 1 - order
+            if k == 1:
+                s.wait_event(parent_advanced)
+            ctx.tvd_fill_coarse_fine(fb, self.vnbr[lev], self.nsrc[lev], self.u[lev], cb,
+                                     self.u[lev - 1], self.u_new[lev - 1], 0.5 * k,
+                                     self.cnbr[lev], self.corigin[lev], stream=s)
+            self._k[lev] = k
+            if lev + 1 < self.L.n_levels:
+                self._advance_then_child(lev, fb, self.rec[lev][k], o, h, s)
+            else:
+                self._advance_gather(lev, fb, self.rec[lev][k], o, stream=s)
+            self.u[lev], self.u_new[lev] = self.u_new[lev], self.u[lev]
+        ctx.tvd_lerp(self.code, self.nb[lev] * layout.flux_record_size(self.n), self.rec[lev][0],
+                     self.rec[lev][1], self.rec_mean[lev], 0.5, stream=s)
 
     def _subcycle_gather(self, lev, dt, order):
         """_subcycle without ghosted copies: the coarse-fine fill writes only
@@ -272,6 +325,17 @@ class NestedDevice:
         ctx = self.ctx
         self._k = [0] * self.L.n_levels
         b0 = self._batch(0, dt)
+        if self.overlap and self.L.n_levels > 1:
+            if torch.cuda.is_current_stream_capturing():
+                # capturing the forks and joins across the levels' streams
+                # crashed the host inside the runtime's end of capture;
+                # refused until the cause is known
+                raise RuntimeError("the overlapped driver (overlap=True) cannot be captured "
+                                   "into a graph; use the sequential driver")
+            self._advance_then_child(0, b0, self.rec[0][0], order, dt,
+                                     torch.cuda.current_stream())
+            self.u[0], self.u_new[0] = self.u_new[0], self.u[0]
+            return
         if self.gather:
             # the root grid is complete: every ghost cell is a sibling's
             self._advance_gather(0, b0, self.rec[0][0], order)

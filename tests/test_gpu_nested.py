@@ -148,6 +148,70 @@ def test_nested_streamed_levels_equal_per_block(ctx):
         amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float32, n=16, stream_min_blocks=1)
 
 
+@pytest.mark.parametrize("dtype,n", [(torch.float64, 8), (torch.float32, 16)])
+def test_nested_overlap_equals_sequential(ctx, dtype, n):
+    """The gathering driver with every level on a stream of its own, a
+    level's first sub-step overlapping its parent's advance, gives the same
+    bits as the sequential driver over two root steps."""
+    note(f"nested driver, overlapped levels vs sequential, dtype={dtype}, blocks of {n}^3")
+    states = _states(532, dtype == torch.float32)
+    ref = amr.NestedDevice(ctx, NC, _refined(), dtype=dtype, n=n, gather=True)
+    got = amr.NestedDevice(ctx, NC, _refined(), dtype=dtype, n=n, gather=True, overlap=True)
+    blocks = [b.astype(np.float32) if dtype == torch.float32 else b
+              for b in _blocks(ref.L, states)]
+    for d in (ref, got):
+        d.upload(blocks)
+    ctx.tvd_read_flags()
+    dt = 0.1 / NC
+    for o in (0, 1):
+        ref.step(dt, o)
+        got.step(dt, o)
+    torch.cuda.synchronize()
+    assert ctx.tvd_read_flags()[2] == 0
+    for a, b in zip(ref.download(), got.download()):
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        amr.NestedDevice(ctx, NC, _refined(), dtype=dtype, n=n, overlap=True)
+
+
+@pytest.mark.skip(reason="capturing the overlapped driver's forks and joins across the levels' "
+                         "streams crashed the host inside hipStreamEndCapture; the driver refuses "
+                         "capture in overlap mode until the cause is known")
+def test_nested_overlap_graph_replay(ctx):
+    """Two root steps of the overlapped driver (fork and join across the
+    levels' streams) recorded into one HIP graph and replayed three times,
+    with eager steps in between, against eager overlapped steps: identical
+    bits after every replay."""
+    note("nested driver, overlapped levels, graph replay")
+    states = _states(533, True)
+    mk = lambda: amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float32, n=16, gather=True,
+                                  overlap=True)
+    eager, graph = mk(), mk()
+    blocks = [b.astype(np.float32) for b in _blocks(eager.L, states)]
+    for d in (eager, graph):
+        d.upload(blocks)
+    torch.cuda.synchronize()
+    dt = 0.1 / NC
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.tvd_graph_begin(s)
+        for o in (0, 1):
+            graph.step(dt, o)
+        g = ctx.tvd_graph_end(s)
+    torch.cuda.synchronize()
+    try:
+        for rep in range(3):
+            for o in (0, 1):
+                eager.step(dt, o)
+            g.replay(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            for a, b in zip(eager.download(), graph.download()):
+                assert np.array_equal(a, b), rep
+    finally:
+        g.close()
+
+
 def test_nested_driver_conserves_over_steps(ctx):
     states = _states(510, False)
     dev = amr.NestedDevice(ctx, NC, _refined(), dtype=torch.float64)
