@@ -81,8 +81,42 @@ __device__ __forceinline__ void diag_init(CellDiag& d) {
   for (int k = 0; k < kNV; ++k) d.sum[k] = CSum{0.0, 0.0};
 }
 
+// Eq. (CFL) signal speed c_s + max |v| of an FP32 state, in FP64.  The
+// division and the square root are the hardware reciprocal and reciprocal
+// square root estimates (about 2^-23 relative) refined by Newton steps on
+// FMAs (two for 1/rho; for the square root one Goldschmidt step and two
+// corrections), which lands within a few FP64 ulp of the correctly rounded
+// evaluation, far below the FP32 state's own rounding, in about half the
+// instructions of IEEE division and square root.  Square roots of values
+// below 2^-1000 are taken as 0 (the estimate does not cover denormals).
+__device__ __forceinline__ double speed_of_f32_state(const float u[kNV], double gamma,
+                                                     double pfloor) {
+  const double rho = u[0], mx = u[1], my = u[2], mz = u[3], e = u[4];
+  double r = __builtin_amdgcn_rcp(rho);
+  double t = __builtin_fma(-rho, r, 1.0);
+  r = __builtin_fma(r, t, r);
+  t = __builtin_fma(-rho, r, 1.0);
+  r = __builtin_fma(r, t, r);
+  const double m2 = __builtin_fma(mz, mz, __builtin_fma(my, my, mx * mx));
+  const double P = __builtin_fmax((gamma - 1.0) * __builtin_fma(-0.5 * m2, r, e), pfloor);
+  const double x = (gamma * P) * r;
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double q = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, q, g);
+  h = __builtin_fma(h, q, h);
+  double dd = __builtin_fma(-g, g, x);
+  g = __builtin_fma(dd, h, g);
+  dd = __builtin_fma(-g, g, x);
+  g = __builtin_fma(dd, h, g);
+  const double cs = x >= 0x1p-1000 ? g : 0.0;
+  const double mm = __builtin_fmax(__builtin_fabs(mx), __builtin_fmax(__builtin_fabs(my), __builtin_fabs(mz)));
+  return __builtin_fma(mm, r, cs);
+}
+
 // Health check of one output cell (in the bulk precision) and, as the
-// flags ask, its Eq. (CFL) signal speed (FP64, one division) and its share
+// flags ask, its Eq. (CFL) signal speed (FP64: IEEE division and square
+// root for an FP64 state, refined estimates for an FP32 one) and its share
 // of the compensated conservation sums.
 template <typename T>
 __device__ __forceinline__ void diag_cell(CellDiag& d, const T u[kNV], int flags, double gamma,
@@ -94,7 +128,9 @@ __device__ __forceinline__ void diag_cell(CellDiag& d, const T u[kNV], int flags
     d.floored += P < T(pfloor);
     d.bad += !(u[0] > T(0)) || !__builtin_isfinite(P);
   }
-  if (flags & kDiagSpeed) {
+  if constexpr (sizeof(T) == 4) {
+    if (flags & kDiagSpeed) d.smax = __builtin_fmax(d.smax, speed_of_f32_state(u, gamma, pfloor));
+  } else if (flags & kDiagSpeed) {
     const double rho = u[0], mx = u[1], my = u[2], mz = u[3], e = u[4];
     const double inv = 1.0 / rho;
     const double vx = mx * inv, vy = my * inv, vz = mz * inv;

@@ -95,14 +95,17 @@ __device__ __forceinline__ T vanleer(T a, T b) {
   const T p = a * b;
   return p > T(0) ? Num<T>::div(p, a + b) : T(0);
 }
+// The multiply whose zero operand wins over an infinite or NaN one
+// (v_mul_legacy_f32; an ordinary IEEE product otherwise).
+extern "C" __device__ float tvd_fmul_zero_wins(float, float) __asm("llvm.amdgcn.fmul.legacy");
+
 // FP32, without a compare and select: max(ab, 0) times the reciprocal of
-// a+b clamped to finite values (a+b = 0 only happens with ab <= 0, where the
-// product must be 0, not 0 * inf); for ab > 0 this is ab * rcp(a+b) exactly.
+// a+b.  a+b = 0 only happens with ab <= 0, where the result must be 0, not
+// 0 * inf: the zero-wins product gives exactly that, and for ab > 0 it is
+// ab * rcp(a+b) exactly.
 template <>
 __device__ __forceinline__ float vanleer<float>(float a, float b) {
-  constexpr float kBig = 3.402823466e38f;
-  const float r = __builtin_amdgcn_fmed3f(Num<float>::rcp(a + b), -kBig, kBig);
-  return Num<float>::max(a * b, 0.0f) * r;
+  return tvd_fmul_zero_wins(Num<float>::max(a * b, 0.0f), Num<float>::rcp(a + b));
 }
 
 // Whether a sweep destination also takes the interface fluxes of the full

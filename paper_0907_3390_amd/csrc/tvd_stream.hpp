@@ -35,6 +35,11 @@ constexpr int kStreamNT = 256;    // threads: one column of the 16 x 16 tile eac
 constexpr int kTile = 16;         // tile edge across the first two sweep axes
 constexpr int kRows = kTile + 2 * kG;   // first-sweep rows of a plane (ghosts included)
 constexpr int kStreamMaxChain = 64;     // blocks per chain at most
+// Fourth word of a raw buffer resource on gfx950 (32-bit data format, no
+// swizzle), and the vector types of the buffer stores' data.
+constexpr int kBufferWord3 = 0x00020000;
+typedef uint32_t U32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 
 // Axes of the streamed advance: A (swept first), B (second), S (last,
 // streamed).  Order 0 (xyz): A = x, B = y, S = z; order 1 (zyx): A = z,
@@ -351,32 +356,46 @@ struct StreamChain {
 
   // Store finished cell `cell` (0 .. C*E-1 along the chain) of this
   // thread's column and account for it in the diagnostics; with runs, the
-  // cell waits in registers until its run is complete.
+  // cell waits in registers until its run is complete.  The stores are
+  // buffer stores: the block's base (uniform over the workgroup) goes into
+  // the resource, the variable and plane into the scalar offset, and the
+  // lane's place in the plane (`lane`, bytes, fixed for the whole chain) is
+  // the one vector operand, so that a store costs no vector address
+  // arithmetic.
   template <int RPOS>
-  __device__ __forceinline__ void emit(int cell, const T out[kNV]) {
+  __device__ __forceinline__ void emit(int cell, const T out[kNV], uint32_t lane) {
     T ug[kNV];
 #pragma unroll
     for (int k = 0; k < kNV; ++k) ug[gcomp<AX::S>(k)] = out[k];
     diag_cell<T>(dg, ug, kp.diag, kp.gamma, kp.pfloor);
     const int kk = cell / E, sl = cell % E;
-    const int al = tid & (kTile - 1), bl = tid / kTile;
-    T* base = reinterpret_cast<T*>(kp.uout) + sm.chain_off[kk] + (int64_t)(a0 + al) * AX::sa +
-              (int64_t)(b0 + bl) * AX::sb;
-    if constexpr (RUN == 1) {
-#pragma unroll
-      for (int k = 0; k < kNV; ++k) base[(int64_t)k * E3 + (int64_t)sl * AX::ss] = ug[k];
-    } else {
+    if constexpr (RUN != 1) {
 #pragma unroll
       for (int k = 0; k < kNV; ++k) run[RPOS][k] = ug[k];
-      if constexpr (RPOS == RUN - 1) {
-        // x = sl - RUN + 1 .. sl, 16-byte aligned
+    }
+    if constexpr (RPOS == RUN - 1) {
+      const int64_t off = sm.chain_off[kk];
+      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)off);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off >> 32));
+      T* blk = reinterpret_cast<T*>(kp.uout) + (int64_t)(((uint64_t)hi << 32) | lo);
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc(blk, 0, (int)(kNV * E3 * sizeof(T)), kBufferWord3);
+      // first cell of the run along S (RUN == 1: the cell itself)
+      const int s0 = (sl - RUN + 1) * AX::ss;
 #pragma unroll
-        for (int k = 0; k < kNV; ++k) {
-          T* c = base + (int64_t)k * E3 + (sl - RUN + 1);
+      for (int k = 0; k < kNV; ++k) {
+        const int so = (k * E3 + s0) * (int)sizeof(T);
+        if constexpr (RUN == 1) {
           if constexpr (sizeof(T) == 4)
-            *reinterpret_cast<float4*>(c) = make_float4(run[0][k], run[1][k], run[2][k], run[3][k]);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, ug[k]), rs, lane, so, 0);
           else
-            *reinterpret_cast<double2*>(c) = make_double2(run[0][k], run[1][k]);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, ug[k]), rs, lane, so, 0);
+        } else if constexpr (sizeof(T) == 4) {
+          const float4 v = make_float4(run[0][k], run[1][k], run[2][k], run[3][k]);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs, lane, so, 0);
+        } else {
+          const double2 v = make_double2(run[0][k], run[1][k]);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs, lane, so, 0);
         }
       }
     }
@@ -425,6 +444,7 @@ struct StreamChain {
     int tid = this->tid;  // opaque, as in planes_ab
     asm volatile("" : "+v"(tid));
     const int al = tid & (kTile - 1), bl = tid / kTile;
+    const uint32_t lane = (uint32_t)(((a0 + al) * AX::sa + (b0 + bl) * AX::sb) * (int)sizeof(T));
     static_for<0, P>([&](auto I) {
       constexpr int pl = decltype(I)::value;
       constexpr int j4 = (3 + pl) & 3;
@@ -442,7 +462,7 @@ struct StreamChain {
         }
         // finished cell g - 3, at position (pl - 3) mod RUN of its 16-byte run
         constexpr int rpos = ((pl - kG) % RUN + RUN) % RUN;
-        if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out);
+        if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out, lane);
       }
     });
     __syncthreads();
