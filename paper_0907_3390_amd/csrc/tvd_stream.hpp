@@ -262,7 +262,7 @@ struct StreamChain {
   // s_lo + pl of block `cb` (rs = 0) or of its neighbour at S-offset rs (the
   // chain's ghost planes).  Chain ends use the same code with fewer planes,
   // so that one copy of each phase serves every slab.
-  __device__ __forceinline__ void planes_ab(int cb, int rs, int s_lo, int lo, int hi) {
+  __device__ __forceinline__ void planes_ab(int cb, int rs, int s_lo, int lo, int hi, int rot) {
     // An opaque copy of the thread index: the per-lane LDS and HBM addresses
     // derived from it are recomputed in every slab instead of being hoisted
     // out of the slab loop, where the compiler keeps dozens of them alive
@@ -333,11 +333,13 @@ struct StreamChain {
       __syncthreads();
       if (act) held.flush(acc);
     } else {
+      // whole pencils packed densely into the fewest waves (two for P = 8),
+      // the other waves idle; which waves work rotates from slab to slab
+      // (rot), so that over two slabs every SIMD gets the same share
       constexpr int npen = kTile * P;
-      constexpr int per = (npen + 3) / 4;
-      const int l = tid & 63, p = (tid >> 6) * per + l;
+      const int l = tid & 63, p = (((tid >> 6) - rot) & 3) * 64 + l;
       const int pl = p / kTile;
-      if (l < per && p < npen && pl >= lo && pl < hi) {
+      if (p < npen && pl >= lo && pl < hi) {
         const StreamPencilB<T, P, AX::B> acc{sm.s, p % kTile, pl};
         if constexpr (FLUX != 0) {
           const int a = a0 + p % kTile, s_ = s_lo + pl;
@@ -494,7 +496,7 @@ struct StreamChain {
         // the chain's first three planes finish nothing (cells -3 .. -1)
         emit_from = (kk == 0 && m == 0) ? kG : 0;
       }
-      planes_ab(cb, rs, s_lo, lo, hi);
+      planes_ab(cb, rs, s_lo, lo, hi, (t & 1) * 2);
       planes_s(g0, lo, hi, emit_from);
     }
     publish();
