@@ -250,7 +250,9 @@ struct StreamChain {
   double dh;
   StreamRing<T> ring;
   CellDiag dg;
-  T run[RUN][kNV];
+  // a 16-byte output run per variable (the backward order)
+  typedef T RunVec __attribute__((ext_vector_type(RUN)));
+  RunVec run[kNV];
 
   // flux record of block b (FLUX != 0)
   __device__ __forceinline__ T* record(int b) const {
@@ -373,7 +375,7 @@ struct StreamChain {
     const int kk = cell / E, sl = cell % E;
     if constexpr (RUN != 1) {
 #pragma unroll
-      for (int k = 0; k < kNV; ++k) run[RPOS][k] = ug[k];
+      for (int k = 0; k < kNV; ++k) run[k][RPOS] = ug[k];
     }
     if constexpr (RPOS == RUN - 1) {
       const int64_t off = sm.chain_off[kk];
@@ -389,15 +391,13 @@ struct StreamChain {
         const int so = (k * E3 + s0) * (int)sizeof(T);
         if constexpr (RUN == 1) {
           if constexpr (sizeof(T) == 4)
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, ug[k]), rs, lane, so, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ug[k]), rs, lane, so, 0);
           else
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, ug[k]), rs, lane, so, 0);
-        } else if constexpr (sizeof(T) == 4) {
-          const float4 v = make_float4(run[0][k], run[1][k], run[2][k], run[3][k]);
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs, lane, so, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(
+                U32x2{(uint32_t)__double_as_longlong(ug[k]), (uint32_t)((uint64_t)__double_as_longlong(ug[k]) >> 32)},
+                rs, lane, so, 0);
         } else {
-          const double2 v = make_double2(run[0][k], run[1][k]);
-          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, v), rs, lane, so, 0);
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U32x4, run[k]), rs, lane, so, 0);
         }
       }
     }
