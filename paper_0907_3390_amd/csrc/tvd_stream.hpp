@@ -367,7 +367,8 @@ struct StreamChain {
   // the one vector operand, so that a store costs no vector address
   // arithmetic.
   template <int RPOS>
-  __device__ __forceinline__ void emit(int cell, const T out[kNV], uint32_t lane) {
+  __device__ __forceinline__ void emit(int cell, const T out[kNV]) {
+    const uint32_t lane = (uint32_t)(((a0 + (tid & (kTile - 1))) * AX::sa + (b0 + tid / kTile) * AX::sb) * (int)sizeof(T));
     T ug[kNV];
 #pragma unroll
     for (int k = 0; k < kNV; ++k) ug[gcomp<AX::S>(k)] = out[k];
@@ -377,7 +378,19 @@ struct StreamChain {
 #pragma unroll
       for (int k = 0; k < kNV; ++k) run[k][RPOS] = ug[k];
     }
-    if constexpr (RPOS == RUN - 1) {
+    if constexpr (RPOS == RUN - 1 && sizeof(T) == 8) {
+      // FP64: plain stores (the buffer-store form costs the FP64 kernels,
+      // which already spill, more registers than it saves instructions)
+      T* base = reinterpret_cast<T*>(kp.uout) + sm.chain_off[kk] + lane / sizeof(T);
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
+        if constexpr (RUN == 1)
+          base[(int64_t)k * E3 + (int64_t)sl * AX::ss] = ug[k];
+        else
+          *reinterpret_cast<double2*>(base + (int64_t)k * E3 + (sl - RUN + 1)) =
+              make_double2(run[k].x, run[k].y);
+      }
+    } else if constexpr (RPOS == RUN - 1) {
       const int64_t off = sm.chain_off[kk];
       const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)off);
       const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off >> 32));
@@ -446,7 +459,6 @@ struct StreamChain {
     int tid = this->tid;  // opaque, as in planes_ab
     asm volatile("" : "+v"(tid));
     const int al = tid & (kTile - 1), bl = tid / kTile;
-    const uint32_t lane = (uint32_t)(((a0 + al) * AX::sa + (b0 + bl) * AX::sb) * (int)sizeof(T));
     static_for<0, P>([&](auto I) {
       constexpr int pl = decltype(I)::value;
       constexpr int j4 = (3 + pl) & 3;
@@ -464,7 +476,7 @@ struct StreamChain {
         }
         // finished cell g - 3, at position (pl - 3) mod RUN of its 16-byte run
         constexpr int rpos = ((pl - kG) % RUN + RUN) % RUN;
-        if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out, lane);
+        if (pl >= emit_from) emit<rpos>(g0 + pl - kG, out);
       }
     });
     __syncthreads();
