@@ -177,10 +177,20 @@ def tune_stream(ctx, dev, candidates, reps=2):
     (L, flags), ms = min(times.items(), key=lambda kv: kv[1])
     dev.set_chains(L)
     dev.kernel = flags
-    return {"chain_len": L, "second_sweep": "whole pencils" if flags else "half pencils",
+    return {"chain_len": L, "second_sweep": second_sweep(flags, dev.dtype),
             "ms_per_pair": ms,
-            "candidates_ms_per_pair": {f"chain {k[0]}, {'whole' if k[1] else 'halves'}": v
-                                       for k, v in times.items()}}
+            "candidates_ms_per_pair": {
+                f"chain {k[0]}, {'whole' if second_sweep(k[1], dev.dtype)[0] == 'w' else 'halves'}": v
+                for k, v in times.items()}}
+
+
+def second_sweep(flags, dtype):
+    """The second-sweep layout the streamed advance runs for `flags`
+    (TVD_KERNEL_AUTO: half pencils in FP32, whole pencils in FP64)."""
+    import torch
+    from paper_0907_3390_amd import tvd
+    whole = flags == tvd.TVD_STREAM_WHOLE_B or (flags == tvd.TVD_KERNEL_AUTO and dtype == torch.float64)
+    return "whole pencils" if whole else "half pencils"
 
 
 def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=False,
@@ -208,13 +218,12 @@ def run_gpu(ctx, grid32, n, dtype, kernel, steps, warmup, gather=False, tune=Fal
         dev.conservation_sums()
         info["sums0"] = dev.sums.cpu().numpy().tolist()
     if stream and not tune:
-        info["variant"] = {"chain_len": dev.chain_len,
-                           "second_sweep": "whole pencils" if kernel else "half pencils"}
+        info["variant"] = {"chain_len": dev.chain_len, "second_sweep": second_sweep(kernel, dtype)}
     if tune and stream:
         col = N // n
         lens = sorted({L for L in (col // 4, col // 2, col) if 2 <= L <= 64})
         info["variant"] = tune_stream(ctx, dev, [(L, f) for L in lens
-                                                 for f in (tvd.TVD_KERNEL_AUTO,
+                                                 for f in (tvd.TVD_STREAM_HALF_B,
                                                            tvd.TVD_STREAM_WHOLE_B)])
         log(f"bench: streamed advance tuned {info['variant']}")
     elif tune:

@@ -229,8 +229,13 @@ typedef struct {
     const int32_t *d_blocks;  /* [n_members]                                    */
 } tvd_chains;
 
-/* flags of tvd_patch_advance_stream besides TVD_KERNEL_AUTO */
-enum { TVD_STREAM_WHOLE_B = 16 };  /* second sweep in whole pencils (default: halves) */
+/* flags of tvd_patch_advance_stream besides TVD_KERNEL_AUTO (which takes
+ * half pencils in FP32 and whole pencils in FP64, the faster layout of
+ * each: the FP64 half-pencil kernels run out of registers) */
+enum {
+    TVD_STREAM_WHOLE_B = 16,  /* second sweep in whole pencils               */
+    TVD_STREAM_HALF_B = 32    /* second sweep in half pencils                */
+};
 
 /*
  * The same step as tvd_patch_advance_gather (interior blocks in, ghost
@@ -255,7 +260,8 @@ enum { TVD_STREAM_WHOLE_B = 16 };  /* second sweep in whole pencils (default: ha
  *            offsets that are not multiples of 16 bytes, is not advanced:
  *            its output is left untouched and its cells are counted as
  *            non-physical.
- *   flags    TVD_KERNEL_AUTO or TVD_STREAM_WHOLE_B.
+ *   flags    TVD_KERNEL_AUTO, TVD_STREAM_WHOLE_B or TVD_STREAM_HALF_B (the
+ *            layout of the second sweep; all give the same bits).
  *   d_smax, d_sums  as for tvd_patch_advance, over the chains' blocks; they
  *            use n_blocks * (1 or 4) workspace entries (tvd_reserve; else
  *            TVD_ERR_STATE).

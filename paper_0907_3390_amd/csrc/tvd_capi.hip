@@ -483,9 +483,9 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   if ((st = check_gamma(ctx, gamma, p_floor))) return st;
   if (sweep_order != TVD_XYZ && sweep_order != TVD_ZYX)
     return fail(ctx, TVD_ERR_INVALID_ARG, "sweep_order %d", sweep_order);
-  if (flags != TVD_KERNEL_AUTO && flags != TVD_STREAM_WHOLE_B)
-    return fail(ctx, TVD_ERR_INVALID_ARG, "flags %d (TVD_KERNEL_AUTO or TVD_STREAM_WHOLE_B)",
-                flags);
+  if (flags != TVD_KERNEL_AUTO && flags != TVD_STREAM_WHOLE_B && flags != TVD_STREAM_HALF_B)
+    return fail(ctx, TVD_ERR_INVALID_ARG,
+                "flags %d (TVD_KERNEL_AUTO, TVD_STREAM_WHOLE_B or TVD_STREAM_HALF_B)", flags);
   if (batch->d_edge || (batch->edge != 16 && batch->edge != 32))
     return fail(ctx, TVD_ERR_UNSUPPORTED, "the streamed advance takes a uniform edge 16 or 32");
   if (!chains) return fail(ctx, TVD_ERR_INVALID_ARG, "chains is NULL");
@@ -550,7 +550,9 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   if (d_smax) e = tvd::launch_zero_f64(ws_smax, parts, s);
   if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(ws_sums, 10 * parts, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
-  const bool splitb = flags != TVD_STREAM_WHOLE_B;
+  // second sweep in half pencils: FP32 by default, FP64 only when asked
+  // (its half-pencil kernels spill registers to scratch memory)
+  const bool splitb = flags == TVD_STREAM_HALF_B || (flags == TVD_KERNEL_AUTO && batch->dtype == TVD_F32);
   if (fx)
     e = tvd::launch_stream_flux_f32(sweep_order, fx->acc, kp, sp, s);
   else

@@ -34,6 +34,7 @@ TVD_KERNEL_BATCHED = 1
 TVD_KERNEL_PLAIN = 2
 TVD_KERNEL_PERSISTENT = 3
 TVD_STREAM_WHOLE_B = 16
+TVD_STREAM_HALF_B = 32
 
 EXPORTS = [
     "tvd_create", "tvd_destroy", "tvd_status_string", "tvd_last_error", "tvd_reserve",

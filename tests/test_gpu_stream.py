@@ -114,6 +114,22 @@ def test_whole_pencil_variant_and_fused_sums(ctx):
     assert np.all(np.abs(sa - sc) <= 1e-15 * scale)
 
 
+@pytest.mark.parametrize("n", [16, 32])
+def test_whole_pencil_variant_fp64(ctx, n):
+    """FP64: the whole-pencil second sweep (the default in FP64: no registers
+    held across a barrier) gives the bits of the half-pencil one and of the
+    per-block advance on 8^3 patches (the region rule is exact), on edge-16
+    and edge-32 blocks."""
+    note(f"stream whole-pencil variant fp64 edge {n}")
+    g = wl.lognormal(64, seed=27, sigma_ln=0.7)
+    a, _, _ = run(ctx, g, 4, n, torch.float64, stream=True)  # default: whole in FP64
+    h, _, _ = run(ctx, g, 4, n, torch.float64, stream=True, kernel=tvd.TVD_STREAM_HALF_B)
+    w, _, _ = run(ctx, g, 4, n, torch.float64, stream=True, kernel=tvd.TVD_STREAM_WHOLE_B)
+    c, _, _ = run(ctx, g, 4, 8, torch.float64, stream=False)
+    assert not np.isnan(a).any()
+    assert np.array_equal(a, h) and np.array_equal(a, w) and np.array_equal(a, c)
+
+
 def test_stream_graph_replay_matches_eager(ctx):
     """A captured pair of streamed steps replays to the eager steps' bits."""
     note("stream graph replay")
@@ -228,6 +244,10 @@ def test_stream_argument_errors(ctx):
     assert e.value.status == tvd.TVD_ERR_UNSUPPORTED
     with pytest.raises(tvd.TvdError) as e:
         ctx.tvd_patch_advance_stream(dev.batch, dev.nbr, ch, u, o, 0, GAMMA, flags=5)
+    assert e.value.status == tvd.TVD_ERR_INVALID_ARG
+    with pytest.raises(tvd.TvdError) as e:   # both layouts at once
+        ctx.tvd_patch_advance_stream(dev.batch, dev.nbr, ch, u, o, 0, GAMMA,
+                                     flags=tvd.TVD_STREAM_WHOLE_B | tvd.TVD_STREAM_HALF_B)
     assert e.value.status == tvd.TVD_ERR_INVALID_ARG
     with pytest.raises(tvd.TvdError) as e:
         ctx.tvd_patch_advance_stream(dev.batch, dev.nbr, ch, u, u, 0, GAMMA)
