@@ -263,8 +263,8 @@ enum {
  *   flags    TVD_KERNEL_AUTO, TVD_STREAM_WHOLE_B or TVD_STREAM_HALF_B (the
  *            layout of the second sweep; all give the same bits).
  *   d_smax, d_sums  as for tvd_patch_advance, over the chains' blocks; they
- *            use n_blocks * (1 or 4) workspace entries (tvd_reserve; else
- *            TVD_ERR_STATE).
+ *            use n_chains * (1 or 4) workspace entries, one per chain and
+ *            tile (tvd_reserve; else TVD_ERR_STATE).
  * Asynchronous on stream; capture-safe.
  */
 int tvd_patch_advance_stream(tvd_ctx *ctx, const tvd_batch *batch, const int32_t *d_nbr,
@@ -281,12 +281,14 @@ int tvd_patch_advance_stream(tvd_ctx *ctx, const tvd_batch *batch, const int32_t
  * 5.8 MB, held until the process ends) instead of the context's workspace.
  * It calls no hipMalloc, hipFree or allocating routine and needs no
  * tvd_reserve.
- *   Limit: with d_smax or d_sums, n_blocks * (1 for edge 16, 4 for edge 32)
+ *   Limit: with d_smax or d_sums, n_chains * (1 for edge 16, 4 for edge 32)
  *            must not exceed 65536 (else TVD_ERR_STATE, nothing launched).
  *   Sharing: every call on a device uses that device's one array; calls
  *            that overlap in time on one device (other streams, other
  *            contexts, other host threads) race and give wrong diagnostics.
- *            The partials are cleared by each call before its kernel runs.
+ *            Each call's kernel writes every partial the call then reads
+ *            (zeros for a refused chain), so nothing is left over from an
+ *            earlier call.
  */
 int tvd_patch_advance_stream_noalloc(tvd_ctx *ctx, const tvd_batch *batch,
                                      const int32_t *d_nbr, const tvd_chains *chains,

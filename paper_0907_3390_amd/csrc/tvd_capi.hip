@@ -517,7 +517,8 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
         return fail(ctx, TVD_ERR_ALIAS, "the flux records overlap a state");
     }
   }
-  const int64_t parts = (int64_t)batch->n_blocks * quads;
+  // one diagnostics record per (chain, tile) item
+  const int64_t parts = (int64_t)chains->n_chains * quads;
   if ((d_smax || d_sums) && parts > 0x7fffffff)
     return fail(ctx, TVD_ERR_INVALID_ARG, "too many blocks for the fused diagnostics");
   if ((d_smax || d_sums) && parts > cap)
@@ -545,11 +546,8 @@ int stream_impl(tvd_ctx* ctx, const tvd_batch* batch, const int32_t* d_nbr,
   sp.n_members = chains->n_members;
   sp.quads = quads;
   hipError_t e = hipSuccess;
-  // every per-tile partial starts at zero, so that blocks no valid chain
-  // covers add nothing to the fused maximum and sums
-  if (d_smax) e = tvd::launch_zero_f64(ws_smax, parts, s);
-  if (e == hipSuccess && d_sums) e = tvd::launch_zero_f64(ws_sums, 10 * parts, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "partials reset launch");
+  // every (chain, tile) workgroup writes its record, zeros for a chain that
+  // is refused, so no reset is needed; blocks no chain covers add nothing
   // second sweep in half pencils: FP32 by default, FP64 only when asked
   // (its half-pencil kernels spill registers to scratch memory)
   const bool splitb = flags == TVD_STREAM_HALF_B || (flags == TVD_KERNEL_AUTO && batch->dtype == TVD_F32);

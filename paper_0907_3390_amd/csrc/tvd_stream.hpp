@@ -246,6 +246,7 @@ struct StreamChain {
   const StreamParams& sp;
   StreamLds<T, P>& sm;
   int tid, quad, a0, b0, chain0, C;
+  int item;  // the workgroup's (chain, tile): the index of its diagnostics record
   Coef<T> cf;
   double dh;
   StreamRing<T> ring;
@@ -417,12 +418,10 @@ struct StreamChain {
   }
 
   // The chain's diagnostics, once all its cells are finished, into the
-  // partial record of its first block (the records of the other blocks of
-  // the chain stay zero): one block reduction per chain instead of one per
-  // block.
+  // partial record of its (chain, tile) item: one block reduction per chain
+  // instead of one per block, and n_chains * tiles records to finalize.
   __device__ __forceinline__ void publish() {
-    const int b = sp.blocks[chain0];
-    diag_publish<kStreamNT>(dg, b * sp.quads + quad, dh, kp, sm.red, tid);
+    diag_publish<kStreamNT>(dg, item, dh, kp, sm.red, tid);
   }
 
   // The third sweep's flux through chain plane q (0 .. C*E, a multiple of
@@ -561,8 +560,13 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
   }
   __syncthreads();
   if (sm.nbad) {
-    if (tid == 0 && shape_ok)
-      atomicAdd(&kp.counters[1], (unsigned long long)C * (E * E * E / sp.quads));
+    if (tid == 0) {
+      if (shape_ok) atomicAdd(&kp.counters[1], (unsigned long long)C * (E * E * E / sp.quads));
+      // the item's diagnostics record holds nothing
+      if (kp.diag & kDiagSpeed) kp.ws_smax[item] = 0.0;
+      if (kp.diag & kDiagSums)
+        for (int k = 0; k < 2 * kNV; ++k) kp.ws_sums[(size_t)item * 2 * kNV + k] = 0.0;
+    }
     return;  // uniform over the workgroup
   }
   StreamChain<T, E, ORDER, P, SPLITB, FLUX> ch{kp, sp, sm};
@@ -572,6 +576,7 @@ __global__ __launch_bounds__(kStreamNT) __attribute__((amdgpu_waves_per_eu(2, 2)
   ch.b0 = kTile * (quad >> 1);
   ch.chain0 = c0;
   ch.C = C;
+  ch.item = item;
   ch.cf = make_coef<T>(kp, sp.blocks[c0], ch.dh);
   ch.run_chain();
 }

@@ -258,12 +258,15 @@ def test_stream_argument_errors(ctx):
     with pytest.raises(tvd.TvdError) as e:
         ctx.tvd_patch_advance_stream(dev.batch, dev.nbr, ch, shifted, o, 0, GAMMA)
     assert e.value.status == tvd.TVD_ERR_INVALID_ARG and "aligned" in str(e.value)
-    big = layout.periodic_grid_blockset(256, 16)   # 4096 blocks, more than reserved so far
+    # 4096 blocks in 2048 chains: more partials (one per chain) than the
+    # 1024 a fresh context reserves
+    big = layout.periodic_grid_blockset(256, 16)
     c2 = tvd.Context(0)
     try:
         b2 = tvd.Batch(tvd.TVD_F32, big.n_blocks, 16, dt=1e-4, dh=1.0 / 256)
-        st, bl = layout.stream_chains(big.nbr, 2, 8)
+        st, bl = layout.stream_chains(big.nbr, 2, 2)
         chb = tvd.Chains(torch.from_numpy(st).cuda(), torch.from_numpy(bl).cuda())
+        assert len(st) - 1 > 1024
         nb = torch.from_numpy(big.nbr).cuda()
         uu = torch.ones(big.out_total, dtype=torch.float32, device="cuda")
         oo = torch.zeros_like(uu)

@@ -109,35 +109,39 @@ def test_noalloc_second_smaller_call_clears_partials(ctx):
 
 
 def test_noalloc_refuses_more_partials_than_the_array_holds(ctx):
-    """n_blocks * tiles above 65536 with fused diagnostics: TVD_ERR_STATE,
-    nothing launched; without diagnostics no partial is used and the limit
-    does not apply (checked on an empty chain list, which launches nothing)."""
+    """chains * tiles above 65536 with fused diagnostics (one partial per
+    chain and tile): TVD_ERR_STATE, nothing launched; without diagnostics no
+    partial is used and the limit does not apply (checked on an empty chain
+    list, which launches nothing)."""
     dev = torch.device("cuda:0")
-    n_blocks = SCRATCH_PARTS + 1
     # offset tables (never read: nothing is launched) so that the dense-layout
     # overlap check, which would see two small buffers as overlapping
-    # n_blocks-sized ranges, does not answer first
+    # block-sized ranges, does not answer first
     off = torch.zeros(1, dtype=torch.int64, device=dev)
-    batch = tvd.Batch(tvd.TVD_F32, n_blocks, 16, dt=1e-3, dh=1e-2, d_in_off=off, d_out_off=off)
-    start = torch.tensor([0, 1], dtype=torch.int32, device=dev)
-    members = torch.zeros(1, dtype=torch.int32, device=dev)
-    chains = tvd.Chains(start, members)
+    n = SCRATCH_PARTS + 1
+    batch = tvd.Batch(tvd.TVD_F32, n, 16, dt=1e-3, dh=1e-2, d_in_off=off, d_out_off=off)
+
+    def many_chains(n):  # n one-block chains (never read: nothing is launched)
+        start = torch.arange(n + 1, dtype=torch.int32, device=dev)
+        return tvd.Chains(start, torch.zeros(n, dtype=torch.int32, device=dev))
+
     nbr = torch.zeros(27, dtype=torch.int32, device=dev)
     u = torch.zeros(16, dtype=torch.float32, device=dev)
     v = torch.zeros(16, dtype=torch.float32, device=dev)
     sums = torch.zeros(5, dtype=torch.float64, device=dev)
-    st = ctx.tvd_patch_advance_stream_noalloc(batch, nbr, chains, u, v, tvd.TVD_XYZ, GAMMA,
-                                              sums=sums, check=False)
+    st = ctx.tvd_patch_advance_stream_noalloc(batch, nbr, many_chains(n), u, v,
+                                              tvd.TVD_XYZ, GAMMA, sums=sums, check=False)
     assert st == tvd.TVD_ERR_STATE
     assert "scratch" in ctx.last_error()
+    members = torch.zeros(1, dtype=torch.int32, device=dev)
     empty = tvd.Chains(torch.zeros(1, dtype=torch.int32, device=dev), members)
     st = ctx.tvd_patch_advance_stream_noalloc(batch, nbr, empty, u, v, tvd.TVD_XYZ, GAMMA,
                                               check=False)
     assert st == tvd.TVD_OK
-    # edge 32: four tiles per block count against the limit
-    b32 = tvd.Batch(tvd.TVD_F32, SCRATCH_PARTS // 4 + 1, 32, dt=1e-3, dh=1e-2, d_in_off=off,
-                    d_out_off=off)
-    st = ctx.tvd_patch_advance_stream_noalloc(b32, nbr, chains, u, v, tvd.TVD_XYZ, GAMMA,
-                                              sums=sums, check=False)
+    # edge 32: four tiles per chain count against the limit
+    n32 = SCRATCH_PARTS // 4 + 1
+    b32 = tvd.Batch(tvd.TVD_F32, n32, 32, dt=1e-3, dh=1e-2, d_in_off=off, d_out_off=off)
+    st = ctx.tvd_patch_advance_stream_noalloc(b32, nbr, many_chains(n32), u, v,
+                                              tvd.TVD_XYZ, GAMMA, sums=sums, check=False)
     assert st == tvd.TVD_ERR_STATE
     torch.cuda.synchronize()
